@@ -1,0 +1,205 @@
+// CPU oracle for the kernel-actor pipelines.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library.  It shares no code,
+// header, table or helper with the HIP implementation, and the product path
+// never calls it.
+//
+// Everything here is plain, sequential and unblocked, written to be checked by
+// eye against the paper ("OpenCL Actors -- Adding Data Parallelism to
+// Actor-based Programming with CAF", arXiv 1709.07781):
+//
+//  * WAH bitmap index, Sec. 4.1: values are tagged with their input position,
+//    sorted by value, cut into chunk ids and literals, given fills, the fills and
+//    literals are interleaved and the zero entries removed by a stream
+//    compaction ("fuseFillsLiterals"), and a lookup table maps each distinct
+//    value to its bitmap.  The six parts are separate functions below, called
+//    in that order by ora_wah_index.
+//  * Exclusive prefix sum (phase 2 of the stream compaction in Sec. 4.1) and
+//    stream compaction of zero entries (Sec. 4.1).
+//  * The affine stage x <- a*x + b (mod 2^32), the per-stage workload of the
+//    kernel-stage overhead experiments (Sec. 3.6, Sec. 5.2-5.3).
+//
+// Word conventions where the paper is silent (each is a reading of the text):
+//  * a literal has bit 31 clear; bit b (0..30) stands for row 31*g + b of its
+//    31-row group g (least significant bit first);
+//  * a fill has bit 31 set, bit 30 holds the fill bit (always 0 here), and bits
+//    29..0 count the 31-row groups it covers;
+//  * every non-empty group is one literal (the fill/literal pair structure of
+//    fuseFillsLiterals, whose only compaction predicate is "zero"), runs of
+//    empty groups before a literal become one 0-fill, counted from group 0, and
+//    a bitmap ends at its last literal (no trailing fill).
+//
+// Return codes: 0 on success, -1 on a bad argument, -2 if a fill length would
+// not fit in 30 bits (unreachable for 32-bit row ids).
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+namespace {
+
+constexpr uint32_t kGroupRows = 31;           // rows per WAH group
+constexpr uint32_t kFillFlag = 0x80000000u;   // bit 31: word is a fill
+constexpr uint32_t kMaxFillLen = 0x3FFFFFFFu; // bits 29..0
+
+}  // namespace
+
+extern "C" {
+
+// Parts 1 and 2 (Sec. 4.1): tag each value with its input position and sort by
+// value.  Ties keep input order (a stable sort), which is what keeps the rows
+// of one value ascending.  rows == nullptr means rows 0..n-1.
+int ora_sort_pairs(const uint32_t* keys, const uint32_t* rows, uint64_t n,
+                   uint32_t* skeys, uint32_t* srows) {
+  if (n && (!keys || !skeys || !srows)) return -1;
+  std::vector<uint64_t> perm(n);
+  std::iota(perm.begin(), perm.end(), uint64_t{0});
+  std::stable_sort(perm.begin(), perm.end(),
+                   [&](uint64_t a, uint64_t b) { return keys[a] < keys[b]; });
+  for (uint64_t j = 0; j < n; ++j) {
+    skeys[j] = keys[perm[j]];
+    srows[j] = rows ? rows[perm[j]] : static_cast<uint32_t>(perm[j]);
+  }
+  return 0;
+}
+
+// Part 3 (Sec. 4.1): chunk ids and literals.  In the sorted (value, row)
+// sequence a group is a maximal run with the same value and the same chunk id
+// row / 31.  Each group yields its value, its chunk id and its literal, the OR
+// of 1 << (row % 31) over its rows.  Outputs hold n entries; *k receives the
+// number of groups.
+int ora_wah_groups(const uint32_t* skeys, const uint32_t* srows, uint64_t n,
+                   uint32_t* gkey, uint32_t* gchunk, uint32_t* glit, uint64_t* k) {
+  if (!k || (n && (!skeys || !srows || !gkey || !gchunk || !glit))) return -1;
+  uint64_t g = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint32_t chunk = srows[i] / kGroupRows;
+    const uint32_t bit = 1u << (srows[i] % kGroupRows);
+    const bool same = g > 0 && gkey[g - 1] == skeys[i] && gchunk[g - 1] == chunk;
+    if (same) {
+      glit[g - 1] |= bit;
+    } else {
+      gkey[g] = skeys[i];
+      gchunk[g] = chunk;
+      glit[g] = bit;
+      ++g;
+    }
+  }
+  *k = g;
+  return 0;
+}
+
+// Part 4 (Sec. 4.1): fills.  The fill in front of group g covers the empty
+// groups between the previous group of the same value (or group -1 when g is
+// the first group of its value) and g.  A gap of zero gives the word 0, which
+// the compaction of part 5 removes.
+int ora_wah_fills(const uint32_t* gkey, const uint32_t* gchunk, uint64_t k, uint32_t* gfill) {
+  if (k && (!gkey || !gchunk || !gfill)) return -1;
+  for (uint64_t g = 0; g < k; ++g) {
+    const bool first_of_value = (g == 0) || gkey[g - 1] != gkey[g];
+    const int64_t prev = first_of_value ? -1 : static_cast<int64_t>(gchunk[g - 1]);
+    const int64_t gap = static_cast<int64_t>(gchunk[g]) - prev - 1;
+    if (gap < 0) return -1;  // groups of one value must have increasing chunk ids
+    if (gap > kMaxFillLen) return -2;
+    gfill[g] = gap > 0 ? (kFillFlag | static_cast<uint32_t>(gap)) : 0u;
+  }
+  return 0;
+}
+
+// Part 5a, "prepare_index" (Sec. 4.1): interleave fills and literals into a
+// 2k-entry index, the fill of each group in front of its literal.
+int ora_wah_interleave(const uint32_t* gfill, const uint32_t* glit, uint64_t k, uint32_t* index) {
+  if (k && (!gfill || !glit || !index)) return -1;
+  for (uint64_t g = 0; g < k; ++g) {
+    index[2 * g] = gfill[g];
+    index[2 * g + 1] = glit[g];
+  }
+  return 0;
+}
+
+// Part 5b, stream compaction (Sec. 4.1): keep the non-zero entries in order.
+int ora_compact_nonzero(const uint32_t* in, uint64_t m, uint32_t* out, uint64_t* kept) {
+  if (!kept || (m && (!in || !out))) return -1;
+  uint64_t w = 0;
+  for (uint64_t i = 0; i < m; ++i)
+    if (in[i] != 0) out[w++] = in[i];
+  *kept = w;
+  return 0;
+}
+
+// Part 6 (Sec. 4.1): lookup table.  keys[d] is the d-th distinct value in
+// ascending order and offsets[d] the position of its first word among the
+// compacted words; offsets[D] = W.  The position of group g's first word is the
+// number of non-zero index entries in front of index[2g].
+int ora_wah_table(const uint32_t* gkey, const uint32_t* index, uint64_t k,
+                  uint32_t* keys, uint32_t* offsets, uint64_t* D) {
+  if (!D || !offsets || (k && (!gkey || !index || !keys))) return -1;
+  uint64_t d = 0, kept = 0;
+  for (uint64_t g = 0; g < k; ++g) {
+    if (g == 0 || gkey[g - 1] != gkey[g]) {
+      keys[d] = gkey[g];
+      offsets[d] = static_cast<uint32_t>(kept);
+      ++d;
+    }
+    kept += (index[2 * g] != 0) + (index[2 * g + 1] != 0);
+  }
+  offsets[d] = static_cast<uint32_t>(kept);
+  *D = d;
+  return 0;
+}
+
+// The whole index build: parts 1..6 in the paper's order.
+// keys needs n entries, offsets n + 1, words 2n.
+int ora_wah_index(const uint32_t* values, uint64_t n, uint32_t* keys, uint32_t* offsets,
+                  uint32_t* words, uint64_t* D, uint64_t* W) {
+  if (!D || !W || !offsets || (n && (!values || !keys || !words))) return -1;
+  std::vector<uint32_t> skeys(n), srows(n), gkey(n), gchunk(n), glit(n), gfill(n), index(2 * n);
+  uint64_t k = 0;
+  int rc = ora_sort_pairs(values, nullptr, n, skeys.data(), srows.data());
+  if (!rc) rc = ora_wah_groups(skeys.data(), srows.data(), n, gkey.data(), gchunk.data(), glit.data(), &k);
+  if (!rc) rc = ora_wah_fills(gkey.data(), gchunk.data(), k, gfill.data());
+  if (!rc) rc = ora_wah_interleave(gfill.data(), glit.data(), k, index.data());
+  if (!rc) rc = ora_compact_nonzero(index.data(), 2 * k, words, W);
+  if (!rc) rc = ora_wah_table(gkey.data(), index.data(), k, keys, offsets, D);
+  return rc;
+}
+
+// Parts 3..6 from an already sorted (value, row) sequence.
+int ora_wah_encode_sorted(const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
+                          uint32_t* offsets, uint32_t* words, uint64_t* D, uint64_t* W) {
+  if (!D || !W || !offsets || (n && (!skeys || !srows || !keys || !words))) return -1;
+  std::vector<uint32_t> gkey(n), gchunk(n), glit(n), gfill(n), index(2 * n);
+  uint64_t k = 0;
+  int rc = ora_wah_groups(skeys, srows, n, gkey.data(), gchunk.data(), glit.data(), &k);
+  if (!rc) rc = ora_wah_fills(gkey.data(), gchunk.data(), k, gfill.data());
+  if (!rc) rc = ora_wah_interleave(gfill.data(), glit.data(), k, index.data());
+  if (!rc) rc = ora_compact_nonzero(index.data(), 2 * k, words, W);
+  if (!rc) rc = ora_wah_table(gkey.data(), index.data(), k, keys, offsets, D);
+  return rc;
+}
+
+// Exclusive prefix sum in uint32 arithmetic (wraps mod 2^32): out[0] = 0,
+// out[i] = in[0] + ... + in[i-1].
+int ora_exclusive_scan(const uint32_t* in, uint64_t m, uint32_t* out) {
+  if (m && (!in || !out)) return -1;
+  uint32_t acc = 0;
+  for (uint64_t i = 0; i < m; ++i) {
+    const uint32_t v = in[i];
+    out[i] = acc;
+    acc += v;
+  }
+  return 0;
+}
+
+// The affine chain: stage s maps x to a[s] * x + b[s] in uint32 arithmetic.
+int ora_affine_chain(uint32_t* x, uint64_t m, const uint32_t* a, const uint32_t* b, uint32_t stages) {
+  if ((m && !x) || (stages && (!a || !b))) return -1;
+  for (uint32_t s = 0; s < stages; ++s)
+    for (uint64_t i = 0; i < m; ++i) x[i] = a[s] * x[i] + b[s];
+  return 0;
+}
+
+}  // extern "C"
