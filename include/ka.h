@@ -1,0 +1,295 @@
+/*
+ * ka.h -- kernel actors on MI355X (gfx950): the C ABI.
+ *
+ * A kernel actor wraps one data-parallel kernel behind a message interface:
+ * a message is matched against the kernel's signature, the kernel is launched
+ * over an ND-range, and the outputs are answered either as host values or as
+ * references to device memory that the next actor consumes in place
+ * (arXiv 1709.07781, Sec. 3.2 "core approach", Sec. 3.4 "programming
+ * interface", Sec. 3.5 "OpenCL actors as kernel stages").  Actors compose
+ * (C = B (.) A, Sec. 3.5) into pipelines whose intermediate data never leave
+ * the device; the WAH bitmap index of Sec. 4 is the composed workload.
+ *
+ * Conventions for every call:
+ *  - Every function returns int: KA_OK (0) or a negative KA_E_* code.  On
+ *    failure out-parameters are left untouched and ka_last_error() gives a
+ *    message for the calling thread.  No C++ exception crosses this ABI.
+ *  - Objects are reference counted.  Every create / spawn / compose / send and
+ *    every returned ka_ref gives the caller one reference, released with the
+ *    matching *_release / *_destroy.  Composed actors keep their stages alive;
+ *    commands in flight keep the refs they use alive until the device is done
+ *    with them.
+ *  - Pointers named host point to host memory, pointers named dptr to device
+ *    memory of the system's device.  Sizes are element counts unless the name
+ *    says bytes.
+ *  - Only uint32 data (KA_U32) is accepted by the built-in kernels.  Signature
+ *    checking is by dtype, direction and mode, as in Sec. 3.4.
+ */
+#ifndef KA_H_
+#define KA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KA_API __attribute__((visibility("default")))
+
+/* ---- status codes ---------------------------------------------------------------- */
+enum {
+  KA_OK = 0,
+  KA_E_ARG = -1,              /* invalid argument or null pointer */
+  KA_E_TYPE = -2,             /* dtype / direction / mode does not match the signature */
+  KA_E_ARITY = -3,            /* wrong number of message elements */
+  KA_E_NOKERNEL = -4,         /* no kernel of that name in the program */
+  KA_E_DEVICE = -5,           /* no usable gfx950 device, or a HIP runtime failure */
+  KA_E_OOM = -6,              /* device allocation failed */
+  KA_E_BUDGET = -7,           /* the system's HBM budget would be exceeded */
+  KA_E_TIMEOUT = -8,          /* ka_receive timed out; the ticket stays valid */
+  KA_E_NOT_SERIALIZABLE = -9, /* device references never leave the process (Sec. 3.5, option a) */
+  KA_E_LAUNCH = -10,          /* kernel launch failed (the ticket carries the error) */
+  KA_E_CANCELLED = -11,       /* work was cancelled (system destroyed, server stopped) */
+  KA_E_STATE = -12            /* object used in a state that does not allow the call */
+};
+
+/* ---- types ----------------------------------------------------------------------- */
+typedef enum ka_dtype { KA_U32 = 1, KA_I32 = 2, KA_U64 = 3, KA_F32 = 4, KA_U8 = 5 } ka_dtype;
+
+/* Argument directions of a kernel signature (Sec. 3.4): in, out, in_out,
+ * local (work-group memory, neither initialised nor read by the host, not
+ * persistent) and priv (private values fixed at spawn, passed by value). */
+typedef enum ka_dir { KA_IN = 1, KA_OUT = 2, KA_IN_OUT = 3, KA_LOCAL = 4, KA_PRIV = 5 } ka_dir;
+
+/* How an argument is accepted from / handed on to messages (Sec. 3.4):
+ * a host value, or a reference to device memory (mem_ref). */
+typedef enum ka_mode { KA_VAL = 0, KA_REF = 1 } ka_mode;
+
+enum { KA_ACCESS_READ = 1u, KA_ACCESS_WRITE = 2u, KA_ACCESS_RW = 3u };
+
+typedef struct ka_system ka_system;
+typedef struct ka_program ka_program;
+typedef struct ka_actor ka_actor;
+typedef struct ka_ref ka_ref;
+typedef struct ka_ticket ka_ticket;
+
+/* System configuration (the actor_system_config that loads the device module,
+ * Sec. 3.4).  HIP is initialised lazily on the first call that needs the
+ * device (Sec. 3.2: discovery on first access). */
+typedef struct ka_system_config {
+  int32_t device;            /* HIP device ordinal; the first device by default (Sec. 3.6) */
+  uint32_t n_streams;        /* command queues (HIP streams) in the system; 0 means 1 */
+  uint64_t hbm_budget_bytes; /* device memory the system may hold at once; 0 = unlimited */
+  void* stream;              /* optional borrowed hipStream_t used as stream 0 (e.g. torch's) */
+  uint32_t flags;            /* KA_SYS_* */
+} ka_system_config;
+
+#define KA_SYS_PROFILE 1u /* time every kernel launch with device events (ka_profile_get) */
+
+/* ND-range (Sec. 3.4): global dimensions, optional offsets of the global ids,
+ * optional work-group dimensions.  For the built-in kernels global[0] is the
+ * number of elements processed (one logical work-item per element); 0 means
+ * "the length of the first input".  local[0] = 0 picks the kernel's own
+ * work-group size; a non-zero value must be one the kernel supports. */
+typedef struct ka_nd_range {
+  uint32_t dims;      /* 1..3 */
+  uint64_t global[3];
+  uint64_t offset[3];
+  uint32_t local[3];
+} ka_nd_range;
+
+/* One element of a message or of a response. */
+typedef struct ka_value {
+  uint32_t mode;  /* KA_VAL or KA_REF */
+  uint32_t dtype; /* ka_dtype of a VAL (ignored for REF: the ref knows its type) */
+  void* ptr;      /* VAL: host pointer (input: read before ka_send returns;
+                     output: caller buffer of `count` elements, or NULL to query) */
+  uint64_t count; /* VAL: element count (output: set to the produced count) */
+  ka_ref* ref;    /* REF: a device reference (input: borrowed; output: +1 reference) */
+} ka_value;
+
+/* Output size from the inputs of the message (Sec. 3.4: a user function
+ * overriding the default size). */
+typedef uint64_t (*ka_size_fn)(const ka_value* inputs, uint32_t n_inputs, void* ud);
+
+/* One argument of a kernel signature. */
+typedef struct ka_arg {
+  uint32_t dir;       /* ka_dir */
+  uint32_t dtype;     /* ka_dtype */
+  uint32_t in_mode;   /* IN / IN_OUT: accepted mode (KA_VAL or KA_REF) */
+  uint32_t out_mode;  /* OUT / IN_OUT: produced mode (KA_VAL or KA_REF) */
+  uint64_t count;     /* OUT: capacity in elements (0 = default: the number of work-items,
+                         or the kernel's own bound); LOCAL: elements per work-group;
+                         PRIV: number of elements at `init` (1 for a scalar) */
+  ka_size_fn size_fn; /* OUT: optional capacity function, takes precedence over count */
+  void* size_ud;
+  const void* init;   /* PRIV: the value(s), copied at spawn */
+} ka_arg;
+
+/* Pre- and post-processing (Sec. 3.4, Listing 3 and Sec. 3.5): map an incoming
+ * message to the kernel's in / in_out arguments, and the kernel's in_out / out
+ * results to the response.  Both run on the thread that runs the actor.
+ * Inputs are borrowed for the duration of the call; the function writes at
+ * most `cap` values to `out` and their number to `*n_out`.  REF values it
+ * returns are borrowed from its inputs (the runtime takes its own reference);
+ * a REF it drops is released, which frees the device memory once unused
+ * (Sec. 3.5).  VAL host data it returns must stay valid until it returns.
+ * A non-zero return fails the request with that code. */
+typedef int (*ka_map_fn)(const ka_value* in, uint32_t n_in, ka_value* out, uint32_t* n_out, uint32_t cap,
+                         void* ud);
+
+/* ---- errors ---------------------------------------------------------------------- */
+KA_API const char* ka_error_string(int code);
+KA_API const char* ka_last_error(void); /* thread-local message of the last failure */
+
+/* ---- system ---------------------------------------------------------------------- */
+/* Creates a system.  cfg may be NULL (defaults).  Touches no device until
+ * needed; a later call fails with KA_E_DEVICE if the device is not gfx950. */
+KA_API int ka_system_create(const ka_system_config* cfg, ka_system** out);
+/* Waits for all work in flight, then frees every resource the system holds.
+ * Objects still referenced by the caller become unusable (KA_E_STATE). */
+KA_API int ka_system_destroy(ka_system* sys);
+/* Blocks until every stream of the system is idle. */
+KA_API int ka_system_synchronize(ka_system* sys);
+/* The hipStream_t of stream i (initialises the device). */
+KA_API int ka_system_stream(ka_system* sys, uint32_t i, void** stream);
+/* Device memory currently held by the system, in bytes (in use and cached). */
+KA_API int ka_system_memory(ka_system* sys, uint64_t* in_use, uint64_t* reserved);
+
+/* ---- programs (Sec. 3.2: kernels looked up by name) ------------------------------ */
+/* The built-in kernels, compiled ahead of time for gfx950:
+ *   affine_u32            (in_out x; priv a; priv b)             x <- a*x + b mod 2^32
+ *   exclusive_scan_u32    (in x; out y)                           y[i] = x[0] + .. + x[i-1] mod 2^32
+ *   compact_nonzero_u32   (in x; out y)                           y = x without zeros, in order;
+ *                                                                 the produced count is device-resident
+ *   radix_sort_pairs_u32  (in keys; in rows; out skeys; out srows) stable sort of (key, row) by key
+ *   radix_sort_rows_u32   (in keys; out skeys; out srows)         same with rows 0..n-1 (Sec. 4.1 part 1-2)
+ *   wah_encode_sorted     (in skeys; in srows; out keys; out offsets; out words)
+ *                                                                 Sec. 4.1 parts 3-6 on sorted pairs
+ * The names, their signatures and the data each one reads and writes are
+ * documented at ka_spawn. */
+KA_API int ka_program_builtin(ka_system* sys, ka_program** out);
+/* Loads a gfx950 code object (.hsaco).  Its kernels are launched with one
+ * parameter per signature argument, in order: a device pointer for
+ * in / out / in_out, a uint32 byte offset into the dynamic LDS for local, the
+ * value(s) of priv; then a ka_nd_range_dev holding the global sizes and offsets.
+ * Grid = ceil(global / local) work-groups of `local` work-items. */
+KA_API int ka_program_load(ka_system* sys, const char* hsaco_path, ka_program** out);
+KA_API int ka_program_release(ka_program* prog);
+
+/* Trailing parameter of kernels from ka_program_load. */
+typedef struct ka_nd_range_dev {
+  uint64_t global[3];
+  uint64_t offset[3];
+} ka_nd_range_dev;
+
+/* ---- actors ---------------------------------------------------------------------- */
+/* Spawns a kernel actor (Sec. 3.4, Listing 2): `kernel` from `prog`, launched
+ * over `range`, with the signature sig[0..nargs).  The signature is checked
+ * against the kernel's own (KA_E_TYPE / KA_E_ARITY); out arguments are
+ * allocated by the runtime with their default or given capacity.  A message
+ * is matched against the in and in_out arguments in order; the response
+ * consists of the in_out and out arguments in order (Sec. 3.4).
+ * Outputs whose length depends on the data (compact_nonzero_u32,
+ * wah_encode_sorted) keep their true length on the device; consumers read it
+ * there, so no host round-trip is needed between stages (Sec. 4.1, the
+ * "config" array). */
+KA_API int ka_spawn(ka_system* sys, ka_program* prog, const char* kernel, const ka_nd_range* range,
+                    const ka_arg* sig, uint32_t nargs, ka_actor** out);
+/* Installs pre/post-processing functions (either may be NULL = identity). */
+KA_API int ka_actor_set_mapping(ka_actor* actor, ka_map_fn pre, ka_map_fn post, void* ud);
+/* out = outer (.) inner (Sec. 3.5): a message to `out` goes to `inner`, whose
+ * response becomes the message to `outer`, whose response answers the
+ * original request.  Without mapping functions the response of `inner` must
+ * match the message of `outer` in arity, dtype and mode (else KA_E_TYPE). */
+KA_API int ka_compose(ka_actor* outer, ka_actor* inner, ka_actor** out);
+/* Selects the stream (command queue) the actor's work is queued on; a
+ * composed actor queues all its stages on its own stream. */
+KA_API int ka_actor_set_stream(ka_actor* actor, uint32_t stream);
+KA_API int ka_actor_retain(ka_actor* actor);
+KA_API int ka_actor_release(ka_actor* actor);
+
+/* ---- messaging (Sec. 3.4: request / receive) ------------------------------------- */
+/* Asynchronous request.  VAL host inputs are copied before the call returns;
+ * REF inputs are borrowed (each command keeps its own reference until the
+ * device is done).  Device work of a chain is enqueued before the call
+ * returns; stages hand references on before the device finishes (Sec. 3.5). */
+KA_API int ka_send(ka_actor* actor, const ka_value* args, uint32_t nargs, ka_ticket** out);
+/* Waits for the response (timeout_us < 0: forever; 0: poll).  For each VAL
+ * output, outs[i].count is set to the produced count and, if outs[i].ptr is
+ * non-NULL, that many elements are copied there (KA_E_ARG, with count set, if
+ * the caller's count is smaller).  For each REF output, outs[i].ref receives a
+ * new reference and outs[i].count its length if known on the host, else its
+ * capacity (ka_ref_info gives the true length).  A failed request returns its
+ * error code.  The ticket stays valid until ka_ticket_release, so receive may
+ * be called again. */
+KA_API int ka_receive(ka_ticket* ticket, ka_value* outs, uint32_t nouts, int64_t timeout_us);
+/* Number of response elements (available before completion). */
+KA_API int ka_ticket_arity(ka_ticket* ticket, uint32_t* n);
+KA_API int ka_ticket_release(ka_ticket* ticket);
+
+/* ---- device references (mem_ref, Sec. 3.5) --------------------------------------- */
+/* Type, element count and access rights.  count is the true length; for a
+ * data-dependent output this waits for the producing kernel. */
+KA_API int ka_ref_info(ka_ref* ref, uint32_t* dtype, uint64_t* count, uint32_t* access);
+/* Capacity in elements (never waits). */
+KA_API int ka_ref_capacity(ka_ref* ref, uint64_t* capacity);
+/* Copies min(bytes, length) to host memory after the producer finished. */
+KA_API int ka_ref_read(ka_ref* ref, void* host, uint64_t bytes);
+/* Device address of the referenced buffer (valid while the ref is held). */
+KA_API int ka_ref_device_ptr(ka_ref* ref, void** dptr);
+/* Wraps caller-owned device memory (e.g. a torch tensor) without copying.
+ * The caller keeps it alive and unmodified while any command uses it;
+ * releasing the last reference does not free it. */
+KA_API int ka_ref_wrap(ka_system* sys, void* dptr, uint32_t dtype, uint64_t count, uint32_t access,
+                       ka_ref** out);
+/* Allocates an uninitialised device buffer from the system's pool. */
+KA_API int ka_ref_alloc(ka_system* sys, uint32_t dtype, uint64_t count, ka_ref** out);
+KA_API int ka_ref_retain(ka_ref* ref);
+/* Drops a reference; the last one returns the memory to the system's pool,
+ * ordered after every command that used it (Sec. 3.5: dropping a ref
+ * releases its device memory). */
+KA_API int ka_ref_release(ka_ref* ref);
+/* Device references are process-local: always KA_E_NOT_SERIALIZABLE
+ * (Sec. 3.5, option (a)). */
+KA_API int ka_ref_serialize(const ka_ref* ref, void* buf, uint64_t cap, uint64_t* len);
+
+/* ---- the composed WAH index (Sec. 4) --------------------------------------------- */
+#define KA_WAH_INPUT_DEVICE 1u /* `values` is a device pointer (else host memory) */
+#define KA_WAH_OUTPUT_REFS 2u  /* return device refs (else host arrays from malloc) */
+
+typedef struct ka_wah_result {
+  uint64_t n;        /* input elements */
+  uint64_t D;        /* distinct values = bitmaps */
+  uint64_t W;        /* WAH words over all bitmaps */
+  uint32_t* keys;    /* host: keys[D] ascending (NULL with KA_WAH_OUTPUT_REFS) */
+  uint32_t* offsets; /* host: offsets[D+1], bitmap d is words[offsets[d] .. offsets[d+1]) */
+  uint32_t* words;   /* host: words[W] */
+  ka_ref* keys_ref;  /* device refs (KA_WAH_OUTPUT_REFS only) */
+  ka_ref* offsets_ref;
+  ka_ref* words_ref;
+} ka_wah_result;
+
+/* Builds the WAH bitmap index of values[0..n) (rows 0..n-1) with the composed
+ * actor wah_encode_sorted (.) radix_sort_rows_u32 and waits for it.  Word
+ * format: a literal has bit 31 clear and bit b standing for row 31*g + b of
+ * its 31-row group g; a fill has bit 31 set, bit 30 clear and the number of
+ * empty groups it covers in bits 29..0.  Each non-empty group of a value is
+ * one literal, each run of empty groups before a literal one fill, counted
+ * from group 0; a bitmap ends at its last literal.  n < 2^30. */
+KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint32_t flags,
+                        ka_wah_result* out);
+/* Frees the host arrays and releases the refs of a result. */
+KA_API int ka_wah_result_free(ka_wah_result* res);
+
+/* ---- profiling (KA_SYS_PROFILE) -------------------------------------------------- */
+/* Launch count and summed device time of every kernel named `kernel` since
+ * the last reset (waits for the device). */
+KA_API int ka_profile_get(ka_system* sys, const char* kernel, uint64_t* launches, double* total_ms);
+KA_API int ka_profile_reset(ka_system* sys);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KA_H_ */

@@ -1,0 +1,121 @@
+// The built-in program: kernel names, their signatures and the adapters that
+// turn bound arguments into launches (Sec. 3.2: a program maps kernel names
+// to kernels).
+#include "runtime_internal.hpp"
+
+namespace ka {
+namespace {
+
+uint64_t cap_same(uint32_t, uint64_t n) { return n; }
+uint64_t cap_wah(uint32_t i, uint64_t n) {
+  // (in skeys, in srows, out keys[D <= n], out offsets[D+1], out words[W <= 2n])
+  if (i == 2) return n ? n : 1;
+  if (i == 3) return n + 1;
+  return n ? 2 * n : 1;
+}
+bool len_host(uint32_t) { return false; }
+bool len_compact(uint32_t i) { return i == 1; }
+bool len_wah(uint32_t i) { return i >= 2; }
+
+// affine_u32: (in_out x; priv a; priv b)
+int run_affine(LaunchCtx& c) {
+  Bound& x = (*c.args)[0];
+  const uint64_t off = c.range ? c.range->offset[0] : 0;
+  if (off > x.cap || c.n > x.cap - off) return c.env->fail(KA_E_ARG, "affine_u32: range exceeds the buffer");
+  return launch_affine(*c.env, static_cast<uint32_t*>(x.ptr), c.n, c.d_n, off, (uint32_t)(*c.args)[1].priv[0],
+                       (uint32_t)(*c.args)[2].priv[0]);
+}
+
+// exclusive_scan_u32: (in x; out y)
+int run_scan(LaunchCtx& c) {
+  Bound& in = (*c.args)[0];
+  Bound& out = (*c.args)[1];
+  if (c.n > in.cap || c.n > out.cap) return c.env->fail(KA_E_ARG, "exclusive_scan_u32: range exceeds a buffer");
+  int rc = launch_exclusive_scan(*c.env, static_cast<const uint32_t*>(in.ptr), static_cast<uint32_t*>(out.ptr), c.n,
+                                 c.d_n);
+  return rc;
+}
+
+// compact_nonzero_u32: (in x; out y) -- y's length is written on the device
+int run_compact(LaunchCtx& c) {
+  Bound& in = (*c.args)[0];
+  Bound& out = (*c.args)[1];
+  if (c.n > in.cap || c.n > out.cap) return c.env->fail(KA_E_ARG, "compact_nonzero_u32: range exceeds a buffer");
+  return launch_compact_nonzero(*c.env, static_cast<const uint32_t*>(in.ptr), static_cast<uint32_t*>(out.ptr), c.n,
+                                c.d_n, const_cast<uint64_t*>(out.d_len));
+}
+
+// radix_sort_rows_u32: (in keys; out skeys; out srows)
+int run_sort_rows(LaunchCtx& c) {
+  Bound& k = (*c.args)[0];
+  Bound& sk = (*c.args)[1];
+  Bound& sr = (*c.args)[2];
+  if (c.n > k.cap || c.n > sk.cap || c.n > sr.cap)
+    return c.env->fail(KA_E_ARG, "radix_sort_rows_u32: range exceeds a buffer");
+  return launch_radix_sort_pairs(*c.env, static_cast<const uint32_t*>(k.ptr), nullptr, static_cast<uint32_t*>(sk.ptr),
+                                 static_cast<uint32_t*>(sr.ptr), c.n);
+}
+
+// radix_sort_pairs_u32: (in keys; in rows; out skeys; out srows)
+int run_sort_pairs(LaunchCtx& c) {
+  Bound& k = (*c.args)[0];
+  Bound& r = (*c.args)[1];
+  Bound& sk = (*c.args)[2];
+  Bound& sr = (*c.args)[3];
+  if (c.n > k.cap || c.n > r.cap || c.n > sk.cap || c.n > sr.cap)
+    return c.env->fail(KA_E_ARG, "radix_sort_pairs_u32: range exceeds a buffer");
+  return launch_radix_sort_pairs(*c.env, static_cast<const uint32_t*>(k.ptr), static_cast<const uint32_t*>(r.ptr),
+                                 static_cast<uint32_t*>(sk.ptr), static_cast<uint32_t*>(sr.ptr), c.n);
+}
+
+// wah_encode_sorted: (in skeys; in srows; out keys; out offsets; out words)
+int run_wah(LaunchCtx& c) {
+  auto& a = *c.args;
+  if (c.n > a[0].cap || c.n > a[1].cap) return c.env->fail(KA_E_ARG, "wah_encode_sorted: range exceeds an input");
+  if (a[2].cap < c.n || a[3].cap < c.n + 1 || a[4].cap < 2 * c.n)
+    return c.env->fail(KA_E_ARG, "wah_encode_sorted: outputs need capacities n, n+1 and 2n");
+  return launch_wah_encode(*c.env, static_cast<const uint32_t*>(a[0].ptr), static_cast<const uint32_t*>(a[1].ptr), c.n,
+                           static_cast<uint32_t*>(a[2].ptr), static_cast<uint32_t*>(a[3].ptr),
+                           static_cast<uint32_t*>(a[4].ptr), const_cast<uint64_t*>(a[2].d_len),
+                           const_cast<uint64_t*>(a[3].d_len), const_cast<uint64_t*>(a[4].d_len));
+}
+
+std::vector<BuiltinKernel> make_registry() {
+  std::vector<BuiltinKernel> r;
+  r.push_back({"affine_u32", {{KA_IN_OUT, KA_U32}, {KA_PRIV, KA_U32}, {KA_PRIV, KA_U32}}, cap_same, len_host, false,
+               run_affine});
+  r.push_back({"exclusive_scan_u32", {{KA_IN, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_host, false, run_scan});
+  r.push_back({"compact_nonzero_u32", {{KA_IN, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_compact, false,
+               run_compact});
+  r.push_back({"radix_sort_rows_u32", {{KA_IN, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_host, true,
+               run_sort_rows});
+  r.push_back({"radix_sort_pairs_u32",
+               {{KA_IN, KA_U32}, {KA_IN, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}},
+               cap_same,
+               len_host,
+               true,
+               run_sort_pairs});
+  r.push_back({"wah_encode_sorted",
+               {{KA_IN, KA_U32}, {KA_IN, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}},
+               cap_wah,
+               len_wah,
+               true,
+               run_wah});
+  return r;
+}
+
+}  // namespace
+
+const std::vector<BuiltinKernel>& builtin_kernels() {
+  static const std::vector<BuiltinKernel> reg = make_registry();
+  return reg;
+}
+
+const BuiltinKernel* find_builtin(const char* name) {
+  if (!name) return nullptr;
+  for (const auto& k : builtin_kernels())
+    if (std::string(k.name) == name) return &k;
+  return nullptr;
+}
+
+}  // namespace ka

@@ -1,0 +1,213 @@
+// Exclusive prefix sum and stream compaction of uint32 arrays.
+//
+// Both are single-pass: every work-group takes a tile ticket, reduces its
+// tile, publishes the tile total, finds its exclusive prefix by decoupled
+// look-back over its predecessors and writes its results -- 8 bytes of HBM
+// traffic per element for the scan, 4 + 4*kept for the compaction.  The
+// compaction is the primitive of the fuseFillsLiterals step (Sec. 4.1): it
+// removes the zero entries and keeps the order; its phases "count per group",
+// "scan of the group counts" and "move the valid elements" run in one kernel.
+//
+// Tile layout: round r of thread t holds the 4 consecutive elements starting at
+// tile_base + 4 (r * BLOCK + t), so every global access is a coalesced
+// 16-byte load or store; element order inside the tile is (round, thread, lane
+// of the vector).
+#include "common.hpp"
+
+namespace ka {
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanRounds = 4;
+constexpr int kScanTile = kScanBlock * kScanRounds * 4;  // 4096 elements
+constexpr int kWaves = kScanBlock / 64;
+
+template <bool kVec>
+__device__ __forceinline__ void load4(const uint32_t* __restrict__ p, uint64_t e, uint64_t n, uint32_t v[4]) {
+  if (kVec && e + 4 <= n) {
+    const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p + e));
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = (e + j < n) ? p[e + j] : 0u;
+  }
+}
+
+template <bool kVec>
+__device__ __forceinline__ void store4(uint32_t* __restrict__ p, uint64_t e, uint64_t n, const uint32_t v[4]) {
+  if (kVec && e + 4 <= n) {
+    u32x4 q;
+    q.x = v[0];
+    q.y = v[1];
+    q.z = v[2];
+    q.w = v[3];
+    __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(p + e));
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (e + j < n) p[e + j] = v[j];
+  }
+}
+
+// Exclusive prefix of each thread's round sums over (round, thread) order,
+// plus the tile total.  One barrier.
+__device__ __forceinline__ void tile_scan(const uint32_t s[kScanRounds], uint32_t pre[kScanRounds],
+                                          uint32_t* tile_total, uint32_t (*s_wave)[kWaves]) {
+  const uint32_t w = threadIdx.x / 64;
+  uint32_t inc[kScanRounds];
+#pragma unroll
+  for (int r = 0; r < kScanRounds; ++r) {
+    inc[r] = wave_incl_scan(s[r]);
+    if (lane_id() == 63) s_wave[r][w] = inc[r];
+  }
+  __syncthreads();
+  uint32_t round_base = 0;
+#pragma unroll
+  for (int r = 0; r < kScanRounds; ++r) {
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+      const uint32_t t = s_wave[r][i];
+      before += (i < (int)w) ? t : 0u;
+      tot += t;
+    }
+    pre[r] = round_base + before + inc[r] - s[r];
+    round_base += tot;
+  }
+  *tile_total = round_base;
+}
+
+// Wave 0 publishes the tile total, looks back, publishes the inclusive prefix
+// and leaves the tile's exclusive prefix in *s_prefix.
+__device__ __forceinline__ void tile_lookback(const LbArgs& lb, uint32_t tile, uint32_t tile_total,
+                                              uint32_t* s_prefix) {
+  if (threadIdx.x < 64) {
+    uint32_t prefix = 0;
+    if (tile == 0) {
+      if (threadIdx.x == 0) lb_publish(lb.status, tile_total, lb.epoch, kLbInclusive);
+    } else {
+      if (threadIdx.x == 0) lb_publish(lb.status + tile, tile_total, lb.epoch, kLbAggregate);
+      prefix = lb_lookback_wave(lb.status, 1, tile, lb.epoch);
+      if (threadIdx.x == 0) lb_publish(lb.status + tile, prefix + tile_total, lb.epoch, kLbInclusive);
+    }
+    if (threadIdx.x == 0) *s_prefix = prefix;
+  }
+  __syncthreads();
+}
+
+template <bool kVec>
+__global__ __launch_bounds__(kScanBlock) void k_exclusive_scan_u32(const uint32_t* __restrict__ in,
+                                                                   uint32_t* __restrict__ out, uint64_t n_cap,
+                                                                   const uint64_t* __restrict__ d_n, LbArgs lb) {
+  __shared__ uint32_t s_tile, s_prefix;
+  __shared__ uint32_t s_wave[kScanRounds][kWaves];
+  const uint32_t tile = lb_take_tile(lb, &s_tile);
+  const uint64_t n = device_count(n_cap, d_n);
+  const uint64_t base = (uint64_t)tile * kScanTile;
+  if (base >= n) return;
+
+  uint32_t v[kScanRounds][4], s[kScanRounds], pre[kScanRounds];
+#pragma unroll
+  for (int r = 0; r < kScanRounds; ++r) {
+    load4<kVec>(in, base + ((uint64_t)r * kScanBlock + threadIdx.x) * 4, n, v[r]);
+    s[r] = v[r][0] + v[r][1] + v[r][2] + v[r][3];
+  }
+  uint32_t total;
+  tile_scan(s, pre, &total, s_wave);
+  tile_lookback(lb, tile, total, &s_prefix);
+  const uint32_t tp = s_prefix;
+#pragma unroll
+  for (int r = 0; r < kScanRounds; ++r) {
+    uint32_t acc = tp + pre[r], o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      o[j] = acc;
+      acc += v[r][j];
+    }
+    store4<kVec>(out, base + ((uint64_t)r * kScanBlock + threadIdx.x) * 4, n, o);
+  }
+}
+
+// Kept elements are staged in LDS at their tile-local positions, then copied
+// to out[prefix ...] with consecutive work-items writing consecutive words.
+template <bool kVec>
+__global__ __launch_bounds__(kScanBlock) void k_compact_nonzero_u32(const uint32_t* __restrict__ in,
+                                                                    uint32_t* __restrict__ out, uint64_t n_cap,
+                                                                    const uint64_t* __restrict__ d_n,
+                                                                    uint64_t* __restrict__ d_out_len, LbArgs lb) {
+  __shared__ uint32_t s_tile, s_prefix;
+  __shared__ uint32_t s_wave[kScanRounds][kWaves];
+  __shared__ uint32_t s_out[kScanTile];
+  const uint32_t tile = lb_take_tile(lb, &s_tile);
+  const uint64_t n = device_count(n_cap, d_n);
+  const uint64_t base = (uint64_t)tile * kScanTile;
+  if (base >= n) {
+    if (tile == 0 && threadIdx.x == 0) *d_out_len = 0;  // empty input
+    return;
+  }
+  uint32_t v[kScanRounds][4], s[kScanRounds], pre[kScanRounds];
+#pragma unroll
+  for (int r = 0; r < kScanRounds; ++r) {
+    load4<kVec>(in, base + ((uint64_t)r * kScanBlock + threadIdx.x) * 4, n, v[r]);
+    s[r] = (v[r][0] != 0) + (v[r][1] != 0) + (v[r][2] != 0) + (v[r][3] != 0);
+  }
+  uint32_t total;
+  tile_scan(s, pre, &total, s_wave);
+#pragma unroll
+  for (int r = 0; r < kScanRounds; ++r) {
+    uint32_t pos = pre[r];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (v[r][j] != 0) s_out[pos++] = v[r][j];
+  }
+  tile_lookback(lb, tile, total, &s_prefix);  // ends with a barrier
+  const uint64_t dst = s_prefix;
+  for (uint32_t i = threadIdx.x; i < total; i += kScanBlock) out[dst + i] = s_out[i];
+  const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  if (tile == ntiles - 1 && threadIdx.x == 0) *d_out_len = dst + total;
+}
+
+}  // namespace
+
+int launch_exclusive_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t n_cap, const uint64_t* d_n) {
+  if (n_cap == 0) return kOk;
+  if (!in || !out) return env.fail(kErrArg, "exclusive_scan_u32: null buffer");
+  if (n_cap > 0xFFFFFFFFull) return env.fail(kErrArg, "exclusive_scan_u32: more than 2^32-1 elements");
+  const uint32_t grid = (uint32_t)((n_cap + kScanTile - 1) / kScanTile);
+  LbArgs lb;
+  if (!env.lookback(grid, grid, &lb)) return env.fail(kErrOom, "exclusive_scan_u32: look-back state");
+  const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
+  env.prof_begin("exclusive_scan_u32");
+  if (vec)
+    k_exclusive_scan_u32<true><<<dim3(grid), dim3(kScanBlock), 0, env.stream()>>>(in, out, n_cap, d_n, lb);
+  else
+    k_exclusive_scan_u32<false><<<dim3(grid), dim3(kScanBlock), 0, env.stream()>>>(in, out, n_cap, d_n, lb);
+  env.prof_end("exclusive_scan_u32");
+  return check_launch(env, "exclusive_scan_u32 launch");
+}
+
+int launch_compact_nonzero(Env& env, const uint32_t* in, uint32_t* out, uint64_t n_cap, const uint64_t* d_n,
+                           uint64_t* d_out_len) {
+  if (!d_out_len) return env.fail(kErrArg, "compact_nonzero_u32: no length slot");
+  if (n_cap == 0) return launch_set_len(env, d_out_len, 0);
+  if (!in || !out) return env.fail(kErrArg, "compact_nonzero_u32: null buffer");
+  if (n_cap > 0xFFFFFFFFull) return env.fail(kErrArg, "compact_nonzero_u32: more than 2^32-1 elements");
+  const uint32_t grid = (uint32_t)((n_cap + kScanTile - 1) / kScanTile);
+  LbArgs lb;
+  if (!env.lookback(grid, grid, &lb)) return env.fail(kErrOom, "compact_nonzero_u32: look-back state");
+  const bool vec = (reinterpret_cast<uintptr_t>(in) & 15u) == 0;
+  env.prof_begin("compact_nonzero_u32");
+  if (vec)
+    k_compact_nonzero_u32<true><<<dim3(grid), dim3(kScanBlock), 0, env.stream()>>>(in, out, n_cap, d_n,
+                                                                                  d_out_len, lb);
+  else
+    k_compact_nonzero_u32<false><<<dim3(grid), dim3(kScanBlock), 0, env.stream()>>>(in, out, n_cap, d_n,
+                                                                                   d_out_len, lb);
+  env.prof_end("compact_nonzero_u32");
+  return check_launch(env, "compact_nonzero_u32 launch");
+}
+
+}  // namespace ka

@@ -1,0 +1,206 @@
+"""Marshalling conveniences over the C ABI: a system with its built-in program,
+spawning, composing, sending and receiving with numpy arrays or torch tensors.
+
+Nothing here computes: every call goes through ``libka.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_void_p
+
+import numpy as np
+
+from . import (KA_IN, KA_IN_OUT, KA_OUT, KA_PRIV, KA_REF, KA_SYS_PROFILE, KA_U32, KA_VAL, KA_WAH_INPUT_DEVICE,
+               KA_WAH_OUTPUT_REFS, arg, check, ka_nd_range, ka_system_config, ka_value, ka_wah_result, lib,
+               nd_range, ref, sig, val, values)
+
+
+class Session:
+    """One kernel-actor system on device 0 plus its built-in program."""
+
+    def __init__(self, n_streams: int = 1, profile: bool = False, budget_bytes: int = 0,
+                 use_torch_stream: bool = True):
+        cfg = ka_system_config()
+        cfg.device = 0
+        cfg.n_streams = n_streams
+        cfg.hbm_budget_bytes = budget_bytes
+        cfg.flags = KA_SYS_PROFILE if profile else 0
+        self.torch_stream = None
+        if use_torch_stream:
+            # A dedicated stream (default priority) made torch's current one, so
+            # torch copies, torch events and the library's kernels are ordered.
+            import torch
+            self.torch_stream = torch.cuda.Stream()
+            torch.cuda.set_stream(self.torch_stream)
+            cfg.stream = self.torch_stream.cuda_stream
+        self.sys = c_void_p()
+        check(lib.ka_system_create(byref(cfg), byref(self.sys)), "ka_system_create")
+        self.prog = c_void_p()
+        check(lib.ka_program_builtin(self.sys, byref(self.prog)), "ka_program_builtin")
+        self._keep = []
+
+    # ---- actors --------------------------------------------------------------------
+    def spawn(self, kernel: str, args, rng: ka_nd_range | None = None, prog=None) -> c_void_p:
+        a = c_void_p()
+        s = sig(*args)
+        r = rng if rng is not None else nd_range()
+        check(lib.ka_spawn(self.sys, prog or self.prog, kernel.encode(), byref(r), s, len(args), byref(a)),
+              f"ka_spawn {kernel}")
+        return a
+
+    def compose(self, outer, inner) -> c_void_p:
+        c = c_void_p()
+        check(lib.ka_compose(outer, inner, byref(c)), "ka_compose")
+        return c
+
+    def release_actor(self, a):
+        check(lib.ka_actor_release(a), "ka_actor_release")
+
+    def affine_actor(self, a: int, b: int, in_mode=KA_REF, out_mode=KA_REF) -> c_void_p:
+        ca = (ctypes.c_uint32 * 1)(a)
+        cb = (ctypes.c_uint32 * 1)(b)
+        return self.spawn("affine_u32", [arg(KA_IN_OUT, in_mode=in_mode, out_mode=out_mode),
+                                         arg(KA_PRIV, count=1, init=ca), arg(KA_PRIV, count=1, init=cb)])
+
+    # ---- messages ------------------------------------------------------------------
+    def send(self, actor, *vs: ka_value) -> c_void_p:
+        t = c_void_p()
+        check(lib.ka_send(actor, values(*vs) if vs else None, len(vs), byref(t)), "ka_send")
+        return t
+
+    def receive(self, ticket, n: int, timeout_us: int = -1):
+        """Receives n outputs: REF outputs as refs, VAL outputs as numpy arrays."""
+        outs = (ka_value * n)()
+        check(lib.ka_receive(ticket, outs, n, timeout_us), "ka_receive")  # sizes / refs
+        res = []
+        for i in range(n):
+            if outs[i].mode == KA_REF:
+                res.append(c_void_p(outs[i].ref))
+            else:
+                buf = np.empty(outs[i].count, dtype=np.uint32)
+                res.append(buf)
+        vals = [i for i in range(n) if outs[i].mode == KA_VAL]
+        if vals:
+            outs2 = (ka_value * n)()
+            for i in range(n):
+                if i in vals:
+                    outs2[i].ptr = res[i].ctypes.data if res[i].size else None
+                    outs2[i].count = res[i].size
+            check(lib.ka_receive(ticket, outs2, n, timeout_us), "ka_receive")
+            for i in range(n):
+                if outs2[i].mode == KA_REF:  # the second receive returned new refs too
+                    lib.ka_ref_release(c_void_p(outs2[i].ref))
+        return res
+
+    def release_ticket(self, t):
+        check(lib.ka_ticket_release(t), "ka_ticket_release")
+
+    def request(self, actor, *vs: ka_value, n_out: int):
+        t = self.send(actor, *vs)
+        try:
+            return self.receive(t, n_out)
+        finally:
+            self.release_ticket(t)
+
+    # ---- refs ----------------------------------------------------------------------
+    def wrap(self, tensor) -> c_void_p:
+        """Borrowed ref over a contiguous 4-byte torch tensor on the device."""
+        assert tensor.is_cuda and tensor.is_contiguous() and tensor.element_size() == 4
+        r = c_void_p()
+        check(lib.ka_ref_wrap(self.sys, c_void_p(tensor.data_ptr()), KA_U32, tensor.numel(), 3, byref(r)),
+              "ka_ref_wrap")
+        return r
+
+    def upload(self, x: np.ndarray):
+        """A torch tensor on the device holding the uint32 array x."""
+        import torch
+        x = np.ascontiguousarray(x, dtype=np.uint32)
+        return torch.from_numpy(x.view(np.int32)).to("cuda")
+
+    def length(self, r) -> int:
+        n = ctypes.c_uint64()
+        check(lib.ka_ref_info(r, None, byref(n), None), "ka_ref_info")
+        return n.value
+
+    def read(self, r) -> np.ndarray:
+        n = self.length(r)
+        out = np.empty(n, dtype=np.uint32)
+        if n:
+            check(lib.ka_ref_read(r, out.ctypes.data, n * 4), "ka_ref_read")
+        return out
+
+    def release_ref(self, r):
+        check(lib.ka_ref_release(r), "ka_ref_release")
+
+    def device_ptr(self, r) -> int:
+        p = c_void_p()
+        check(lib.ka_ref_device_ptr(r, byref(p)), "ka_ref_device_ptr")
+        return p.value or 0
+
+    # ---- composed index --------------------------------------------------------------
+    def wah_index(self, values_, refs: bool = False):
+        """WAH index of a numpy uint32 array (host input) or a device tensor.
+        Returns (keys, offsets, words) numpy arrays, or the result struct with refs."""
+        res = ka_wah_result()
+        flags = KA_WAH_OUTPUT_REFS if refs else 0
+        if isinstance(values_, np.ndarray):
+            v = np.ascontiguousarray(values_, dtype=np.uint32)
+            check(lib.ka_wah_index(self.sys, v.ctypes.data if v.size else None, v.size, flags, byref(res)),
+                  "ka_wah_index")
+        else:
+            check(lib.ka_wah_index(self.sys, c_void_p(values_.data_ptr()), values_.numel(),
+                                   flags | KA_WAH_INPUT_DEVICE, byref(res)), "ka_wah_index")
+        if refs:
+            return res
+        D, W = res.D, res.W
+        keys = np.ctypeslib.as_array(res.keys, shape=(max(D, 1),))[:D].copy()
+        offs = np.ctypeslib.as_array(res.offsets, shape=(D + 1,)).copy()
+        words = np.ctypeslib.as_array(res.words, shape=(max(W, 1),))[:W].copy()
+        check(lib.ka_wah_result_free(byref(res)), "ka_wah_result_free")
+        return keys, offs, words
+
+    def stream_handle(self, i: int = 0) -> int:
+        s = c_void_p()
+        check(lib.ka_system_stream(self.sys, i, byref(s)), "ka_system_stream")
+        return s.value or 0
+
+    def synchronize(self):
+        check(lib.ka_system_synchronize(self.sys), "ka_system_synchronize")
+
+    def profile(self, kernel: str):
+        n = ctypes.c_uint64()
+        ms = ctypes.c_double()
+        check(lib.ka_profile_get(self.sys, kernel.encode(), byref(n), byref(ms)), "ka_profile_get")
+        return n.value, ms.value
+
+    def profile_reset(self):
+        check(lib.ka_profile_reset(self.sys), "ka_profile_reset")
+
+    def memory(self):
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib.ka_system_memory(self.sys, byref(a), byref(b)), "ka_system_memory")
+        return a.value, b.value
+
+    def close(self):
+        if self.prog:
+            lib.ka_program_release(self.prog)
+            self.prog = None
+        if self.sys:
+            check(lib.ka_system_destroy(self.sys), "ka_system_destroy")
+            self.sys = None
+        if self.torch_stream is not None:
+            import torch
+            torch.cuda.synchronize()
+            torch.cuda.set_stream(torch.cuda.default_stream())
+            self.torch_stream = None
+
+
+def sig_in(mode=KA_REF):
+    return arg(KA_IN, in_mode=mode)
+
+
+def sig_out(mode=KA_REF, count=0):
+    return arg(KA_OUT, out_mode=mode, count=count)
+
+
+__all__ = ["Session", "sig_in", "sig_out", "val", "ref", "KA_VAL", "KA_REF"]

@@ -1,0 +1,275 @@
+"""GPU parity: every built-in kernel actor and the composed pipeline against the
+CPU oracle, element by element on the same seeded inputs.  Everything is
+uint32 arithmetic, so the bar is bit-exactness."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+SCAN_TILE, SORT_TILE, ENC_TILE = 4096, 8192, 2048
+
+
+@pytest.fixture(scope="module")
+def sess():
+    from paper_1709_07781_amd.session import Session
+    s = Session()
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def ora():
+    return oracle.default()
+
+
+def _ka():
+    import paper_1709_07781_amd as ka
+    return ka
+
+
+# ---- exclusive scan ------------------------------------------------------------------
+SCAN_SIZES = [1, 2, 3, 4, 5, 63, 64, 65, SCAN_TILE - 1, SCAN_TILE, SCAN_TILE + 1, 3 * SCAN_TILE + 7,
+              70 * SCAN_TILE + 3, (1 << 20) + 1]
+
+
+@pytest.mark.parametrize("n", SCAN_SIZES)
+def test_exclusive_scan(sess, ora, n):
+    ka = _ka()
+    x = workloads.u32(1000 + n, n)
+    act = sess.spawn("exclusive_scan_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL)])
+    try:
+        (y,) = sess.request(act, ka.val(x.ctypes.data, n), n_out=1)
+    finally:
+        sess.release_actor(act)
+    np.testing.assert_array_equal(y, ora.exclusive_scan(x))
+
+
+def test_exclusive_scan_constant_wraps(sess, ora):
+    ka = _ka()
+    n = 5 * SCAN_TILE + 11
+    x = np.full(n, 0xDEADBEEF, dtype=np.uint32)
+    act = sess.spawn("exclusive_scan_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL)])
+    (y,) = sess.request(act, ka.val(x.ctypes.data, n), n_out=1)
+    sess.release_actor(act)
+    exp = (np.arange(n, dtype=np.uint64) * np.uint64(0xDEADBEEF)) & np.uint64(0xFFFFFFFF)
+    np.testing.assert_array_equal(y, exp.astype(np.uint32))
+
+
+def test_exclusive_scan_unaligned_device_input(sess, ora):
+    """A borrowed input that starts 4 bytes into a tensor (not 16-byte aligned)."""
+    ka = _ka()
+    n = 2 * SCAN_TILE + 9
+    x = workloads.u32(77, n + 1)
+    t = sess.upload(x)
+    import ctypes
+    r = ctypes.c_void_p()
+    ka.check(ka.lib.ka_ref_wrap(sess.sys, ctypes.c_void_p(t.data_ptr() + 4), ka.KA_U32, n, 3, ctypes.byref(r)))
+    act = sess.spawn("exclusive_scan_u32", [ka.arg(ka.KA_IN), ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL)])
+    (y,) = sess.request(act, ka.ref(r), n_out=1)
+    sess.release_actor(act)
+    sess.release_ref(r)
+    np.testing.assert_array_equal(y, ora.exclusive_scan(x[1:]))
+
+
+# ---- compaction ----------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 5, SCAN_TILE - 1, SCAN_TILE, SCAN_TILE + 1, 9 * SCAN_TILE + 13, (1 << 20) + 5])
+@pytest.mark.parametrize("zeros", ["none", "third", "all", "most"])
+def test_compact_nonzero(sess, ora, n, zeros):
+    ka = _ka()
+    x = workloads.u32(2000 + n, n)
+    x[x == 0] = 1
+    sel = workloads.uniform_values(3000 + n, n, 16)
+    if zeros == "third":
+        x[sel < 5] = 0
+    elif zeros == "all":
+        x[:] = 0
+    elif zeros == "most":
+        x[sel != 0] = 0
+    act = sess.spawn("compact_nonzero_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL)])
+    (y,) = sess.request(act, ka.val(x.ctypes.data, n), n_out=1)
+    sess.release_actor(act)
+    np.testing.assert_array_equal(y, ora.compact_nonzero(x))
+
+
+# ---- affine ----------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 3, 4, 4095, 4096, 4097, 100003, 1 << 20])
+def test_affine(sess, ora, n):
+    ka = _ka()
+    a, b = workloads.affine_params(5 + n, 1)
+    x = workloads.u32(6 + n, n)
+    act = sess.affine_actor(int(a[0]), int(b[0]), in_mode=ka.KA_VAL, out_mode=ka.KA_VAL)
+    (y,) = sess.request(act, ka.val(x.ctypes.data, n), n_out=1)
+    sess.release_actor(act)
+    np.testing.assert_array_equal(y, ora.affine_chain(x, a, b))
+
+
+def test_affine_offset_range(sess, ora):
+    """ND-range with a global offset: only elements [off, off+m) change."""
+    ka = _ka()
+    n, off, m = 10000, 37, 5000
+    a, b = workloads.affine_params(8, 1)
+    x = workloads.u32(9, n)
+    import ctypes
+    ca, cb = (ctypes.c_uint32 * 1)(int(a[0])), (ctypes.c_uint32 * 1)(int(b[0]))
+    act = sess.spawn("affine_u32", [ka.arg(ka.KA_IN_OUT, in_mode=ka.KA_VAL, out_mode=ka.KA_VAL),
+                                    ka.arg(ka.KA_PRIV, count=1, init=ca), ka.arg(ka.KA_PRIV, count=1, init=cb)],
+                     rng=ka.nd_range(global0=m, offset0=off))
+    (y,) = sess.request(act, ka.val(x.ctypes.data, n), n_out=1)
+    sess.release_actor(act)
+    exp = x.copy()
+    exp[off:off + m] = ora.affine_chain(x[off:off + m], a, b)
+    np.testing.assert_array_equal(y[:n], exp)
+
+
+# ---- radix sort ----------------------------------------------------------------------
+SORT_SIZES = [1, 2, 63, 64, SORT_TILE - 1, SORT_TILE, SORT_TILE + 1, 3 * SORT_TILE + 7, 100_003]
+
+
+@pytest.mark.parametrize("kind", ["uniform1024", "u32", "all_equal", "distinct", "reverse", "zipf", "all_max",
+                                  "high_bits", "presorted", "sparse_hot"])
+@pytest.mark.parametrize("n", SORT_SIZES)
+def test_radix_sort_rows(sess, ora, kind, n):
+    ka = _ka()
+    v = workloads.structured(kind, n, seed=n)
+    act = sess.spawn("radix_sort_rows_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL),
+                                             ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL), ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL)])
+    sk, sr = sess.request(act, ka.val(v.ctypes.data, n), n_out=2)
+    sess.release_actor(act)
+    ek, er = ora.sort_pairs(v)
+    np.testing.assert_array_equal(sk, ek)
+    np.testing.assert_array_equal(sr, er)
+
+
+@pytest.mark.parametrize("n", [1, 1000, SORT_TILE + 1, 50_001])
+def test_radix_sort_pairs_explicit_rows(sess, ora, n):
+    ka = _ka()
+    v = workloads.structured("u32", n, seed=n + 1) % np.uint32(3000)
+    rows = workloads.u32(n + 2, n)
+    act = sess.spawn("radix_sort_pairs_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_IN, in_mode=ka.KA_VAL),
+                                              ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL), ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL)])
+    sk, sr = sess.request(act, ka.val(v.ctypes.data, n), ka.val(rows.ctypes.data, n), n_out=2)
+    sess.release_actor(act)
+    ek, er = ora.sort_pairs(v, rows)
+    np.testing.assert_array_equal(sk, ek)
+    np.testing.assert_array_equal(sr, er)
+
+
+# ---- WAH encode on sorted pairs ----------------------------------------------------------
+@pytest.mark.parametrize("kind", ["uniform1024", "all_equal", "distinct", "zipf", "alternating_chunks", "sparse_hot",
+                                  "all_max"])
+@pytest.mark.parametrize("n", [1, 30, 31, 32, 62, ENC_TILE - 1, ENC_TILE, ENC_TILE + 1, ENC_TILE + 31,
+                               5 * ENC_TILE + 17, 65_536])
+def test_wah_encode_sorted(sess, ora, kind, n):
+    ka = _ka()
+    v = workloads.structured(kind, n, seed=n + 3)
+    sk, sr = ora.sort_pairs(v)
+    act = sess.spawn("wah_encode_sorted", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_IN, in_mode=ka.KA_VAL)]
+                     + [ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL) for _ in range(3)])
+    keys, offs, words = sess.request(act, ka.val(sk.ctypes.data, n), ka.val(sr.ctypes.data, n), n_out=3)
+    sess.release_actor(act)
+    ek, eo, ew = ora.wah_encode_sorted(sk, sr)
+    np.testing.assert_array_equal(keys, ek)
+    np.testing.assert_array_equal(offs, eo)
+    np.testing.assert_array_equal(words, ew)
+
+
+# ---- the composed index ------------------------------------------------------------------
+@pytest.mark.parametrize("kind", workloads.STRUCTURED_KINDS)
+@pytest.mark.parametrize("n", [0, 1, 31, 32, 2047, 2048, 2049, 8191, 8192, 8193, 40_000])
+def test_wah_index_host(sess, ora, kind, n):
+    v = workloads.structured(kind, n, seed=7 * n + 1)
+    got = sess.wah_index(v)
+    exp = ora.wah_index(v)
+    for g, e, what in zip(got, exp, ("keys", "offsets", "words")):
+        np.testing.assert_array_equal(g, e, err_msg=f"{what} {kind} n={n}")
+
+
+def test_wah_index_plain_request(sess, ora):
+    """The plain request: 2^16 values uniform in [0, 1024)."""
+    v = workloads.plain_request()
+    t = sess.upload(v)
+    got = sess.wah_index(t)
+    exp = ora.wah_index(v)
+    for g, e in zip(got, exp):
+        np.testing.assert_array_equal(g, e)
+
+
+def test_wah_index_composed_equals_stepwise(sess, ora):
+    """fuse(msg) = encode(sort(msg)): the composed actor gives the same words
+    as sending to the two stages one after the other (Sec. 3.5, 4.1)."""
+    ka = _ka()
+    v = workloads.structured("zipf", 30_000, seed=5)
+    sort = sess.spawn("radix_sort_rows_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_OUT), ka.arg(ka.KA_OUT)])
+    enc = sess.spawn("wah_encode_sorted", [ka.arg(ka.KA_IN), ka.arg(ka.KA_IN)]
+                     + [ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL) for _ in range(3)])
+    comp = sess.compose(enc, sort)
+    composed = sess.request(comp, ka.val(v.ctypes.data, v.size), n_out=3)
+    sk, sr = sess.request(sort, ka.val(v.ctypes.data, v.size), n_out=2)
+    stepwise = sess.request(enc, ka.ref(sk), ka.ref(sr), n_out=3)
+    sess.release_ref(sk)
+    sess.release_ref(sr)
+    for a in (sort, enc, comp):
+        sess.release_actor(a)
+    exp = ora.wah_index(v)
+    for c, s, e in zip(composed, stepwise, exp):
+        np.testing.assert_array_equal(c, e)
+        np.testing.assert_array_equal(s, e)
+
+
+# ---- the affine chain ---------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["device_refs", "host_round_trip"])
+@pytest.mark.parametrize("m", [1 << 10, 1 << 14, (1 << 18) + 3])
+def test_affine_chain(sess, ora, mode, m):
+    ka = _ka()
+    a, b = workloads.chain_params(2, 8)
+    x = workloads.chain_input(2, m)
+    inner_in = ka.KA_VAL
+    mid = ka.KA_REF if mode == "device_refs" else ka.KA_VAL
+    actors = []
+    for i in range(8):
+        im = inner_in if i == 0 else mid
+        om = ka.KA_VAL if i == 7 else mid
+        actors.append(sess.affine_actor(int(a[i]), int(b[i]), in_mode=im, out_mode=om))
+    chain = actors[0]
+    for act in actors[1:]:
+        chain = sess.compose(act, chain)
+    (y,) = sess.request(chain, ka.val(x.ctypes.data, m), n_out=1)
+    for act in actors:
+        sess.release_actor(act)
+    np.testing.assert_array_equal(y, ora.affine_chain(x, a, b))
+
+
+# ---- device-resident lengths between stages -----------------------------------------------
+def test_compaction_feeds_scan_without_host_length(sess, ora):
+    """A data-dependent length handed on as a device count (Sec. 4.1 config
+    array): compaction then scan of the kept elements."""
+    ka = _ka()
+    n = 3 * SCAN_TILE + 100
+    x = workloads.u32(31, n)
+    x[workloads.uniform_values(32, n, 3) == 0] = 0
+    comp = sess.spawn("compact_nonzero_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_OUT)])
+    scan = sess.spawn("exclusive_scan_u32", [ka.arg(ka.KA_IN), ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL)])
+    chain = sess.compose(scan, comp)
+    (y,) = sess.request(chain, ka.val(x.ctypes.data, n), n_out=1)
+    for a in (comp, scan, chain):
+        sess.release_actor(a)
+    np.testing.assert_array_equal(y, ora.exclusive_scan(ora.compact_nonzero(x)))
+
+
+def test_ref_outputs_and_info(sess, ora):
+    ka = _ka()
+    v = workloads.plain_request()
+    res = sess.wah_index(v, refs=True)
+    import ctypes
+    keys = sess.read(ctypes.c_void_p(res.keys_ref))
+    offs = sess.read(ctypes.c_void_p(res.offsets_ref))
+    words = sess.read(ctypes.c_void_p(res.words_ref))
+    assert keys.size == res.D and words.size == res.W and offs.size == res.D + 1
+    ka.check(ka.lib.ka_wah_result_free(ctypes.byref(res)))
+    exp = ora.wah_index(v)
+    np.testing.assert_array_equal(keys, exp[0])
+    np.testing.assert_array_equal(offs, exp[1])
+    np.testing.assert_array_equal(words, exp[2])
