@@ -46,6 +46,19 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_code_object(src: str, out: str | None = None) -> str:
+    """Compiles a HIP source of user kernels into a gfx950 code object (.hsaco)
+    for ka_program_load."""
+    out = out or os.path.splitext(src)[0] + ".hsaco"
+    cmd = [HIPCC, "--genco", "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", src, "-o", out + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"code object build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

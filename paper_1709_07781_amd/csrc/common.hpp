@@ -28,7 +28,12 @@ struct LookbackArena {
   uint32_t epoch = 0;                    // last epoch handed out (1 .. 2^30-1)
   uint32_t* hist[2] = {nullptr, nullptr};  // radix digit histograms, double-buffered
   uint32_t hist_turn = 0;
+  void* plan = nullptr;                    // radix sort plan (kSortPlanBytes)
 };
+
+// Device memory of one arena: ticket counter, two histograms, the sort plan.
+constexpr uint32_t kArenaTicketBytes = 256, kArenaHistBytes = 4096, kSortPlanBytes = 8192;
+constexpr uint32_t kArenaBytes = kArenaTicketBytes + 2 * kArenaHistBytes + kSortPlanBytes;
 
 // Per-launch arguments of a look-back kernel.
 struct LbArgs {
@@ -78,6 +83,32 @@ constexpr int kOk = 0, kErrArg = -1, kErrDevice = -5, kErrOom = -6, kErrLaunch =
 inline int check_launch(Env& env, const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return env.fail(kErrLaunch, what);
+  return kOk;
+}
+
+// Work-groups of `kernel` that fit on the device at once (occupancy x CUs).
+int coresident_blocks(const void* kernel, int block_threads);
+
+// Persistent look-back kernels: a cooperative launch guarantees that all
+// work-groups of the grid are resident together, so a work-group that waits
+// for a lower tile always waits for a running one.  Tiles are then assigned
+// statically (tile = blockIdx.x + k * gridDim.x) and no ticket counter, whose
+// same-address atomics serialise, is needed.
+template <typename... Args>
+int launch_persistent(Env& env, const char* name, void (*kernel)(Args...), uint32_t tiles, uint32_t block,
+                      Args... args) {
+  int cap = coresident_blocks(reinterpret_cast<const void*>(kernel), (int)block);
+  if (cap <= 0) return env.fail(kErrLaunch, "persistent launch: no resident work-group fits");
+  const uint32_t grid = tiles < (uint32_t)cap ? (tiles ? tiles : 1u) : (uint32_t)cap;
+  void* params[] = {reinterpret_cast<void*>(&args)...};
+  env.prof_begin(name);
+  hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(block), params,
+                                            0, env.stream());
+  env.prof_end(name);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return env.fail(kErrLaunch, name);
+  }
   return kOk;
 }
 
@@ -164,33 +195,54 @@ __device__ __forceinline__ uint32_t lb_flag(uint64_t w, uint32_t epoch) {
 }
 
 // Decoupled look-back by one whole wave over a single channel whose status
-// word for tile t is status[t * stride].  Lane l inspects predecessor j - l;
-// the window slides back 64 tiles at a time until an inclusive prefix is
-// found.  Returns the exclusive prefix of `tile` in every lane.
+// word for tile t is status[t * stride].  In a round, lane l inspects the
+// kDepth predecessors j - kDepth*l .. j - kDepth*l - kDepth + 1, so one round
+// trip to memory covers 64*kDepth tiles; the window slides back until an
+// inclusive prefix is found.  Returns the exclusive prefix of `tile` in every
+// lane.  Every lane of the wave must call it.
+template <int kDepth>
 __device__ __forceinline__ uint32_t lb_lookback_wave(const uint64_t* status, uint32_t stride, uint32_t tile,
                                                      uint32_t epoch) {
   const uint32_t lane = lane_id();
   uint32_t excl = 0;
   int64_t j = (int64_t)tile - 1;
   while (j >= 0) {
-    const int64_t idx = j - (int64_t)lane;
-    uint32_t f = kLbInclusive, v = 0;
-    if (idx >= 0) {
-      const uint64_t w = lb_load(status + (uint64_t)idx * stride);
-      f = lb_flag(w, epoch);
-      v = (uint32_t)(w >> 32);
+    uint64_t w[kDepth];
+#pragma unroll
+    for (int k = 0; k < kDepth; ++k) {
+      const int64_t idx = j - (int64_t)(kDepth * lane + k);
+      w[k] = idx >= 0 ? lb_load(status + (uint64_t)idx * stride) : 0ull;
     }
-    const uint64_t inc = __ballot(f == kLbInclusive);
-    const uint64_t notready = __ballot(f == 0);
+    // This lane's run of predecessors, nearest first: 2 = reaches an inclusive
+    // prefix (or the start), 1 = all aggregates, 0 = meets an unpublished tile.
+    uint32_t state = 1, sum = 0;
+#pragma unroll
+    for (int k = 0; k < kDepth; ++k) {
+      if (state != 1) break;
+      const int64_t idx = j - (int64_t)(kDepth * lane + k);
+      if (idx < 0) {
+        state = 2;
+        break;
+      }
+      const uint32_t f = lb_flag(w[k], epoch);
+      if (f == 0) {
+        state = 0;
+        break;
+      }
+      sum += (uint32_t)(w[k] >> 32);
+      if (f == kLbInclusive) state = 2;
+    }
+    const uint64_t inc = __ballot(state == 2);
+    const uint64_t stall = __ballot(state == 0);
     const uint32_t stop = inc ? (uint32_t)__builtin_ctzll(inc) : 63u;
     const uint64_t need = (stop == 63u) ? ~0ull : ((2ull << stop) - 1ull);
-    if (notready & need) {
+    if (stall & need) {
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    excl += wave_sum(lane <= stop ? v : 0u);
+    excl += wave_sum(lane <= stop ? sum : 0u);
     if (inc) break;
-    j -= 64;
+    j -= 64 * kDepth;
   }
   return excl;
 }

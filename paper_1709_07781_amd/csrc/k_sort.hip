@@ -2,22 +2,30 @@
 // and 2 of the WAH index build (Sec. 4.1: tag every value with its input
 // position, then sort by value; Sec. 4.2 sorts with a radix sort).
 //
-// Structure (8-bit digits, up to 4 passes):
-//  * k_radix_hist reads the keys once and builds the digit histograms of all
-//    four passes (LDS sub-histograms per wave, wave-aggregated LDS atomics for
-//    runs of equal digits, one global atomic per non-empty bin and work-group).
-//  * k_radix_pass, once per digit position.  Every work-group derives the same
-//    plan from the histograms: a pass whose digit is the same for all keys is
-//    the identity of a stable sort and is skipped (so 16-bit keys cost two
-//    passes), the first active pass reads the input (and makes row ids
-//    0..n-1 when no rows are given), later ones read the previous active
-//    pass's output, and the last active pass writes the caller's buffers.
-//    Inside a pass a tile is ranked with wave64 ballots (peers with the same
-//    digit within the wave, counted against lanes of lower index, so equal
-//    keys keep their order), per-digit global offsets come from the upfront
-//    histogram plus a decoupled look-back over the tile counts of earlier
-//    tiles, and the tile is reordered through LDS so that consecutive
-//    work-items write consecutive addresses of each digit's run.
+// 8-bit digits, up to four passes, each a reduce-then-scan over tiles of
+// kTile keys -- no work-group ever waits for another one's tile:
+//  * k_radix_count (cooperative launch, a few hundred work-groups, each owning
+//    a contiguous range of tiles) counts every tile's digits into a table and
+//    sums its range; after one grid barrier each work-group turns its tiles'
+//    counts into global offsets: the digit's start (exclusive prefix over
+//    digits of the digit totals) plus the counts of all earlier tiles.  The
+//    pass-0 instance also forms the OR and the AND of all keys for the sort
+//    plan: a pass whose digit is the same in every key (equal in the OR and
+//    the AND) is the identity of a stable sort and is skipped, so 16-bit keys
+//    cost two passes.
+//  * k_radix_scatter (one work-group per tile) ranks its keys by digit inside
+//    each wave with an LDS match (every lane ORs its lane bit into a 64-bit
+//    mask per digit and reads back the mask of its digit, so equal keys keep
+//    their order), reorders the tile by digit in LDS and writes each digit's
+//    run to its offset from the table, consecutive work-items writing
+//    consecutive addresses.
+// The first active pass reads the input (and makes row ids 0..n-1 when no rows
+// are given), later ones read the previous active pass's output, and the last
+// active pass writes the caller's buffers.
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace ka {
@@ -27,75 +35,21 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kPasses = 32 / kRadixBits;
 
-constexpr int kHistBlock = 256;
-constexpr int kHistWaves = kHistBlock / 64;
+constexpr int kBlock = 1024;
+constexpr int kWaves = kBlock / 64;
+constexpr int kItems = 8;
+constexpr int kTile = kBlock * kItems;  // 8192 keys per tile
+constexpr int kCountVecs = kTile / 4 / kBlock;
 
-constexpr int kPassBlock = 512;
-constexpr int kPassItems = 16;
-constexpr int kPassWaves = kPassBlock / 64;
-constexpr int kPassTile = kPassBlock * kPassItems;  // 8192 pairs
-constexpr uint32_t kNoDigit = kRadix;               // marks elements past the end
+}  // namespace
 
-// LDS add of 1 to bin d by every active lane, aggregated over lanes that share
-// the first active lane's bin (the common case for skewed or high digits).
-__device__ __forceinline__ void lds_add_aggregated(uint32_t* bins, uint32_t d, bool valid) {
-  uint64_t active = __ballot(valid);
-  if (!active) return;
-  const uint32_t first_lane = (uint32_t)__builtin_ctzll(active);
-  const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, (int)first_lane);
-  const uint64_t same = __ballot(valid && d == d0);
-  if (lane_id() == first_lane) atomicAdd(&bins[d0], (uint32_t)__popcll(same));
-  if (valid && d != d0) atomicAdd(&bins[d], 1u);
-}
+// The sort plan, written by the pass-0 count kernel.
+struct SortPlan {
+  uint32_t active;  // bit p: pass p moves data
+};
+static_assert(sizeof(SortPlan) <= kSortPlanBytes, "plan storage");
 
-__global__ __launch_bounds__(kHistBlock) void k_radix_hist(const uint32_t* __restrict__ keys, uint64_t n,
-                                                           uint32_t* __restrict__ hist,
-                                                           uint32_t* __restrict__ hist_next) {
-  __shared__ uint32_t s_bins[kHistWaves][kPasses][kRadix];
-  uint32_t* flat = &s_bins[0][0][0];
-  for (int i = threadIdx.x; i < kHistWaves * kPasses * kRadix; i += kHistBlock) flat[i] = 0;
-  // The other histogram buffer is cleared here for the next sort on this
-  // stream; the previous sort, which used it, has completed (stream order).
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < kPasses * kRadix; i += kHistBlock) hist_next[i] = 0;
-  __syncthreads();
-  const uint32_t w = threadIdx.x / 64;
-  const bool vec = (reinterpret_cast<uintptr_t>(keys) & 15u) == 0;
-  const uint64_t nvec = (n + 3) / 4;
-  for (uint64_t q = (uint64_t)blockIdx.x * kHistBlock + threadIdx.x; q - threadIdx.x < nvec;
-       q += (uint64_t)gridDim.x * kHistBlock) {
-    uint32_t k[4];
-    bool valid[4];
-    const uint64_t e = q * 4;
-    if (vec && e + 4 <= n) {
-      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + e));
-      k[0] = v.x;
-      k[1] = v.y;
-      k[2] = v.z;
-      k[3] = v.w;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) valid[j] = true;
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        valid[j] = (q < nvec) && (e + j < n);
-        k[j] = valid[j] ? keys[e + j] : 0u;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int p = 0; p < kPasses; ++p)
-        lds_add_aggregated(s_bins[w][p], (k[j] >> (p * kRadixBits)) & (kRadix - 1), valid[j]);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kPasses * kRadix; i += kHistBlock) {
-    uint32_t sum = 0;
-#pragma unroll
-    for (int ww = 0; ww < kHistWaves; ++ww) sum += (&s_bins[ww][0][0])[i];
-    if (sum) atomicAdd(&hist[i], sum);
-  }
-}
+namespace {
 
 struct PassBuffers {
   const uint32_t* keys_in;
@@ -106,128 +60,304 @@ struct PassBuffers {
   uint32_t* rows_b;
 };
 
-__global__ __launch_bounds__(kPassBlock) void k_radix_pass(PassBuffers buf, const uint32_t* __restrict__ hist,
-                                                           uint32_t pass, uint32_t n, LbArgs lb) {
-  __shared__ uint32_t s_keys[kPassTile];
-  __shared__ uint32_t s_rows[kPassTile];
-  __shared__ uint32_t s_wcnt[kPassWaves][kRadix];  // per-wave digit counts, then per-wave offsets
-  __shared__ uint32_t s_loff[kRadix];              // tile-local start of each digit
-  __shared__ uint32_t s_dbase[kRadix];             // global start minus tile-local start
-  __shared__ uint32_t s_scan[kPassBlock / 64];
-  __shared__ uint32_t s_tile, s_full;
+struct PassIo {
+  const uint32_t* src_keys;
+  const uint32_t* src_rows;
+  uint32_t* dst_keys;
+  uint32_t* dst_rows;
+  bool implicit_rows;
+};
 
-  const uint32_t tile = lb_take_tile(lb, &s_tile);
-  const uint32_t tid = threadIdx.x;
-
-  // ---- plan: a pass is active unless one digit holds all n keys -------------
-  if (tid == 0) s_full = 0;
-  __syncthreads();
-  if (tid < kRadix) {
-#pragma unroll
-    for (int p = 0; p < kPasses; ++p)
-      if (hist[p * kRadix + tid] == n) atomicOr(&s_full, 1u << p);
-  }
-  __syncthreads();
-  uint32_t active = ~s_full & ((1u << kPasses) - 1);
-  if (active == 0) active = 1u << (kPasses - 1);  // all keys equal: one pass still moves them
-  if (!((active >> pass) & 1u)) return;
+// Source and destination of pass `pass` under the plan's active mask: the
+// last active pass writes buffer a, the one before it b, and so on.
+__device__ __forceinline__ PassIo pass_io(const PassBuffers& buf, uint32_t active, uint32_t pass) {
   const uint32_t later = (uint32_t)__popc(active >> pass);  // active passes from this one on
   const bool first = (active & ((1u << pass) - 1)) == 0;
-  uint32_t* dst_keys = (later & 1u) ? buf.keys_a : buf.keys_b;
-  uint32_t* dst_rows = (later & 1u) ? buf.rows_a : buf.rows_b;
-  const uint32_t* src_keys = first ? buf.keys_in : (((later + 1) & 1u) ? buf.keys_a : buf.keys_b);
-  const uint32_t* src_rows = first ? buf.rows_in : (((later + 1) & 1u) ? buf.rows_a : buf.rows_b);
-  const bool implicit_rows = first && buf.rows_in == nullptr;
+  PassIo io;
+  io.dst_keys = (later & 1u) ? buf.keys_a : buf.keys_b;
+  io.dst_rows = (later & 1u) ? buf.rows_a : buf.rows_b;
+  io.src_keys = first ? buf.keys_in : (((later + 1) & 1u) ? buf.keys_a : buf.keys_b);
+  io.src_rows = first ? buf.rows_in : (((later + 1) & 1u) ? buf.rows_a : buf.rows_b);
+  io.implicit_rows = first && buf.rows_in == nullptr;
+  return io;
+}
+
+// LDS add of 1 to bin d by every active lane, aggregated over lanes that share
+// the first active lane's bin (the common case for skewed or high digits).
+__device__ __forceinline__ void lds_add_aggregated(uint32_t* bins, uint32_t d, bool valid) {
+  const uint64_t active = __ballot(valid);
+  if (!active) return;
+  const uint32_t first_lane = (uint32_t)__builtin_ctzll(active);
+  const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, (int)first_lane);
+  const uint64_t same = __ballot(valid && d == d0);
+  if (lane_id() == first_lane) atomicAdd(&bins[d0], (uint32_t)__popcll(same));
+  if (valid && d != d0) atomicAdd(&bins[d], 1u);
+}
+
+// ---------------------------------------------------------------------------------
+// count: per-tile digit counts -> per-tile digit offsets
+// ---------------------------------------------------------------------------------
+constexpr int kPartStride = kRadix + 2;  // per work-group: digit counts, then OR and AND of its keys
+
+template <bool kFirst>
+__global__ __launch_bounds__(kBlock) void k_radix_count(PassBuffers buf, SortPlan* __restrict__ plan,
+                                                        uint32_t* __restrict__ table, uint32_t* __restrict__ part,
+                                                        uint32_t pass, uint32_t n) {
+  __shared__ uint32_t s_tile[kWaves][kRadix];  // per-wave counts of the current tile
+  __shared__ uint32_t s_acc[kRadix];           // this work-group's counts over its tiles
+  __shared__ uint32_t s_scan[kWaves];
+  __shared__ uint32_t s_or[kWaves], s_and[kWaves];
+  const uint32_t tid = threadIdx.x, w = tid / 64;
+
+  uint32_t active = 1u;
+  if (!kFirst) {
+    active = plan->active;
+    if (!((active >> pass) & 1u)) return;  // uniform: no work-group reaches the grid barrier
+  }
+  const uint32_t* keys = kFirst ? buf.keys_in : pass_io(buf, active, pass).src_keys;
   const uint32_t shift = pass * kRadixBits;
+  const uint32_t ntiles = (n + kTile - 1) / kTile;
+  const uint32_t G = gridDim.x, b = blockIdx.x;
+  const uint32_t t0 = (uint32_t)((uint64_t)b * ntiles / G), t1 = (uint32_t)((uint64_t)(b + 1) * ntiles / G);
+  const bool vec = (reinterpret_cast<uintptr_t>(keys) & 15u) == 0;
 
-  const uint32_t base = tile * kPassTile;
-  if (base >= n) return;
-  const uint32_t tile_n = min((uint32_t)kPassTile, n - base);
-
-  for (int i = tid; i < kPassWaves * kRadix; i += kPassBlock) (&s_wcnt[0][0])[i] = 0;
-
-  // ---- load: wave w owns 64*kPassItems consecutive elements ---------------
-  const uint32_t w = tid / 64, lane = lane_id();
-  const uint32_t wbase = w * 64 * kPassItems;
-  uint32_t key[kPassItems], row[kPassItems], dig[kPassItems];
+  // Keys of a tile: element 4 (j * kBlock + tid) + c in slot (j, c).
+  auto fetch = [&](uint32_t t, uint32_t (&k)[kCountVecs][4]) {
+    const uint32_t base = t * kTile;
+    const uint32_t len = t < t1 ? min((uint32_t)kTile, n - base) : 0u;
 #pragma unroll
-  for (int i = 0; i < kPassItems; ++i) {
-    const uint32_t local = wbase + i * 64 + lane;
-    const bool valid = local < tile_n;
-    const uint32_t g = base + local;
-    key[i] = valid ? src_keys[g] : 0u;
-    row[i] = valid ? (implicit_rows ? g : src_rows[g]) : 0u;
-    dig[i] = valid ? ((key[i] >> shift) & (kRadix - 1)) : kNoDigit;
-  }
-  __syncthreads();
-
-  // ---- rank inside the wave: peers = lanes with the same digit -------------
-  uint32_t rank[kPassItems];
+    for (int j = 0; j < kCountVecs; ++j) {
+      const uint32_t e = 4 * (j * kBlock + tid);
+      if (vec && e + 4 <= len) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + base + e));
+        k[j][0] = v.x, k[j][1] = v.y, k[j][2] = v.z, k[j][3] = v.w;
+      } else {
 #pragma unroll
-  for (int i = 0; i < kPassItems; ++i) {
-    const bool valid = dig[i] != kNoDigit;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-      const uint64_t bal = __ballot((dig[i] >> b) & 1u);
-      peers &= ((dig[i] >> b) & 1u) ? bal : ~bal;
+        for (int c = 0; c < 4; ++c) k[j][c] = e + c < len ? keys[base + e + c] : 0u;
+      }
     }
-    const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
-    uint32_t old = 0;
-    if (valid) old = s_wcnt[w][dig[i]];
-    if (valid && below == 0) s_wcnt[w][dig[i]] = old + (uint32_t)__popcll(peers);
-    rank[i] = old + below;
+  };
+
+  if (tid < kRadix) s_acc[tid] = 0;
+  uint32_t kor = 0, kand = ~0u;
+  uint32_t cur[kCountVecs][4];
+  fetch(t0, cur);
+  for (uint32_t t = t0; t < t1; ++t) {
+    for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_tile[0][0])[i] = 0;
+    uint32_t nxt[kCountVecs][4];
+    fetch(t + 1, nxt);  // in flight while this tile is counted
+    __syncthreads();
+    const uint32_t len = min((uint32_t)kTile, n - t * kTile);
+#pragma unroll
+    for (int j = 0; j < kCountVecs; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bool valid = 4 * (j * kBlock + tid) + c < len;
+        lds_add_aggregated(s_tile[w], (cur[j][c] >> shift) & (kRadix - 1), valid);
+        if (kFirst && valid) {
+          kor |= cur[j][c];
+          kand &= cur[j][c];
+        }
+      }
+    __syncthreads();
+    if (tid < kRadix) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int ww = 0; ww < kWaves; ++ww) c += s_tile[ww][tid];
+      table[(uint64_t)t * kRadix + tid] = c;
+      s_acc[tid] += c;
+    }
+#pragma unroll
+    for (int j = 0; j < kCountVecs; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cur[j][c] = nxt[j][c];
+    __syncthreads();  // s_tile is cleared again for the next tile
+  }
+  uint32_t* mine = part + (uint64_t)b * kPartStride;
+  if (tid < kRadix) mine[tid] = s_acc[tid];
+  if (kFirst) {
+    // OR and AND of this work-group's keys: a pass moves data unless its digit
+    // is the same in every key, i.e. the same in the OR and the AND.
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      kor |= (uint32_t)__shfl_xor((int)kor, off);
+      kand &= (uint32_t)__shfl_xor((int)kand, off);
+    }
+    if (lane_id() == 0) {
+      s_or[w] = kor;
+      s_and[w] = kand;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t o = 0, a = ~0u;
+      for (int ww = 0; ww < kWaves; ++ww) {
+        o |= s_or[ww];
+        a &= s_and[ww];
+      }
+      mine[kRadix] = o;
+      mine[kRadix + 1] = a;
+    }
+  }
+  cooperative_groups::this_grid().sync();
+
+  // ---- every work-group: the start of its range for each digit ------------------
+  // Work-item (q, d) sums the partials of every fourth work-group for digit d;
+  // the loads are independent and unrolled so that many are in flight.
+  uint32_t tot = 0, carry = 0;
+  {
+    const uint32_t d = tid & (kRadix - 1), q = tid >> 8;
+#pragma unroll 8
+    for (uint32_t bb = q; bb < G; bb += kBlock / kRadix) {
+      const uint32_t c = part[(uint64_t)bb * kPartStride + d];
+      tot += c;
+      carry += bb < b ? c : 0u;
+    }
+    __syncthreads();
+    s_tile[q][d] = tot;          // s_tile is free again: reuse it for the four quarters
+    s_tile[4 + q][d] = carry;
+    __syncthreads();
+    if (tid < kRadix) {
+      tot = s_tile[0][tid] + s_tile[1][tid] + s_tile[2][tid] + s_tile[3][tid];
+      carry = s_tile[4][tid] + s_tile[5][tid] + s_tile[6][tid] + s_tile[7][tid];
+    }
+  }
+  uint32_t total;
+  const uint32_t start = block_excl_scan<kBlock>(tid < kRadix ? tot : 0u, s_scan, &total);
+  if (kFirst && b == 0 && tid == 0) {
+    uint32_t o = 0, a = ~0u;
+    for (uint32_t bb = 0; bb < G; ++bb) {
+      o |= part[(uint64_t)bb * kPartStride + kRadix];
+      a &= part[(uint64_t)bb * kPartStride + kRadix + 1];
+    }
+    const uint32_t diff = o ^ a;
+    uint32_t act = 0;
+    for (int p = 0; p < kPasses; ++p)
+      if ((diff >> (p * kRadixBits)) & (kRadix - 1)) act |= 1u << p;
+    if (act == 0) act = 1u << (kPasses - 1);  // all keys equal: one pass still moves them
+    plan->active = act;
+  }
+  // ---- counts of this work-group's tiles -> offsets (16 tiles per round) -----------
+  if (tid < kRadix) {
+    uint32_t run = start + carry;
+    for (uint32_t t = t0; t < t1; t += 16) {
+      uint32_t c[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) c[j] = t + j < t1 ? table[(uint64_t)(t + j) * kRadix + tid] : 0u;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (t + j < t1) {
+          table[(uint64_t)(t + j) * kRadix + tid] = run;
+          run += c[j];
+        }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// scatter: one tile, ranked in LDS, written to its offsets
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const SortPlan* __restrict__ plan,
+                                                          const uint32_t* __restrict__ table, uint32_t pass,
+                                                          uint32_t n) {
+  // Reorder buffers; during ranking the key buffer holds the match masks.
+  __shared__ __align__(16) uint32_t s_keys[kTile];
+  __shared__ uint32_t s_rows[kTile];
+  __shared__ uint16_t s_wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave offsets
+  __shared__ uint32_t s_loff[kRadix];          // tile-local start of each digit
+  __shared__ uint32_t s_dbase[kRadix];         // global start minus tile-local start
+  __shared__ uint32_t s_scan[kWaves];
+  static_assert(kWaves * kRadix * 2 <= kTile, "match masks fit in the key buffer");
+  unsigned long long(*s_match)[kRadix] = reinterpret_cast<unsigned long long(*)[kRadix]>(&s_keys[0]);
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t active = plan->active;
+  if (!((active >> pass) & 1u)) return;
+  const PassIo io = pass_io(buf, active, pass);
+  const uint32_t shift = pass * kRadixBits;
+  const uint32_t tile = blockIdx.x;
+  const uint32_t base = tile * kTile;
+  const uint32_t tile_n = min((uint32_t)kTile, n - base);
+
+  for (int i = tid; i < kWaves * kRadix; i += kBlock) {
+    (&s_wcnt[0][0])[i] = 0;
+    (&s_match[0][0])[i] = 0ull;
+  }
+  // ---- load: wave w owns 64*kItems consecutive elements -----------------------
+  const uint32_t w = tid / 64, lane = lane_id();
+  const uint32_t wbase = w * 64 * kItems;
+  uint32_t key[kItems], row[kItems];
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t local = wbase + i * 64 + lane;
+    const uint32_t g = base + local;
+    const bool valid = local < tile_n;
+    key[i] = valid ? __builtin_nontemporal_load(io.src_keys + g) : 0u;
+    row[i] = valid ? (io.implicit_rows ? g : __builtin_nontemporal_load(io.src_rows + g)) : 0u;
   }
   __syncthreads();
 
-  // ---- per digit: counts, tile-local offsets, global offsets ---------------
+  // ---- rank inside the wave: peers = lanes with the same digit ----------------
+  const uint64_t lt = lanemask_lt();
+  uint32_t rank[kItems];
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const bool valid = wbase + i * 64 + lane < tile_n;
+    const uint32_t d = (key[i] >> shift) & (kRadix - 1);
+    uint32_t r = 0;
+    if (valid) {
+      atomicOr(&s_match[w][d], 1ull << lane);
+      const uint64_t peers = s_match[w][d];
+      const uint32_t below = (uint32_t)__popcll(peers & lt);
+      const uint32_t old = s_wcnt[w][d];
+      if (below == 0) {
+        s_wcnt[w][d] = (uint16_t)(old + (uint32_t)__popcll(peers));
+        s_match[w][d] = 0ull;
+      }
+      r = old + below;
+    }
+    rank[i] = r;
+  }
+  __syncthreads();
+
+  // ---- per digit: tile-local offsets and global destinations ------------------
   uint32_t tile_count = 0;
   if (tid < kRadix) {
 #pragma unroll
-    for (int ww = 0; ww < kPassWaves; ++ww) {
+    for (int ww = 0; ww < kWaves; ++ww) {
       const uint32_t c = s_wcnt[ww][tid];
-      s_wcnt[ww][tid] = tile_count;
+      s_wcnt[ww][tid] = (uint16_t)tile_count;
       tile_count += c;
     }
-    uint64_t* st = lb.status + (uint64_t)tile * kRadix + tid;
-    lb_publish(st, tile_count, lb.epoch, tile == 0 ? kLbInclusive : kLbAggregate);
   }
   uint32_t total;
-  const uint32_t loff = block_excl_scan<kPassBlock>(tid < kRadix ? tile_count : 0u, s_scan, &total);
-  __syncthreads();
-  const uint32_t hcount = tid < kRadix ? hist[pass * kRadix + tid] : 0u;
-  const uint32_t gstart = block_excl_scan<kPassBlock>(hcount, s_scan, &total);
+  const uint32_t loff = block_excl_scan<kBlock>(tid < kRadix ? tile_count : 0u, s_scan, &total);
   if (tid < kRadix) {
-    uint32_t prefix = 0;
-    if (tile != 0) {
-      prefix = lb_lookback_thread(lb.status, kRadix, tid, tile, lb.epoch);
-      lb_publish(lb.status + (uint64_t)tile * kRadix + tid, prefix + tile_count, lb.epoch, kLbInclusive);
-    }
     s_loff[tid] = loff;
-    s_dbase[tid] = gstart + prefix - loff;
+    s_dbase[tid] = table[(uint64_t)tile * kRadix + tid] - loff;
   }
   __syncthreads();
 
-  // ---- reorder the tile by digit in LDS -----------------------------------
+  // ---- reorder the tile by digit in LDS ---------------------------------------
 #pragma unroll
-  for (int i = 0; i < kPassItems; ++i) {
-    if (dig[i] != kNoDigit) {
-      const uint32_t pos = s_loff[dig[i]] + s_wcnt[w][dig[i]] + rank[i];
+  for (int i = 0; i < kItems; ++i) {
+    if (wbase + i * 64 + lane < tile_n) {
+      const uint32_t d = (key[i] >> shift) & (kRadix - 1);
+      const uint32_t pos = s_loff[d] + s_wcnt[w][d] + rank[i];
       s_keys[pos] = key[i];
       s_rows[pos] = row[i];
     }
   }
   __syncthreads();
 
-  // ---- write each digit's run to its global place --------------------------
+  // ---- write each digit's run to its global place ------------------------------
 #pragma unroll
-  for (int i = 0; i < kPassItems; ++i) {
-    const uint32_t p = i * kPassBlock + tid;
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t p = i * kBlock + tid;
     if (p < tile_n) {
       const uint32_t k = s_keys[p];
       const uint32_t g = s_dbase[(k >> shift) & (kRadix - 1)] + p;
-      dst_keys[g] = k;
-      dst_rows[g] = s_rows[p];
+      io.dst_keys[g] = k;
+      io.dst_rows[g] = s_rows[p];
     }
   }
 }
@@ -239,18 +369,9 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
   if (n == 0) return kOk;
   if (!keys || !skeys || !srows) return env.fail(kErrArg, "radix_sort: null buffer");
   if (n >= (1ull << 31)) return env.fail(kErrArg, "radix_sort: n must be below 2^31");
-  LookbackArena* ar = env.arena();
-  uint32_t* hist = ar->hist[ar->hist_turn];
-  uint32_t* hist_next = ar->hist[ar->hist_turn ^ 1u];
-  ar->hist_turn ^= 1u;
-
-  uint64_t hgrid = (n + 4095) / 4096;
-  if (hgrid > 1024) hgrid = 1024;
-  env.prof_begin("radix_hist");
-  k_radix_hist<<<dim3((uint32_t)hgrid), dim3(kHistBlock), 0, env.stream()>>>(keys, n, hist, hist_next);
-  env.prof_end("radix_hist");
-  int rc = check_launch(env, "radix_hist launch");
-  if (rc) return rc;
+  SortPlan* plan = reinterpret_cast<SortPlan*>(env.arena()->plan);
+  const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
+  const uint32_t nn = (uint32_t)n;
 
   PassBuffers buf;
   buf.keys_in = keys;
@@ -259,15 +380,27 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
   buf.rows_a = srows;
   buf.keys_b = static_cast<uint32_t*>(env.scratch(n * 4));
   buf.rows_b = static_cast<uint32_t*>(env.scratch(n * 4));
-  if (!buf.keys_b || !buf.rows_b) return env.fail(kErrOom, "radix_sort: scratch buffers");
-  const uint32_t tiles = (uint32_t)((n + kPassTile - 1) / kPassTile);
+  uint32_t* table = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * kRadix * 4));
+  const int cap = coresident_blocks(reinterpret_cast<const void*>(&k_radix_count<true>), kBlock);
+  if (cap <= 0) return env.fail(kErrLaunch, "radix_sort: cooperative launch not available");
+  const uint32_t G = (uint32_t)std::min<int>(cap, (int)ntiles);
+  uint32_t* part = static_cast<uint32_t*>(env.scratch((uint64_t)G * kPartStride * 4));
+  if (!buf.keys_b || !buf.rows_b || !table || !part) return env.fail(kErrOom, "radix_sort: scratch buffers");
+
   for (uint32_t pass = 0; pass < (uint32_t)kPasses; ++pass) {
-    LbArgs lb;
-    if (!env.lookback((uint64_t)tiles * kRadix, tiles, &lb)) return env.fail(kErrOom, "radix_sort: look-back");
-    env.prof_begin("radix_pass");
-    k_radix_pass<<<dim3(tiles), dim3(kPassBlock), 0, env.stream()>>>(buf, hist, pass, (uint32_t)n, lb);
-    env.prof_end("radix_pass");
-    rc = check_launch(env, "radix_pass launch");
+    int rc;
+    if (pass == 0)
+      rc = launch_persistent(env, "radix_count0", k_radix_count<true>, G, (uint32_t)kBlock, buf, plan, table, part,
+                             pass, nn);
+    else
+      rc = launch_persistent(env, "radix_count", k_radix_count<false>, G, (uint32_t)kBlock, buf, plan, table, part,
+                             pass, nn);
+    if (rc) return rc;
+    env.prof_begin("radix_scatter");
+    k_radix_scatter<<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(buf, static_cast<const SortPlan*>(plan), table,
+                                                                     pass, nn);
+    env.prof_end("radix_scatter");
+    rc = check_launch(env, "radix_scatter launch");
     if (rc) return rc;
   }
   return kOk;

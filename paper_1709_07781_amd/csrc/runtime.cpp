@@ -25,6 +25,7 @@ int set_error(int code, const std::string& msg) {
 }
 
 static int hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();  // a handled failure must not stay pending for later HIP users (torch)
   return set_error(KA_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
@@ -73,7 +74,10 @@ int System::ensure_init() {
   };
   int count = 0;
   hipError_t e = hipGetDeviceCount(&count);
-  if (e != hipSuccess || count == 0) return fail(KA_E_DEVICE, "no HIP device available");
+  if (e != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    return fail(KA_E_DEVICE, "no HIP device available");
+  }
   if (cfg.device < 0 || cfg.device >= count) return fail(KA_E_DEVICE, "device ordinal out of range");
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, cfg.device) != hipSuccess) return fail(KA_E_DEVICE, "device query failed");
@@ -97,11 +101,13 @@ int System::ensure_init() {
   // Per-stream look-back arenas: ticket counter and two zeroed histograms.
   for (auto& sc : streams) {
     void* p = nullptr;
-    if (hipMalloc(&p, 256 + 2 * 4096) != hipSuccess) return fail(KA_E_OOM, "arena allocation failed");
-    if (hipMemset(p, 0, 256 + 2 * 4096) != hipSuccess) return fail(KA_E_DEVICE, "arena clear failed");
-    sc->arena.ticket = static_cast<unsigned long long*>(p);
-    sc->arena.hist[0] = reinterpret_cast<uint32_t*>(static_cast<char*>(p) + 256);
-    sc->arena.hist[1] = reinterpret_cast<uint32_t*>(static_cast<char*>(p) + 256 + 4096);
+    if (hipMalloc(&p, kArenaBytes) != hipSuccess) return fail(KA_E_OOM, "arena allocation failed");
+    if (hipMemset(p, 0, kArenaBytes) != hipSuccess) return fail(KA_E_DEVICE, "arena clear failed");
+    char* b = static_cast<char*>(p);
+    sc->arena.ticket = reinterpret_cast<unsigned long long*>(b);
+    sc->arena.hist[0] = reinterpret_cast<uint32_t*>(b + kArenaTicketBytes);
+    sc->arena.hist[1] = reinterpret_cast<uint32_t*>(b + kArenaTicketBytes + kArenaHistBytes);
+    sc->arena.plan = b + kArenaTicketBytes + 2 * kArenaHistBytes;
   }
   init_rc = KA_OK;
   return KA_OK;
@@ -156,7 +162,10 @@ void Pool::poll_deferred_locked() {
     Deferred& d = deferred_[i];
     bool done = true;
     for (hipEvent_t e : d.events)
-      if (hipEventQuery(e) != hipSuccess) done = false;
+      if (hipEventQuery(e) != hipSuccess) {
+        (void)hipGetLastError();  // "not ready" must not stay pending
+        done = false;
+      }
     if (done) {
       for (hipEvent_t e : d.events) sys_->put_event(e);
       free_[d.home].emplace(d.bytes, d.p);
@@ -255,7 +264,9 @@ void* HostStage::get(System* sys, uint64_t bytes) {
   const uint64_t c = Pool::size_class(bytes);
   std::lock_guard<std::mutex> g(mu_);
   for (size_t i = 0; i < busy_.size();) {
-    if (hipEventQuery(busy_[i].done) == hipSuccess) {
+    const hipError_t q = hipEventQuery(busy_[i].done);
+    if (q != hipSuccess) (void)hipGetLastError();  // "not ready" must not stay pending
+    if (q == hipSuccess) {
       sys->put_event(busy_[i].done);
       free_.emplace(busy_[i].bytes, busy_[i].p);
       busy_[i] = busy_.back();
@@ -271,7 +282,10 @@ void* HostStage::get(System* sys, uint64_t bytes) {
     return p;
   }
   void* p = nullptr;
-  if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) return nullptr;
+  if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
   sizes_[p] = c;
   return p;
 }
@@ -541,8 +555,17 @@ static int from_c_values(const ka_value* vals, uint32_t n, Msg& out) {
   return KA_OK;
 }
 
-// Applies a mapping function: `m` is replaced by its result.
+// Applies a mapping function: `m` is replaced by its result.  Value results
+// still on the device are read back first: a mapping function sees values as
+// host data (Sec. 3.4).
 static int apply_map(ka_map_fn fn, void* ud, Msg& m) {
+  for (auto& v : m) {
+    const int rc = materialize(v);
+    if (rc) {
+      msg_clear(m);
+      return rc;
+    }
+  }
   std::vector<ka_value> in;
   to_c_values(m, in);
   const uint32_t cap = 64;
@@ -1030,7 +1053,10 @@ KA_API int ka_program_load(ka_system* sys, const char* path, ka_program** out) {
   if (rc) return rc;
   hipModule_t m = nullptr;
   hipError_t e = hipModuleLoad(&m, path);
-  if (e != hipSuccess) return set_error(KA_E_ARG, std::string("cannot load code object ") + path);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(KA_E_ARG, std::string("cannot load code object ") + path);
+  }
   ka_program* p = new ka_program();
   p->sys = sys;
   sys->retain();
@@ -1086,7 +1112,10 @@ KA_API int ka_spawn(ka_system* sys, ka_program* prog, const char* kernel, const 
     int rc = sys->ensure_init();
     if (rc) return rc;
     hipError_t e = hipModuleGetFunction(&fn, prog->module, kernel);
-    if (e != hipSuccess) return set_error(KA_E_NOKERNEL, std::string("no kernel named ") + kernel + " in module");
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(KA_E_NOKERNEL, std::string("no kernel named ") + kernel + " in module");
+    }
   }
   std::vector<SigArg> s(nargs);
   for (uint32_t i = 0; i < nargs; ++i) {
@@ -1249,6 +1278,7 @@ static int ticket_wait(ka_ticket* t, int64_t timeout_us) {
       return KA_OK;
     }
     if (e != hipErrorNotReady) return hip_fail(e, "waiting for the response");
+    (void)hipGetLastError();
     if (std::chrono::steady_clock::now() >= until) return set_error(KA_E_TIMEOUT, "response not ready");
     std::this_thread::yield();
   }
