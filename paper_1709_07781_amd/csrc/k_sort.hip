@@ -35,9 +35,15 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kPasses = 32 / kRadixBits;
 
-constexpr int kBlock = 1024;
+#ifndef KA_SORT_BLOCK
+#define KA_SORT_BLOCK 1024
+#endif
+#ifndef KA_SORT_ITEMS
+#define KA_SORT_ITEMS 8
+#endif
+constexpr int kBlock = KA_SORT_BLOCK;
 constexpr int kWaves = kBlock / 64;
-constexpr int kItems = 8;
+constexpr int kItems = KA_SORT_ITEMS;
 constexpr int kTile = kBlock * kItems;  // 8192 keys per tile
 constexpr int kCountVecs = kTile / 4 / kBlock;
 
@@ -140,12 +146,14 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(PassBuffers buf, SortPla
 
   if (tid < kRadix) s_acc[tid] = 0;
   uint32_t kor = 0, kand = ~0u;
-  uint32_t cur[kCountVecs][4];
+  // Two tiles of keys are in flight while one is counted.
+  uint32_t cur[kCountVecs][4], nxt[kCountVecs][4];
   fetch(t0, cur);
+  fetch(t0 + 1, nxt);
   for (uint32_t t = t0; t < t1; ++t) {
     for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_tile[0][0])[i] = 0;
-    uint32_t nxt[kCountVecs][4];
-    fetch(t + 1, nxt);  // in flight while this tile is counted
+    uint32_t nxt2[kCountVecs][4];
+    fetch(t + 2, nxt2);
     __syncthreads();
     const uint32_t len = min((uint32_t)kTile, n - t * kTile);
 #pragma unroll
@@ -170,7 +178,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(PassBuffers buf, SortPla
 #pragma unroll
     for (int j = 0; j < kCountVecs; ++j)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) cur[j][c] = nxt[j][c];
+      for (int c = 0; c < 4; ++c) {
+        cur[j][c] = nxt[j][c];
+        nxt[j][c] = nxt2[j][c];
+      }
     __syncthreads();  // s_tile is cleared again for the next tile
   }
   uint32_t* mine = part + (uint64_t)b * kPartStride;
@@ -205,20 +216,27 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(PassBuffers buf, SortPla
   // the loads are independent and unrolled so that many are in flight.
   uint32_t tot = 0, carry = 0;
   {
-    const uint32_t d = tid & (kRadix - 1), q = tid >> 8;
+    constexpr uint32_t kQ = kBlock / kRadix;  // work-items per digit
+    static_assert(2 * kQ <= kWaves, "quarter sums fit in s_tile");
+    const uint32_t d = tid & (kRadix - 1), q = tid / kRadix;
 #pragma unroll 8
-    for (uint32_t bb = q; bb < G; bb += kBlock / kRadix) {
+    for (uint32_t bb = q; bb < G; bb += kQ) {
       const uint32_t c = part[(uint64_t)bb * kPartStride + d];
       tot += c;
       carry += bb < b ? c : 0u;
     }
     __syncthreads();
-    s_tile[q][d] = tot;          // s_tile is free again: reuse it for the four quarters
-    s_tile[4 + q][d] = carry;
+    s_tile[q][d] = tot;  // s_tile is free again: reuse it for the partial sums
+    s_tile[kQ + q][d] = carry;
     __syncthreads();
     if (tid < kRadix) {
-      tot = s_tile[0][tid] + s_tile[1][tid] + s_tile[2][tid] + s_tile[3][tid];
-      carry = s_tile[4][tid] + s_tile[5][tid] + s_tile[6][tid] + s_tile[7][tid];
+      tot = 0;
+      carry = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < kQ; ++k) {
+        tot += s_tile[k][tid];
+        carry += s_tile[kQ + k][tid];
+      }
     }
   }
   uint32_t total;

@@ -24,7 +24,10 @@ namespace ka {
 namespace {
 
 constexpr int kEncBlock = 256;
-constexpr int kEncItems = 16;
+#ifndef KA_ENC_ITEMS
+#define KA_ENC_ITEMS 16
+#endif
+constexpr int kEncItems = KA_ENC_ITEMS;
 constexpr int kEncTile = kEncBlock * kEncItems;  // 4096 pairs
 constexpr int kLook = 32;                        // >= 30 elements of look-ahead
 constexpr int kStage = kEncTile + 1 + kLook;     // one element of look-behind
