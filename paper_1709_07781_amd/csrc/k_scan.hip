@@ -109,8 +109,7 @@ __device__ __forceinline__ void load_tile(const uint32_t* __restrict__ in, uint6
 // Persistent: work-group b handles tiles b, b + G, b + 2G, ... (G = grid);
 // the next tile's loads are issued before the current tile's look-back.
 template <bool kVec>
-__global__ __launch_bounds__(kScanBlock) void k_exclusive_scan_u32(const uint32_t* __restrict__ in,
-                                                                   uint32_t* __restrict__ out, uint64_t n_cap,
+__global__ __launch_bounds__(kScanBlock) void k_exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_cap,
                                                                    const uint64_t* __restrict__ d_n, LbArgs lb) {
   __shared__ uint32_t s_prefix;
   __shared__ uint32_t s_wave[kScanRounds][kWaves];
@@ -204,6 +203,8 @@ __global__ __launch_bounds__(kScanBlock) void k_compact_nonzero_u32(const uint32
 
 }  // namespace
 
+// in == out is allowed: each element is read by the work-group that writes it,
+// before it is written.
 int launch_exclusive_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t n_cap, const uint64_t* d_n) {
   if (n_cap == 0) return kOk;
   if (!in || !out) return env.fail(kErrArg, "exclusive_scan_u32: null buffer");

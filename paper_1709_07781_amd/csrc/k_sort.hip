@@ -3,27 +3,25 @@
 // position, then sort by value; Sec. 4.2 sorts with a radix sort).
 //
 // 8-bit digits, up to four passes, each a reduce-then-scan over tiles of
-// kTile keys -- no work-group ever waits for another one's tile:
-//  * k_radix_count (cooperative launch, a few hundred work-groups, each owning
-//    a contiguous range of tiles) counts every tile's digits into a table and
-//    sums its range; after one grid barrier each work-group turns its tiles'
-//    counts into global offsets: the digit's start (exclusive prefix over
-//    digits of the digit totals) plus the counts of all earlier tiles.  The
-//    pass-0 instance also forms the OR and the AND of all keys for the sort
-//    plan: a pass whose digit is the same in every key (equal in the OR and
-//    the AND) is the identity of a stable sort and is skipped, so 16-bit keys
-//    cost two passes.
+// kTile keys -- no work-group ever waits for another one:
+//  * k_radix_upsweep (one work-group per tile) counts the tile's digits into a
+//    digit-major table; the pass-0 instance also records the OR and the AND of
+//    the tile's keys, from which k_radix_plan forms the sort plan: a pass whose
+//    digit is the same in every key (equal in the OR and the AND) is the
+//    identity of a stable sort and is skipped, so 16-bit keys cost two passes.
+//  * the exclusive scan of the table (the look-back scan kernel, in place)
+//    turns every count into the output position of the tile's first key with
+//    that digit.
 //  * k_radix_scatter (one work-group per tile) ranks its keys by digit inside
 //    each wave with an LDS match (every lane ORs its lane bit into a 64-bit
 //    mask per digit and reads back the mask of its digit, so equal keys keep
 //    their order), reorders the tile by digit in LDS and writes each digit's
 //    run to its offset from the table, consecutive work-items writing
 //    consecutive addresses.
+// Tiles are taken in an XCD-aware order (see xcd_tile).
 // The first active pass reads the input (and makes row ids 0..n-1 when no rows
 // are given), later ones read the previous active pass's output, and the last
 // active pass writes the caller's buffers.
-#include <hip/hip_cooperative_groups.h>
-
 #include <algorithm>
 
 #include "common.hpp"
@@ -41,17 +39,21 @@ constexpr int kPasses = 32 / kRadixBits;
 #ifndef KA_SORT_ITEMS
 #define KA_SORT_ITEMS 8
 #endif
+#ifndef KA_XCD_MAP
+#define KA_XCD_MAP 1
+#endif
 constexpr int kBlock = KA_SORT_BLOCK;
 constexpr int kWaves = kBlock / 64;
 constexpr int kItems = KA_SORT_ITEMS;
 constexpr int kTile = kBlock * kItems;  // 8192 keys per tile
-constexpr int kCountVecs = kTile / 4 / kBlock;
 
 }  // namespace
 
 // The sort plan, written by the pass-0 count kernel.
 struct SortPlan {
-  uint32_t active;  // bit p: pass p moves data
+  uint32_t active;               // bit p: pass p moves data
+  uint32_t pad;
+  uint64_t scan_len[kPasses];    // entries of pass p's table scan (0 when skipped)
 };
 static_assert(sizeof(SortPlan) <= kSortPlanBytes, "plan storage");
 
@@ -100,95 +102,85 @@ __device__ __forceinline__ void lds_add_aggregated(uint32_t* bins, uint32_t d, b
   if (valid && d != d0) atomicAdd(&bins[d], 1u);
 }
 
-// ---------------------------------------------------------------------------------
-// count: per-tile digit counts -> per-tile digit offsets
-// ---------------------------------------------------------------------------------
-constexpr int kPartStride = kRadix + 2;  // per work-group: digit counts, then OR and AND of its keys
+// Tile of work-group b under an XCD-aware order.  Work-groups are dispatched
+// round-robin over the 8 XCDs (b mod 8), each with its own L2; this gives XCD x
+// the contiguous tile range [x*q + min(x, r), ...) of q or q + 1 tiles (q =
+// ntiles / 8, r = ntiles mod 8), so neighbouring tiles -- whose output runs meet
+// in the same cache lines -- are handled by the same L2.  A bijection on
+// [0, ntiles) for every ntiles.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles) {
+#if KA_XCD_MAP
+  const uint32_t x = b & 7u, i = b >> 3, q = ntiles >> 3, r = ntiles & 7u;
+  return x * q + min(x, r) + i;
+#else
+  (void)ntiles;
+  return b;
+#endif
+}
 
+// ---------------------------------------------------------------------------------
+// upsweep: digit counts of one tile into the digit-major table
+// ---------------------------------------------------------------------------------
+constexpr int kUpBlock = kRadix;                  // one work-item per digit when the counts are written
+constexpr int kUpWaves = kUpBlock / 64;
+constexpr int kUpVecs = kTile / 4 / kUpBlock;     // 16-byte loads per work-item
+
+// table[d * ntiles + tile] = number of keys of the tile with digit d.  The
+// exclusive scan of the table in this digit-major order is, entry by entry,
+// the position in the pass's output of the tile's first key with digit d.
+// All of a work-item's loads are issued before the first key is counted; the
+// pass-0 instance also writes the OR and the AND of the tile's keys.
 template <bool kFirst>
-__global__ __launch_bounds__(kBlock) void k_radix_count(PassBuffers buf, SortPlan* __restrict__ plan,
-                                                        uint32_t* __restrict__ table, uint32_t* __restrict__ part,
-                                                        uint32_t pass, uint32_t n) {
-  __shared__ uint32_t s_tile[kWaves][kRadix];  // per-wave counts of the current tile
-  __shared__ uint32_t s_acc[kRadix];           // this work-group's counts over its tiles
-  __shared__ uint32_t s_scan[kWaves];
-  __shared__ uint32_t s_or[kWaves], s_and[kWaves];
+__global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, const SortPlan* __restrict__ plan,
+                                                            uint32_t* __restrict__ table, uint32_t* __restrict__ orand,
+                                                            uint32_t pass, uint32_t n) {
+  __shared__ uint32_t s_hist[kUpWaves][kRadix];
+  __shared__ uint32_t s_or[kUpWaves], s_and[kUpWaves];
   const uint32_t tid = threadIdx.x, w = tid / 64;
-
-  uint32_t active = 1u;
+  const uint32_t* keys = buf.keys_in;
   if (!kFirst) {
-    active = plan->active;
-    if (!((active >> pass) & 1u)) return;  // uniform: no work-group reaches the grid barrier
+    const uint32_t active = plan->active;
+    if (!((active >> pass) & 1u)) return;  // uniform over the grid
+    keys = pass_io(buf, active, pass).src_keys;
   }
-  const uint32_t* keys = kFirst ? buf.keys_in : pass_io(buf, active, pass).src_keys;
+  const uint32_t ntiles = gridDim.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+  const uint32_t base = tile * kTile;
+  const uint32_t len = min((uint32_t)kTile, n - base);
   const uint32_t shift = pass * kRadixBits;
-  const uint32_t ntiles = (n + kTile - 1) / kTile;
-  const uint32_t G = gridDim.x, b = blockIdx.x;
-  const uint32_t t0 = (uint32_t)((uint64_t)b * ntiles / G), t1 = (uint32_t)((uint64_t)(b + 1) * ntiles / G);
-  const bool vec = (reinterpret_cast<uintptr_t>(keys) & 15u) == 0;
 
-  // Keys of a tile: element 4 (j * kBlock + tid) + c in slot (j, c).
-  auto fetch = [&](uint32_t t, uint32_t (&k)[kCountVecs][4]) {
-    const uint32_t base = t * kTile;
-    const uint32_t len = t < t1 ? min((uint32_t)kTile, n - base) : 0u;
+  // Key 4 (j * kUpBlock + tid) + c of the tile in k[j][c].
+  uint32_t k[kUpVecs][4];
+  if (len == (uint32_t)kTile && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
 #pragma unroll
-    for (int j = 0; j < kCountVecs; ++j) {
-      const uint32_t e = 4 * (j * kBlock + tid);
-      if (vec && e + 4 <= len) {
-        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + base + e));
-        k[j][0] = v.x, k[j][1] = v.y, k[j][2] = v.z, k[j][3] = v.w;
-      } else {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) k[j][c] = e + c < len ? keys[base + e + c] : 0u;
-      }
+    for (int j = 0; j < kUpVecs; ++j) {
+      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + base) + j * kUpBlock + tid);
+      k[j][0] = v.x, k[j][1] = v.y, k[j][2] = v.z, k[j][3] = v.w;
     }
-  };
-
-  if (tid < kRadix) s_acc[tid] = 0;
-  uint32_t kor = 0, kand = ~0u;
-  // Two tiles of keys are in flight while one is counted.
-  uint32_t cur[kCountVecs][4], nxt[kCountVecs][4];
-  fetch(t0, cur);
-  fetch(t0 + 1, nxt);
-  for (uint32_t t = t0; t < t1; ++t) {
-    for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_tile[0][0])[i] = 0;
-    uint32_t nxt2[kCountVecs][4];
-    fetch(t + 2, nxt2);
-    __syncthreads();
-    const uint32_t len = min((uint32_t)kTile, n - t * kTile);
+  } else {
 #pragma unroll
-    for (int j = 0; j < kCountVecs; ++j)
+    for (int j = 0; j < kUpVecs; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const bool valid = 4 * (j * kBlock + tid) + c < len;
-        lds_add_aggregated(s_tile[w], (cur[j][c] >> shift) & (kRadix - 1), valid);
-        if (kFirst && valid) {
-          kor |= cur[j][c];
-          kand &= cur[j][c];
-        }
+        const uint32_t e = 4 * (j * kUpBlock + tid) + c;
+        k[j][c] = e < len ? keys[base + e] : 0u;
       }
-    __syncthreads();
-    if (tid < kRadix) {
-      uint32_t c = 0;
-#pragma unroll
-      for (int ww = 0; ww < kWaves; ++ww) c += s_tile[ww][tid];
-      table[(uint64_t)t * kRadix + tid] = c;
-      s_acc[tid] += c;
-    }
-#pragma unroll
-    for (int j = 0; j < kCountVecs; ++j)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        cur[j][c] = nxt[j][c];
-        nxt[j][c] = nxt2[j][c];
-      }
-    __syncthreads();  // s_tile is cleared again for the next tile
   }
-  uint32_t* mine = part + (uint64_t)b * kPartStride;
-  if (tid < kRadix) mine[tid] = s_acc[tid];
+  for (int i = tid; i < kUpWaves * kRadix; i += kUpBlock) (&s_hist[0][0])[i] = 0;
+  __syncthreads();
+  uint32_t kor = 0, kand = ~0u;
+#pragma unroll
+  for (int j = 0; j < kUpVecs; ++j)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bool valid = 4 * (j * kUpBlock + tid) + c < len;
+      lds_add_aggregated(s_hist[w], (k[j][c] >> shift) & (kRadix - 1), valid);
+      if (kFirst && valid) {
+        kor |= k[j][c];
+        kand &= k[j][c];
+      }
+    }
   if (kFirst) {
-    // OR and AND of this work-group's keys: a pass moves data unless its digit
-    // is the same in every key, i.e. the same in the OR and the AND.
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       kor |= (uint32_t)__shfl_xor((int)kor, off);
@@ -198,54 +190,51 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(PassBuffers buf, SortPla
       s_or[w] = kor;
       s_and[w] = kand;
     }
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t o = 0, a = ~0u;
-      for (int ww = 0; ww < kWaves; ++ww) {
-        o |= s_or[ww];
-        a &= s_and[ww];
-      }
-      mine[kRadix] = o;
-      mine[kRadix + 1] = a;
-    }
   }
-  cooperative_groups::this_grid().sync();
-
-  // ---- every work-group: the start of its range for each digit ------------------
-  // Work-item (q, d) sums the partials of every fourth work-group for digit d;
-  // the loads are independent and unrolled so that many are in flight.
-  uint32_t tot = 0, carry = 0;
-  {
-    constexpr uint32_t kQ = kBlock / kRadix;  // work-items per digit
-    static_assert(2 * kQ <= kWaves, "quarter sums fit in s_tile");
-    const uint32_t d = tid & (kRadix - 1), q = tid / kRadix;
-#pragma unroll 8
-    for (uint32_t bb = q; bb < G; bb += kQ) {
-      const uint32_t c = part[(uint64_t)bb * kPartStride + d];
-      tot += c;
-      carry += bb < b ? c : 0u;
-    }
-    __syncthreads();
-    s_tile[q][d] = tot;  // s_tile is free again: reuse it for the partial sums
-    s_tile[kQ + q][d] = carry;
-    __syncthreads();
-    if (tid < kRadix) {
-      tot = 0;
-      carry = 0;
+  __syncthreads();
+  uint32_t c = 0;
 #pragma unroll
-      for (uint32_t k = 0; k < kQ; ++k) {
-        tot += s_tile[k][tid];
-        carry += s_tile[kQ + k][tid];
-      }
-    }
-  }
-  uint32_t total;
-  const uint32_t start = block_excl_scan<kBlock>(tid < kRadix ? tot : 0u, s_scan, &total);
-  if (kFirst && b == 0 && tid == 0) {
+  for (int ww = 0; ww < kUpWaves; ++ww) c += s_hist[ww][tid];
+  table[(uint64_t)tid * ntiles + tile] = c;
+  if (kFirst && tid == 0) {
     uint32_t o = 0, a = ~0u;
-    for (uint32_t bb = 0; bb < G; ++bb) {
-      o |= part[(uint64_t)bb * kPartStride + kRadix];
-      a &= part[(uint64_t)bb * kPartStride + kRadix + 1];
+#pragma unroll
+    for (int ww = 0; ww < kUpWaves; ++ww) {
+      o |= s_or[ww];
+      a &= s_and[ww];
+    }
+    orand[2 * tile] = o;
+    orand[2 * tile + 1] = a;
+  }
+}
+
+// The sort plan from the OR and the AND of every tile's keys: a pass moves
+// data unless its digit is the same in every key, i.e. the same in the OR and
+// the AND.  Also the length of each pass's table scan: the full table for an
+// active pass, 0 (nothing to scan) for a skipped one.  One work-group.
+constexpr int kPlanBlock = 1024;
+__global__ __launch_bounds__(kPlanBlock) void k_radix_plan(const uint32_t* __restrict__ orand, uint32_t ntiles,
+                                                           SortPlan* __restrict__ plan) {
+  __shared__ uint32_t s_or[kPlanBlock / 64], s_and[kPlanBlock / 64];
+  uint32_t o = 0, a = ~0u;
+  for (uint32_t t = threadIdx.x; t < ntiles; t += kPlanBlock) {
+    o |= orand[2 * t];
+    a &= orand[2 * t + 1];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    o |= (uint32_t)__shfl_xor((int)o, off);
+    a &= (uint32_t)__shfl_xor((int)a, off);
+  }
+  if (lane_id() == 0) {
+    s_or[threadIdx.x / 64] = o;
+    s_and[threadIdx.x / 64] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int ww = 1; ww < kPlanBlock / 64; ++ww) {
+      o |= s_or[ww];
+      a &= s_and[ww];
     }
     const uint32_t diff = o ^ a;
     uint32_t act = 0;
@@ -253,21 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(PassBuffers buf, SortPla
       if ((diff >> (p * kRadixBits)) & (kRadix - 1)) act |= 1u << p;
     if (act == 0) act = 1u << (kPasses - 1);  // all keys equal: one pass still moves them
     plan->active = act;
-  }
-  // ---- counts of this work-group's tiles -> offsets (16 tiles per round) -----------
-  if (tid < kRadix) {
-    uint32_t run = start + carry;
-    for (uint32_t t = t0; t < t1; t += 16) {
-      uint32_t c[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) c[j] = t + j < t1 ? table[(uint64_t)(t + j) * kRadix + tid] : 0u;
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (t + j < t1) {
-          table[(uint64_t)(t + j) * kRadix + tid] = run;
-          run += c[j];
-        }
-    }
+    for (int p = 0; p < kPasses; ++p) plan->scan_len[p] = ((act >> p) & 1u) ? (uint64_t)ntiles * kRadix : 0u;
   }
 }
 
@@ -292,7 +267,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   if (!((active >> pass) & 1u)) return;
   const PassIo io = pass_io(buf, active, pass);
   const uint32_t shift = pass * kRadixBits;
-  const uint32_t tile = blockIdx.x;
+  const uint32_t ntiles = gridDim.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
   const uint32_t base = tile * kTile;
   const uint32_t tile_n = min((uint32_t)kTile, n - base);
 
@@ -304,13 +280,26 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   const uint32_t w = tid / 64, lane = lane_id();
   const uint32_t wbase = w * 64 * kItems;
   uint32_t key[kItems], row[kItems];
+  if (tile_n == (uint32_t)kTile) {  // uniform: every load of a full tile is issued unconditionally
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    const uint32_t local = wbase + i * 64 + lane;
-    const uint32_t g = base + local;
-    const bool valid = local < tile_n;
-    key[i] = valid ? __builtin_nontemporal_load(io.src_keys + g) : 0u;
-    row[i] = valid ? (io.implicit_rows ? g : __builtin_nontemporal_load(io.src_rows + g)) : 0u;
+    for (int i = 0; i < kItems; ++i) key[i] = __builtin_nontemporal_load(io.src_keys + base + wbase + i * 64 + lane);
+    if (io.implicit_rows) {
+#pragma unroll
+      for (int i = 0; i < kItems; ++i) row[i] = base + wbase + i * 64 + lane;
+    } else {
+#pragma unroll
+      for (int i = 0; i < kItems; ++i)
+        row[i] = __builtin_nontemporal_load(io.src_rows + base + wbase + i * 64 + lane);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const uint32_t local = wbase + i * 64 + lane;
+      const uint32_t g = base + local;
+      const bool valid = local < tile_n;
+      key[i] = valid ? io.src_keys[g] : 0u;
+      row[i] = valid ? (io.implicit_rows ? g : io.src_rows[g]) : 0u;
+    }
   }
   __syncthreads();
 
@@ -351,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   const uint32_t loff = block_excl_scan<kBlock>(tid < kRadix ? tile_count : 0u, s_scan, &total);
   if (tid < kRadix) {
     s_loff[tid] = loff;
-    s_dbase[tid] = table[(uint64_t)tile * kRadix + tid] - loff;
+    s_dbase[tid] = table[(uint64_t)tid * ntiles + tile] - loff;
   }
   __syncthreads();
 
@@ -399,20 +388,31 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
   buf.keys_b = static_cast<uint32_t*>(env.scratch(n * 4));
   buf.rows_b = static_cast<uint32_t*>(env.scratch(n * 4));
   uint32_t* table = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * kRadix * 4));
-  const int cap = coresident_blocks(reinterpret_cast<const void*>(&k_radix_count<true>), kBlock);
-  if (cap <= 0) return env.fail(kErrLaunch, "radix_sort: cooperative launch not available");
-  const uint32_t G = (uint32_t)std::min<int>(cap, (int)ntiles);
-  uint32_t* part = static_cast<uint32_t*>(env.scratch((uint64_t)G * kPartStride * 4));
-  if (!buf.keys_b || !buf.rows_b || !table || !part) return env.fail(kErrOom, "radix_sort: scratch buffers");
+  uint32_t* orand = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * 2 * 4));
+  if (!buf.keys_b || !buf.rows_b || !table || !orand) return env.fail(kErrOom, "radix_sort: scratch buffers");
 
   for (uint32_t pass = 0; pass < (uint32_t)kPasses; ++pass) {
-    int rc;
-    if (pass == 0)
-      rc = launch_persistent(env, "radix_count0", k_radix_count<true>, G, (uint32_t)kBlock, buf, plan, table, part,
-                             pass, nn);
-    else
-      rc = launch_persistent(env, "radix_count", k_radix_count<false>, G, (uint32_t)kBlock, buf, plan, table, part,
-                             pass, nn);
+    if (pass == 0) {
+      env.prof_begin("radix_upsweep0");
+      k_radix_upsweep<true><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand, pass, nn);
+      env.prof_end("radix_upsweep0");
+      int rc = check_launch(env, "radix_upsweep launch");
+      if (rc) return rc;
+      env.prof_begin("radix_plan");
+      k_radix_plan<<<dim3(1), dim3(kPlanBlock), 0, env.stream()>>>(orand, ntiles, plan);
+      env.prof_end("radix_plan");
+      rc = check_launch(env, "radix_plan launch");
+      if (rc) return rc;
+    } else {
+      env.prof_begin("radix_upsweep");
+      k_radix_upsweep<false><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand, pass, nn);
+      env.prof_end("radix_upsweep");
+      int rc = check_launch(env, "radix_upsweep launch");
+      if (rc) return rc;
+    }
+    // Offsets: exclusive scan of the digit-major table, in place; the plan
+    // gives a skipped pass a scan of length 0.
+    int rc = launch_exclusive_scan(env, table, table, (uint64_t)ntiles * kRadix, &plan->scan_len[pass]);
     if (rc) return rc;
     env.prof_begin("radix_scatter");
     k_radix_scatter<<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(buf, static_cast<const SortPlan*>(plan), table,
