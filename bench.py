@@ -9,8 +9,10 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -21,6 +23,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+SORT_KERNELS = ("radix_upsweep0", "radix_plan", "radix_upsweep", "exclusive_scan_u32", "radix_scatter")
+ENCODE_KERNELS = ("wah_count", "wah_offsets", "wah_write")
+KERNELS = SORT_KERNELS + ENCODE_KERNELS
+# Counter summary of the dominant kernel (FETCH_SIZE / WRITE_SIZE runs of this
+# script under rocprofv3), valid while the kernel's sources hash to what it names.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "radix_scatter_zipf_2p26_traffic.md")
+SCATTER_SOURCES = ("paper_1709_07781_amd/csrc/k_sort.hip", "paper_1709_07781_amd/csrc/common.hpp")
 METRIC = "input elements/s (and % HBM roofline) of composed pipeline; p50/p99 latency served"
 
 
@@ -41,6 +50,32 @@ def active_passes(v: np.ndarray) -> tuple[int, int]:
     return len(act), act[0]
 
 
+def sources_digest(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n_log2: int):
+    """HBM bytes per launch of k_radix_scatter from the committed counter
+    summary, or None when there is none for this size or the kernel's sources
+    changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic_json: (\{.*\})$", text, re.M)
+    if not m:
+        return None
+    t = json.loads(m.group(1))
+    if t.get("sources_sha256") != sources_digest(SCATTER_SOURCES) or t.get("n_log2") != n_log2:
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +85,9 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run the in-place affine kernel over 2^n words 3 times "
+                         "(a plain copy of known size, for scaling the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the pipeline is not sharded "
@@ -108,20 +146,36 @@ def main() -> int:
     dev_ms = ev0.elapsed_time(ev1)
     ms_per_step = dev_ms / args.steps
 
-    prof = {k: sess.profile(k) for k in ("radix_hist", "radix_pass", "wah_encode")}
+    prof = {k: sess.profile(k) for k in KERNELS}
     D = sess.length(last[0])
     W = sess.length(last[2])
 
     # ---- algorithmic bytes (what the method has to move) -----------------------------
-    pass_bytes = 12 * n + 16 * n * (P - 1)               # first pass reads keys only, makes rows
-    hist_bytes = 4 * n
+    # scatter: the first active pass reads keys (rows are made from positions)
+    # and writes keys and rows; every later one reads and writes both.
+    scatter_bytes = 12 * n + 16 * n * (P - 1)
+    upsweep_bytes = 4 * n * P
     enc_bytes = 8 * n + 4 * W + 8 * D + 4
-    pipe_bytes = pass_bytes + hist_bytes + enc_bytes     # = 16 P n + 8 n + 4 W + 8 D + 4
-    launches, pass_ms = prof["radix_pass"]
-    per_launch_bytes = pass_bytes * args.steps / max(launches, 1)
-    avg_pass_ms = pass_ms / max(launches, 1)
-    achieved = per_launch_bytes / (avg_pass_ms * 1e-3) / 1e9
+    pipe_bytes = scatter_bytes + upsweep_bytes + enc_bytes  # = 20 P n + 4 n + 4 W + 8 D + 4 (+ the small tables)
+    launches, scatter_ms = prof["radix_scatter"]
+    per_launch_bytes = scatter_bytes * args.steps / max(launches, 1)
+    avg_launch_ms = scatter_ms / max(launches, 1)
+    achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
     pipe_gbs = pipe_bytes / (ms_per_step * 1e-3) / 1e9
+    traffic = measured_traffic(args.n_log2)
+
+    if args.copy_calibration:
+        buf = torch.zeros(n, dtype=torch.int32, device="cuda")
+        cal = sess.affine_actor(1, 1)
+        rb = sess.wrap(buf)
+        for _ in range(3):
+            (r,) = sess.request(cal, ka.ref(rb), n_out=1)
+            sess.release_ref(r)
+        torch.cuda.synchronize()
+        sess.release_actor(cal)
+        sess.release_ref(rb)
+        del buf
+        log("[bench] copy calibration: 3 in-place affine launches over 2^%d words" % args.n_log2)
 
     parity = None
     ora_s = None
@@ -167,13 +221,14 @@ def main() -> int:
                                "row ids 0..n-1, composed sort->WAH-encode pipeline, per-stage launches, "
                                "input resident in HBM",
                    "n": n, "D": D, "W": W, "radix_passes": P, "seed": args.seed},
-        "roofline": {"bound": "hbm", "kernel": "k_radix_pass", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "launches": launches, "avg_launch_ms": avg_pass_ms,
+        "roofline": {"bound": "hbm", "kernel": "k_radix_scatter", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "launches": launches, "avg_launch_ms": avg_launch_ms,
                      "algorithmic_bytes_per_launch": per_launch_bytes},
         "pipeline": {"algorithmic_bytes": pipe_bytes, "ms": ms_per_step, "achieved_GBs": pipe_gbs,
                      "frac": pipe_gbs / HBM_PEAK_GBS,
                      "kernel_ms_per_step": {k: prof[k][1] / args.steps for k in prof},
+                     "launches_per_step": {k: prof[k][0] / args.steps for k in prof},
                      "wall_s": wall},
         "cpu_baseline": cpu,
         "parity": parity,

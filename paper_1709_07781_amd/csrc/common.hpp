@@ -13,15 +13,16 @@ namespace ka {
 // Host side: what a launcher needs from the runtime.
 // ------------------------------------------------------------------------------
 
-// Look-back state of one stream.  Tiles of a look-back kernel take tickets from
-// a monotone 64-bit counter in launch order, so a tile only ever waits for
-// tiles that already run (inter-workgroup synchronisation without an
-// occupancy-sized grid).  Status words are tagged with a per-launch epoch, so
+// Look-back state of one stream.  Work-groups of a look-back kernel take their
+// tiles from a ticket counter, in order, so a tile only ever waits for tiles
+// that running work-groups hold -- no co-residency guarantee (and no
+// cooperative launch) is needed.  The counter is 0 between launches: a launch
+// draws a number of tickets fixed by its grid and tile count, and the draw of
+// the last one puts the counter back to 0.  Status words are tagged with a per-launch epoch, so
 // stale words from earlier launches read as "not yet published" and nothing
 // has to be cleared between launches.
 struct LookbackArena {
-  unsigned long long* ticket = nullptr;  // device counter, never reset
-  uint64_t tickets_taken = 0;            // host mirror of *ticket after queued launches
+  unsigned long long* ticket = nullptr;  // device counter, 0 between launches
   uint64_t* status = nullptr;            // device status words
   uint64_t status_words = 0;
   uint64_t status_bytes = 0;             // size of the pool block holding `status`
@@ -38,7 +39,6 @@ constexpr uint32_t kArenaBytes = kArenaTicketBytes + 2 * kArenaHistBytes + kSort
 // Per-launch arguments of a look-back kernel.
 struct LbArgs {
   unsigned long long* ticket;
-  unsigned long long ticket_base;
   uint64_t* status;
   uint32_t epoch;
 };
@@ -49,8 +49,8 @@ class Env {
   virtual hipStream_t stream() = 0;
   // Temporary device memory, freed in stream order after the launch is queued.
   virtual void* scratch(uint64_t bytes) = 0;
-  // Reserves `words` status words and one epoch; `blocks` is the launch's grid.
-  virtual bool lookback(uint64_t words, uint32_t blocks, LbArgs* out) = 0;
+  // Reserves `words` status words and one epoch.
+  virtual bool lookback(uint64_t words, LbArgs* out) = 0;
   virtual LookbackArena* arena() = 0;
   // Optional timing of one launch (no-ops unless profiling is on).
   virtual void prof_begin(const char* kernel) = 0;
@@ -89,11 +89,9 @@ inline int check_launch(Env& env, const char* what) {
 // Work-groups of `kernel` that fit on the device at once (occupancy x CUs).
 int coresident_blocks(const void* kernel, int block_threads);
 
-// Persistent look-back kernels: a cooperative launch guarantees that all
-// work-groups of the grid are resident together, so a work-group that waits
-// for a lower tile always waits for a running one.  Tiles are then assigned
-// statically (tile = blockIdx.x + k * gridDim.x) and no ticket counter, whose
-// same-address atomics serialise, is needed.
+// Persistent look-back kernels: the grid is the number of work-groups that fit
+// on the device at once (or the tile count, if smaller), each taking tiles
+// from the stream's ticket counter until they run out.
 template <typename... Args>
 int launch_persistent(Env& env, const char* name, void (*kernel)(Args...), uint32_t tiles, uint32_t block,
                       Args... args) {
@@ -102,7 +100,7 @@ int launch_persistent(Env& env, const char* name, void (*kernel)(Args...), uint3
   const uint32_t grid = tiles < (uint32_t)cap ? (tiles ? tiles : 1u) : (uint32_t)cap;
   void* params[] = {reinterpret_cast<void*>(&args)...};
   env.prof_begin(name);
-  hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(block), params,
+  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(block), params,
                                             0, env.stream());
   env.prof_end(name);
   if (e != hipSuccess) {
@@ -170,11 +168,19 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wave
 
 // ---- tickets and look-back ----------------------------------------------------
 
-__device__ __forceinline__ uint32_t lb_take_tile(const LbArgs& a, uint32_t* s_slot) {
-  if (threadIdx.x == 0)
-    *s_slot = (uint32_t)(atomicAdd(a.ticket, 1ull) - a.ticket_base);
-  __syncthreads();
-  return *s_slot;
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+// One lane draws a ticket: the tile to process, or kNoTile once the tiles are
+// used up.  `last` is the launch's final draw -- gridDim.x - 1 when every
+// work-group draws once, ntiles + gridDim.x - 1 when work-groups draw until
+// they get a ticket past the last tile -- and its draw returns the counter to
+// 0.  A work-group must not hold an unstarted ticket while it waits in a
+// look-back: tiles after it would wait for it in turn, and those waits add up
+// from one tile to the next.
+__device__ __forceinline__ uint32_t lb_draw(const LbArgs& a, uint64_t ntiles, uint64_t last) {
+  const unsigned long long t = atomicAdd(a.ticket, 1ull);
+  if (t == last) __hip_atomic_store(a.ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return t < ntiles ? (uint32_t)t : kNoTile;
 }
 
 __device__ __forceinline__ uint64_t lb_pack(uint32_t value, uint32_t epoch, uint32_t flag) {
@@ -243,26 +249,6 @@ __device__ __forceinline__ uint32_t lb_lookback_wave(const uint64_t* status, uin
     excl += wave_sum(lane <= stop ? sum : 0u);
     if (inc) break;
     j -= 64 * kDepth;
-  }
-  return excl;
-}
-
-// Look-back of one channel by one thread (used where each thread owns a
-// channel, e.g. a radix digit): walks predecessors one at a time.
-__device__ __forceinline__ uint32_t lb_lookback_thread(const uint64_t* status, uint32_t stride, uint32_t ch,
-                                                       uint32_t tile, uint32_t epoch) {
-  uint32_t excl = 0;
-  int64_t j = (int64_t)tile - 1;
-  while (j >= 0) {
-    const uint64_t w = lb_load(status + (uint64_t)j * stride + ch);
-    const uint32_t f = lb_flag(w, epoch);
-    if (f == 0) {
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    excl += (uint32_t)(w >> 32);
-    if (f == kLbInclusive) break;
-    --j;
   }
   return excl;
 }

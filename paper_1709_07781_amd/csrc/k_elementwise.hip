@@ -133,9 +133,8 @@ int coresident_blocks(const void* kernel, int block_threads) {
   std::lock_guard<std::mutex> g(mu);
   auto it = cache.find({dev, kernel, block_threads});
   if (it != cache.end()) return it->second;
-  int cus = 0, per_cu = 0, coop = 0;
+  int cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
-  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return -1;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block_threads, 0) != hipSuccess) return -1;
   const int cap = per_cu * cus;
   cache[{dev, kernel, block_threads}] = cap;

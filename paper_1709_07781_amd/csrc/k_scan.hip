@@ -1,8 +1,8 @@
 // Exclusive prefix sum and stream compaction of uint32 arrays.
 //
-// Both are single-pass: every tile is reduced, publishes its total, finds its
-// exclusive prefix by decoupled look-back over its predecessors and writes its
-// results -- 8 bytes of HBM
+// Both are single-pass: every tile (one work-group, numbered by a ticket) is
+// reduced, publishes its total, finds its exclusive prefix by decoupled
+// look-back over its predecessors and writes its results -- 8 bytes of HBM
 // traffic per element for the scan, 4 + 4*kept for the compaction.  The
 // compaction is the primitive of the fuseFillsLiterals step (Sec. 4.1): it
 // removes the zero entries and keeps the order; its phases "count per group",
@@ -106,47 +106,43 @@ __device__ __forceinline__ void load_tile(const uint32_t* __restrict__ in, uint6
   for (int r = 0; r < kScanRounds; ++r) load4<kVec>(in, base + ((uint64_t)r * kScanBlock + threadIdx.x) * 4, n, v[r]);
 }
 
-// Persistent: work-group b handles tiles b, b + G, b + 2G, ... (G = grid);
-// the next tile's loads are issued before the current tile's look-back.
+// One tile per work-group, numbered by a ticket drawn when the work-group
+// starts (the grid is the tile count of n_cap; with a smaller device-resident
+// count the surplus work-groups draw kNoTile and leave).
+__device__ __forceinline__ uint32_t take_tile(const LbArgs& lb, uint64_t ntiles, uint32_t* s_tk) {
+  if (threadIdx.x == 0) *s_tk = lb_draw(lb, ntiles, gridDim.x - 1);
+  __syncthreads();
+  return *s_tk;
+}
+
 template <bool kVec>
 __global__ __launch_bounds__(kScanBlock) void k_exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_cap,
                                                                    const uint64_t* __restrict__ d_n, LbArgs lb) {
-  __shared__ uint32_t s_prefix;
+  __shared__ uint32_t s_prefix, s_tk;
   __shared__ uint32_t s_wave[kScanRounds][kWaves];
   const uint64_t n = device_count(n_cap, d_n);
   const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
-  uint64_t tile = blockIdx.x;
-  if (tile >= ntiles) return;
+  const uint32_t tile = take_tile(lb, ntiles, &s_tk);
+  if (tile == kNoTile) return;
+  const uint64_t base = (uint64_t)tile * kScanTile;
   uint32_t v[kScanRounds][4];
   load_tile<kVec>(in, tile, n, v);
-  for (;;) {
-    const uint64_t base = tile * kScanTile;
-    uint32_t s[kScanRounds], pre[kScanRounds];
+  uint32_t s[kScanRounds], pre[kScanRounds];
 #pragma unroll
-    for (int r = 0; r < kScanRounds; ++r) s[r] = v[r][0] + v[r][1] + v[r][2] + v[r][3];
-    uint32_t total;
-    tile_scan(s, pre, &total, s_wave);
-    const uint64_t next = tile + gridDim.x;
-    uint32_t nv[kScanRounds][4];
-    load_tile<kVec>(in, next, next < ntiles ? n : 0, nv);
-    tile_lookback(lb, (uint32_t)tile, total, &s_prefix);
-    const uint32_t tp = s_prefix;
+  for (int r = 0; r < kScanRounds; ++r) s[r] = v[r][0] + v[r][1] + v[r][2] + v[r][3];
+  uint32_t total;
+  tile_scan(s, pre, &total, s_wave);
+  tile_lookback(lb, tile, total, &s_prefix);
+  const uint32_t tp = s_prefix;
 #pragma unroll
-    for (int r = 0; r < kScanRounds; ++r) {
-      uint32_t acc = tp + pre[r], o[4];
+  for (int r = 0; r < kScanRounds; ++r) {
+    uint32_t acc = tp + pre[r], o[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        o[j] = acc;
-        acc += v[r][j];
-      }
-      store4<kVec>(out, base + ((uint64_t)r * kScanBlock + threadIdx.x) * 4, n, o);
+    for (int j = 0; j < 4; ++j) {
+      o[j] = acc;
+      acc += v[r][j];
     }
-    if (next >= ntiles) break;
-    tile = next;
-#pragma unroll
-    for (int r = 0; r < kScanRounds; ++r)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) v[r][j] = nv[r][j];
+    store4<kVec>(out, base + ((uint64_t)r * kScanBlock + threadIdx.x) * 4, n, o);
   }
 }
 
@@ -157,48 +153,33 @@ __global__ __launch_bounds__(kScanBlock) void k_compact_nonzero_u32(const uint32
                                                                     uint32_t* __restrict__ out, uint64_t n_cap,
                                                                     const uint64_t* __restrict__ d_n,
                                                                     uint64_t* __restrict__ d_out_len, LbArgs lb) {
-  __shared__ uint32_t s_prefix;
+  __shared__ uint32_t s_prefix, s_tk;
   __shared__ uint32_t s_wave[kScanRounds][kWaves];
   __shared__ uint32_t s_out[kScanTile];
   const uint64_t n = device_count(n_cap, d_n);
   const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
-  if (n == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *d_out_len = 0;  // empty input
-    return;
-  }
-  uint64_t tile = blockIdx.x;
-  if (tile >= ntiles) return;
+  if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) *d_out_len = 0;  // empty input
+  const uint32_t tile = take_tile(lb, ntiles, &s_tk);
+  if (tile == kNoTile) return;
   uint32_t v[kScanRounds][4];
   load_tile<kVec>(in, tile, n, v);
-  for (;;) {
-    uint32_t s[kScanRounds], pre[kScanRounds];
+  uint32_t s[kScanRounds], pre[kScanRounds];
 #pragma unroll
-    for (int r = 0; r < kScanRounds; ++r)
-      s[r] = (v[r][0] != 0) + (v[r][1] != 0) + (v[r][2] != 0) + (v[r][3] != 0);
-    uint32_t total;
-    tile_scan(s, pre, &total, s_wave);
+  for (int r = 0; r < kScanRounds; ++r)
+    s[r] = (v[r][0] != 0) + (v[r][1] != 0) + (v[r][2] != 0) + (v[r][3] != 0);
+  uint32_t total;
+  tile_scan(s, pre, &total, s_wave);
 #pragma unroll
-    for (int r = 0; r < kScanRounds; ++r) {
-      uint32_t pos = pre[r];
+  for (int r = 0; r < kScanRounds; ++r) {
+    uint32_t pos = pre[r];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (v[r][j] != 0) s_out[pos++] = v[r][j];
-    }
-    const uint64_t next = tile + gridDim.x;
-    uint32_t nv[kScanRounds][4];
-    load_tile<kVec>(in, next, next < ntiles ? n : 0, nv);
-    tile_lookback(lb, (uint32_t)tile, total, &s_prefix);  // ends with a barrier
-    const uint64_t dst = s_prefix;
-    for (uint32_t i = threadIdx.x; i < total; i += kScanBlock) out[dst + i] = s_out[i];
-    if (tile == ntiles - 1 && threadIdx.x == 0) *d_out_len = dst + total;
-    if (next >= ntiles) break;
-    __syncthreads();  // s_out is reused by the next tile
-    tile = next;
-#pragma unroll
-    for (int r = 0; r < kScanRounds; ++r)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) v[r][j] = nv[r][j];
+    for (int j = 0; j < 4; ++j)
+      if (v[r][j] != 0) s_out[pos++] = v[r][j];
   }
+  tile_lookback(lb, tile, total, &s_prefix);  // ends with a barrier
+  const uint64_t dst = s_prefix;
+  for (uint32_t i = threadIdx.x; i < total; i += kScanBlock) out[dst + i] = s_out[i];
+  if (tile == ntiles - 1 && threadIdx.x == 0) *d_out_len = dst + total;
 }
 
 }  // namespace
@@ -211,13 +192,15 @@ int launch_exclusive_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t 
   if (n_cap > 0xFFFFFFFFull) return env.fail(kErrArg, "exclusive_scan_u32: more than 2^32-1 elements");
   const uint32_t grid = (uint32_t)((n_cap + kScanTile - 1) / kScanTile);
   LbArgs lb;
-  if (!env.lookback(grid, 0, &lb)) return env.fail(kErrOom, "exclusive_scan_u32: look-back state");
+  if (!env.lookback(grid, &lb)) return env.fail(kErrOom, "exclusive_scan_u32: look-back state");
   const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
+  env.prof_begin("exclusive_scan_u32");
   if (vec)
-    return launch_persistent(env, "exclusive_scan_u32", k_exclusive_scan_u32<true>, grid, (uint32_t)kScanBlock, in,
-                             out, n_cap, d_n, lb);
-  return launch_persistent(env, "exclusive_scan_u32", k_exclusive_scan_u32<false>, grid, (uint32_t)kScanBlock, in,
-                           out, n_cap, d_n, lb);
+    k_exclusive_scan_u32<true><<<dim3(grid), dim3(kScanBlock), 0, env.stream()>>>(in, out, n_cap, d_n, lb);
+  else
+    k_exclusive_scan_u32<false><<<dim3(grid), dim3(kScanBlock), 0, env.stream()>>>(in, out, n_cap, d_n, lb);
+  env.prof_end("exclusive_scan_u32");
+  return check_launch(env, "exclusive_scan_u32 launch");
 }
 
 int launch_compact_nonzero(Env& env, const uint32_t* in, uint32_t* out, uint64_t n_cap, const uint64_t* d_n,
@@ -228,13 +211,16 @@ int launch_compact_nonzero(Env& env, const uint32_t* in, uint32_t* out, uint64_t
   if (n_cap > 0xFFFFFFFFull) return env.fail(kErrArg, "compact_nonzero_u32: more than 2^32-1 elements");
   const uint32_t grid = (uint32_t)((n_cap + kScanTile - 1) / kScanTile);
   LbArgs lb;
-  if (!env.lookback(grid, 0, &lb)) return env.fail(kErrOom, "compact_nonzero_u32: look-back state");
+  if (!env.lookback(grid, &lb)) return env.fail(kErrOom, "compact_nonzero_u32: look-back state");
   const bool vec = (reinterpret_cast<uintptr_t>(in) & 15u) == 0;
+  env.prof_begin("compact_nonzero_u32");
   if (vec)
-    return launch_persistent(env, "compact_nonzero_u32", k_compact_nonzero_u32<true>, grid, (uint32_t)kScanBlock, in,
-                             out, n_cap, d_n, d_out_len, lb);
-  return launch_persistent(env, "compact_nonzero_u32", k_compact_nonzero_u32<false>, grid, (uint32_t)kScanBlock, in,
-                           out, n_cap, d_n, d_out_len, lb);
+    k_compact_nonzero_u32<true><<<dim3(grid), dim3(kScanBlock), 0, env.stream()>>>(in, out, n_cap, d_n, d_out_len, lb);
+  else
+    k_compact_nonzero_u32<false><<<dim3(grid), dim3(kScanBlock), 0, env.stream()>>>(in, out, n_cap, d_n, d_out_len,
+                                                                                    lb);
+  env.prof_end("compact_nonzero_u32");
+  return check_launch(env, "compact_nonzero_u32 launch");
 }
 
 }  // namespace ka

@@ -13,10 +13,11 @@
 //    turns every count into the output position of the tile's first key with
 //    that digit.
 //  * k_radix_scatter (one work-group per tile) ranks its keys by digit inside
-//    each wave with an LDS match (every lane ORs its lane bit into a 64-bit
-//    mask per digit and reads back the mask of its digit, so equal keys keep
-//    their order), reorders the tile by digit in LDS and writes each digit's
-//    run to its offset from the table, consecutive work-items writing
+//    each wave -- the lanes holding the same digit are found with one ballot
+//    per digit bit, and a key's rank is the number of such lanes below it
+//    plus the wave's earlier count of that digit, so equal keys keep their
+//    order -- reorders the tile by digit in LDS and writes each digit's run
+//    to its offset from the table, consecutive work-items writing
 //    consecutive addresses.
 // Tiles are taken in an XCD-aware order (see xcd_tile).
 // The first active pass reads the input (and makes row ids 0..n-1 when no rows
@@ -252,15 +253,13 @@ __global__ __launch_bounds__(kPlanBlock) void k_radix_plan(const uint32_t* __res
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const SortPlan* __restrict__ plan,
                                                           const uint32_t* __restrict__ table, uint32_t pass,
                                                           uint32_t n) {
-  // Reorder buffers; during ranking the key buffer holds the match masks.
+  // Reorder buffers.
   __shared__ __align__(16) uint32_t s_keys[kTile];
   __shared__ uint32_t s_rows[kTile];
   __shared__ uint16_t s_wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave offsets
   __shared__ uint32_t s_loff[kRadix];          // tile-local start of each digit
   __shared__ uint32_t s_dbase[kRadix];         // global start minus tile-local start
   __shared__ uint32_t s_scan[kWaves];
-  static_assert(kWaves * kRadix * 2 <= kTile, "match masks fit in the key buffer");
-  unsigned long long(*s_match)[kRadix] = reinterpret_cast<unsigned long long(*)[kRadix]>(&s_keys[0]);
 
   const uint32_t tid = threadIdx.x;
   const uint32_t active = plan->active;
@@ -272,10 +271,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   const uint32_t base = tile * kTile;
   const uint32_t tile_n = min((uint32_t)kTile, n - base);
 
-  for (int i = tid; i < kWaves * kRadix; i += kBlock) {
-    (&s_wcnt[0][0])[i] = 0;
-    (&s_match[0][0])[i] = 0ull;
-  }
+  // This tile's output position for each digit: loaded first, used last.
+  const uint32_t dstart = tid < kRadix ? table[(uint64_t)tid * ntiles + tile] : 0u;
+  for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
   // ---- load: wave w owns 64*kItems consecutive elements -----------------------
   const uint32_t w = tid / 64, lane = lane_id();
   const uint32_t wbase = w * 64 * kItems;
@@ -311,15 +309,18 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
     const bool valid = wbase + i * 64 + lane < tile_n;
     const uint32_t d = (key[i] >> shift) & (kRadix - 1);
     uint32_t r = 0;
+    // peers: the lanes whose digit equals this lane's, bit by bit from ballots
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bb = 0; bb < kRadixBits; ++bb) {
+      const bool bit = (d >> bb) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
     if (valid) {
-      atomicOr(&s_match[w][d], 1ull << lane);
-      const uint64_t peers = s_match[w][d];
       const uint32_t below = (uint32_t)__popcll(peers & lt);
       const uint32_t old = s_wcnt[w][d];
-      if (below == 0) {
-        s_wcnt[w][d] = (uint16_t)(old + (uint32_t)__popcll(peers));
-        s_match[w][d] = 0ull;
-      }
+      if (below == 0) s_wcnt[w][d] = (uint16_t)(old + (uint32_t)__popcll(peers));
       r = old + below;
     }
     rank[i] = r;
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   const uint32_t loff = block_excl_scan<kBlock>(tid < kRadix ? tile_count : 0u, s_scan, &total);
   if (tid < kRadix) {
     s_loff[tid] = loff;
-    s_dbase[tid] = table[(uint64_t)tid * ntiles + tile] - loff;
+    s_dbase[tid] = dstart - loff;
   }
   __syncthreads();
 

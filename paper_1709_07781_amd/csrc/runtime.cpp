@@ -397,8 +397,9 @@ int ref_use_on(Ref* r, uint32_t si) {
 // ---------------------------------------------------------------------------------
 class CmdEnv final : public Env {
  public:
-  // The stream's lock is held for the whole command: look-back tickets are
-  // handed out in the order the kernels reach the stream.
+  // The stream's lock is held for the whole command, so the stream's
+  // look-back arena (ticket counter, status words, epochs) serves one launch
+  // at a time, in stream order.
   CmdEnv(System* sys, uint32_t si) : sys_(sys), si_(si), lock_(sys->streams[si]->mu) {}
   ~CmdEnv() override {
     for (auto& s : scratch_) sys_->pool.release(s.first, s.second, si_, 1ull << si_);
@@ -411,7 +412,7 @@ class CmdEnv final : public Env {
     scratch_.emplace_back(p, got);
     return p;
   }
-  bool lookback(uint64_t words, uint32_t blocks, LbArgs* out) override {
+  bool lookback(uint64_t words, LbArgs* out) override {
     LookbackArena& ar = sys_->streams[si_]->arena;
     if (words > ar.status_words) {
       uint64_t nw = std::max<uint64_t>(words, 2 * ar.status_words);
@@ -431,11 +432,8 @@ class CmdEnv final : public Env {
     }
     ar.epoch += 1;
     out->ticket = ar.ticket;
-    out->ticket_base = ar.tickets_taken;
     out->status = ar.status;
     out->epoch = ar.epoch;
-    ar.tickets_taken += blocks;
-    reserved_ = true;
     return true;
   }
   LookbackArena* arena() override { return &sys_->streams[si_]->arena; }
@@ -454,20 +452,7 @@ class CmdEnv final : public Env {
     sys_->prof_pending.push_back({kernel, ev0_, ev1});
     ev0_ = nullptr;
   }
-  // A failure after tickets were reserved may leave the host's ticket count
-  // ahead of the device counter (the kernel never ran): read it back so that
-  // later look-back kernels number their tiles from zero again.
-  int fail(int code, const char* msg) override {
-    if (reserved_) {
-      LookbackArena& ar = sys_->streams[si_]->arena;
-      unsigned long long v = 0;
-      (void)hipGetLastError();
-      if (hipStreamSynchronize(stream()) == hipSuccess &&
-          hipMemcpy(&v, ar.ticket, sizeof(v), hipMemcpyDeviceToHost) == hipSuccess)
-        ar.tickets_taken = v;
-    }
-    return set_error(code, msg);
-  }
+  int fail(int code, const char* msg) override { return set_error(code, msg); }
   uint32_t si() const { return si_; }
 
  private:
@@ -476,7 +461,6 @@ class CmdEnv final : public Env {
   std::lock_guard<std::mutex> lock_;
   std::vector<std::pair<void*, uint64_t>> scratch_;
   hipEvent_t ev0_ = nullptr;
-  bool reserved_ = false;
 };
 
 // ---------------------------------------------------------------------------------
