@@ -167,6 +167,10 @@ KA_API int ka_system_memory(ka_system* sys, uint64_t* in_use, uint64_t* reserved
  *   radix_sort_rows_u32   (in keys; out skeys; out srows)         same with rows 0..n-1 (Sec. 4.1 part 1-2)
  *   wah_encode_sorted     (in skeys; in srows; out keys; out offsets; out words)
  *                                                                 Sec. 4.1 parts 3-6 on sorted pairs
+ *   wah_index_batch       (in values; in req_off; priv value_bits; out keys; out offsets;
+ *                          out words; out key_start; out word_start)
+ *                                                                 the index of each of nreq requests
+ *                                                                 (see ka_wah_batch), one pass for all
  * The names, their signatures and the data each one reads and writes are
  * documented at ka_spawn. */
 KA_API int ka_program_builtin(ka_system* sys, ka_program** out);
@@ -282,6 +286,43 @@ KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint
                         ka_wah_result* out);
 /* Frees the host arrays and releases the refs of a result. */
 KA_API int ka_wah_result_free(ka_wah_result* res);
+
+/* ---- batched index builds (Sec. 3.6: data parallelism nested inside one kernel
+ * as an alternative to one actor per stage; Sec. 4: the index of each request) - */
+typedef struct ka_wah_batch_result {
+  uint32_t nreq;     /* requests */
+  uint64_t n;        /* elements over all requests */
+  uint64_t D;        /* bitmaps over all requests */
+  uint64_t W;        /* words over all requests */
+  /* Request j's index is keys[key_start[j] .. key_start[j+1]),
+   * offsets[key_start[j] + j .. key_start[j+1] + j] (D_j + 1 entries, relative
+   * to its own words) and words[word_start[j] .. word_start[j+1]), exactly what
+   * ka_wah_index returns for that request alone. */
+  uint32_t* keys;       /* host: keys[D]        (NULL with KA_WAH_OUTPUT_REFS) */
+  uint32_t* offsets;    /* host: offsets[D + nreq] */
+  uint32_t* words;      /* host: words[W] */
+  uint32_t* key_start;  /* host: key_start[nreq + 1] */
+  uint32_t* word_start; /* host: word_start[nreq + 1] */
+  ka_ref* keys_ref;     /* device refs (KA_WAH_OUTPUT_REFS only) */
+  ka_ref* offsets_ref;
+  ka_ref* words_ref;
+  ka_ref* key_start_ref;
+  ka_ref* word_start_ref;
+} ka_wah_batch_result;
+
+/* Builds the index of each of nreq independent requests in one pass of the
+ * pipeline and waits for it.  values[0..n) holds the requests' values one
+ * after the other; req_off (host memory, nreq + 1 entries) gives request j the
+ * values [req_off[j], req_off[j+1]), with req_off[0] = 0, req_off[nreq] = n,
+ * non-decreasing (empty requests allowed); rows restart at 0 in every request.
+ * Every value must be below 2^value_bits, and value_bits plus the bits of
+ * nreq - 1 must not exceed 32 (the request number is carried in the sort key's
+ * high bits), else KA_E_ARG.  values is host memory, or device memory with
+ * KA_WAH_INPUT_DEVICE.  n < 2^30. */
+KA_API int ka_wah_batch(ka_system* sys, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
+                        uint32_t value_bits, uint32_t flags, ka_wah_batch_result* out);
+/* Frees the host arrays and releases the refs of a batch result. */
+KA_API int ka_wah_batch_result_free(ka_wah_batch_result* res);
 
 /* ---- profiling (KA_SYS_PROFILE) -------------------------------------------------- */
 /* Launch count and summed device time of every kernel named `kernel` since

@@ -77,6 +77,15 @@ _U32P, _U64P = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)
 _DBLP = ctypes.POINTER(ctypes.c_double)
 
 # name -> argtypes; every function returns int except the two string functions.
+class ka_wah_batch_result(ctypes.Structure):
+    _fields_ = [("nreq", ctypes.c_uint32), ("n", ctypes.c_uint64), ("D", ctypes.c_uint64), ("W", ctypes.c_uint64),
+                ("keys", ctypes.POINTER(ctypes.c_uint32)), ("offsets", ctypes.POINTER(ctypes.c_uint32)),
+                ("words", ctypes.POINTER(ctypes.c_uint32)), ("key_start", ctypes.POINTER(ctypes.c_uint32)),
+                ("word_start", ctypes.POINTER(ctypes.c_uint32)), ("keys_ref", ctypes.c_void_p),
+                ("offsets_ref", ctypes.c_void_p), ("words_ref", ctypes.c_void_p), ("key_start_ref", ctypes.c_void_p),
+                ("word_start_ref", ctypes.c_void_p)]
+
+
 SIGNATURES = {
     "ka_system_create": [ctypes.POINTER(ka_system_config), _PP],
     "ka_system_destroy": [_P],
@@ -107,6 +116,8 @@ SIGNATURES = {
     "ka_ref_serialize": [_P, _P, _U64, _U64P],
     "ka_wah_index": [_P, _P, _U64, _U32, ctypes.POINTER(ka_wah_result)],
     "ka_wah_result_free": [ctypes.POINTER(ka_wah_result)],
+    "ka_wah_batch": [_P, _P, _U64, _P, _U32, _U32, _U32, ctypes.POINTER(ka_wah_batch_result)],
+    "ka_wah_batch_result_free": [ctypes.POINTER(ka_wah_batch_result)],
     "ka_profile_get": [_P, ctypes.c_char_p, _U64P, _DBLP],
     "ka_profile_reset": [_P],
 }

@@ -6,14 +6,27 @@
 namespace ka {
 namespace {
 
-uint64_t cap_same(uint32_t, uint64_t n) { return n; }
-uint64_t cap_wah(uint32_t i, uint64_t n) {
+uint64_t cap_same(uint32_t, uint64_t n, const std::vector<Bound>&) { return n; }
+uint64_t cap_wah(uint32_t i, uint64_t n, const std::vector<Bound>&) {
   // (in skeys, in srows, out keys[D <= n], out offsets[D+1], out words[W <= 2n])
   if (i == 2) return n ? n : 1;
   if (i == 3) return n + 1;
   return n ? 2 * n : 1;
 }
+// (in values; in req_off[nreq+1]; priv value_bits; out keys[D <= n];
+//  out offsets[D + nreq]; out words[W <= 2n]; out key_start[nreq+1]; out word_start[nreq+1])
+uint64_t cap_batch(uint32_t i, uint64_t n, const std::vector<Bound>& args) {
+  const uint64_t slots = args[1].len;  // nreq + 1
+  const uint64_t nreq = slots ? slots - 1 : 0;
+  switch (i) {
+    case 3: return n ? n : 1;
+    case 4: return std::max<uint64_t>(n + nreq, 1);
+    case 5: return n ? 2 * n : 1;
+    default: return std::max<uint64_t>(slots, 1);
+  }
+}
 bool len_host(uint32_t) { return false; }
+bool len_batch(uint32_t i) { return i >= 3; }
 bool len_compact(uint32_t i) { return i == 1; }
 bool len_wah(uint32_t i) { return i >= 2; }
 
@@ -80,6 +93,27 @@ int run_wah(LaunchCtx& c) {
                            const_cast<uint64_t*>(a[3].d_len), const_cast<uint64_t*>(a[4].d_len));
 }
 
+// wah_index_batch: (in values; in req_off; priv value_bits; out keys; out offsets;
+//                   out words; out key_start; out word_start)
+int run_batch(LaunchCtx& c) {
+  auto& a = *c.args;
+  if (a[1].d_len) return c.env->fail(KA_E_ARG, "wah_index_batch: the request table's length must be known on the host");
+  if (a[1].len < 2) return c.env->fail(KA_E_ARG, "wah_index_batch: the request table needs nreq + 1 >= 2 entries");
+  if (a[1].len - 1 > 0xFFFFFFFFull) return c.env->fail(KA_E_ARG, "wah_index_batch: too many requests");
+  const uint32_t nreq = (uint32_t)(a[1].len - 1);
+  if (c.n > a[0].cap) return c.env->fail(KA_E_ARG, "wah_index_batch: range exceeds the values");
+  if (a[3].cap < c.n || a[4].cap < c.n + nreq || a[5].cap < 2 * c.n || a[6].cap < nreq + 1ull ||
+      a[7].cap < nreq + 1ull)
+    return c.env->fail(KA_E_ARG, "wah_index_batch: outputs need capacities n, n+nreq, 2n, nreq+1, nreq+1");
+  return launch_wah_batch(*c.env, static_cast<const uint32_t*>(a[0].ptr), c.n, static_cast<const uint32_t*>(a[1].ptr),
+                          nreq, (uint32_t)a[2].priv[0], static_cast<uint32_t*>(a[3].ptr),
+                          static_cast<uint32_t*>(a[4].ptr), static_cast<uint32_t*>(a[5].ptr),
+                          static_cast<uint32_t*>(a[6].ptr), static_cast<uint32_t*>(a[7].ptr),
+                          const_cast<uint64_t*>(a[3].d_len), const_cast<uint64_t*>(a[4].d_len),
+                          const_cast<uint64_t*>(a[5].d_len), const_cast<uint64_t*>(a[6].d_len),
+                          const_cast<uint64_t*>(a[7].d_len));
+}
+
 std::vector<BuiltinKernel> make_registry() {
   std::vector<BuiltinKernel> r;
   r.push_back({"affine_u32", {{KA_IN_OUT, KA_U32}, {KA_PRIV, KA_U32}, {KA_PRIV, KA_U32}}, cap_same, len_host, false,
@@ -101,6 +135,19 @@ std::vector<BuiltinKernel> make_registry() {
                len_wah,
                true,
                run_wah});
+  r.push_back({"wah_index_batch",
+               {{KA_IN, KA_U32},
+                {KA_IN, KA_U32},
+                {KA_PRIV, KA_U32},
+                {KA_OUT, KA_U32},
+                {KA_OUT, KA_U32},
+                {KA_OUT, KA_U32},
+                {KA_OUT, KA_U32},
+                {KA_OUT, KA_U32}},
+               cap_batch,
+               len_batch,
+               true,
+               run_batch});
   return r;
 }
 

@@ -71,7 +71,13 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
                             uint32_t* srows, uint64_t n);
 int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                       uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
-                      uint64_t* d_len_words);
+                      uint64_t* d_len_words, const uint32_t* req_base = nullptr, uint32_t req_shift = 32);
+// Batched index build: nreq requests, values concatenated, req_off[j] the
+// first position of request j (req_off[nreq] = n).
+int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
+                     uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
+                     uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
+                     uint64_t* len_key_start, uint64_t* len_word_start);
 int launch_fill_u64(Env& env, uint64_t* p, uint64_t count, uint64_t value);
 int launch_fill_u32(Env& env, uint32_t* p, uint64_t count, uint32_t value);
 int launch_set_len(Env& env, uint64_t* d_len, uint64_t value);

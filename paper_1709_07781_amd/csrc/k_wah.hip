@@ -92,17 +92,34 @@ __device__ __forceinline__ void load_pairs(const uint32_t* __restrict__ skeys, c
 // ---------------------------------------------------------------------------------
 // count: words and values emitted by each tile
 // ---------------------------------------------------------------------------------
+// Rows of a batch of requests sorted together are batch positions; the row
+// inside the request is the position minus the request's first position,
+// found from the request id in the key's high bits (key >> req_shift).
+struct BatchRows {
+  const uint32_t* req_base;  // null: rows are used as they are
+  uint32_t req_shift;
+  __device__ __forceinline__ uint32_t local(uint32_t key, uint32_t row) const {
+    return req_base ? row - req_base[req_shift < 32 ? key >> req_shift : 0u] : row;
+  }
+};
+
 template <bool kVec>
 __global__ __launch_bounds__(kEncBlock) void k_wah_count(const uint32_t* __restrict__ skeys,
                                                          const uint32_t* __restrict__ srows, uint32_t n,
                                                          uint32_t* __restrict__ tile_words,
-                                                         uint32_t* __restrict__ tile_values) {
+                                                         uint32_t* __restrict__ tile_values, BatchRows br) {
   __shared__ uint32_t s_w[kEncBlock / 64], s_s[kEncBlock / 64];
   const uint32_t tid = threadIdx.x, tile = blockIdx.x;
   const uint32_t b = tile * kEncTile;
   const uint32_t len = min((uint32_t)kEncTile, n - b);
   uint32_t vk[kVecs][4], vr[kVecs][4], pk[kVecs], pr[kVecs];
   load_pairs<kVec>(skeys, srows, b, len, tid, vk, vr);
+  if (br.req_base) {
+#pragma unroll
+    for (int j = 0; j < kVecs; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vr[j][c] = br.local(vk[j][c], vr[j][c]);
+  }
   // The predecessor of each vector's first element is the last element of the
   // lane before (a wave shuffle); lane 0 reads it from memory (it belongs to
   // another wave's vector or to the previous tile, and is served from cache).
@@ -114,7 +131,7 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_count(const uint32_t* __restr
     pr[j] = (uint32_t)__shfl_up((int)vr[j][3], 1);
     if (lane == 0 && b + i > 0 && i < len) {
       pk[j] = skeys[b + i - 1];
-      pr[j] = srows[b + i - 1];
+      pr[j] = br.local(pk[j], srows[b + i - 1]);
     }
   }
   uint32_t nw = 0, ns = 0;
@@ -202,7 +219,7 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
                                                          const uint32_t* __restrict__ tile_values,
                                                          uint32_t* __restrict__ out_keys,
                                                          uint32_t* __restrict__ out_offsets,
-                                                         uint32_t* __restrict__ out_words) {
+                                                         uint32_t* __restrict__ out_words, BatchRows br) {
   __shared__ __align__(16) uint32_t s_mem[2 * kStagePadded];
   __shared__ uint32_t s_scan[kEncBlock / 64];
   uint32_t* s_k = s_mem;
@@ -228,7 +245,7 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
       const int64_t g = (int64_t)base - 1 + xslot;
       const bool ok = g >= 0 && g < (int64_t)n;
       xk = ok ? skeys[g] : 0u;
-      xr = ok ? srows[g] : 0u;
+      xr = ok ? br.local(xk, srows[g]) : 0u;
     }
 #pragma unroll
     for (int j = 0; j < kVecs; ++j)
@@ -236,7 +253,7 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
       for (int c = 0; c < 4; ++c) {
         const uint32_t sl = 1 + 4 * (j * kEncBlock + tid) + c;
         s_k[pidx(sl)] = vk[j][c];
-        s_r[pidx(sl)] = vr[j][c];
+        s_r[pidx(sl)] = br.local(vk[j][c], vr[j][c]);
       }
     if (extra) {
       s_k[pidx(xslot)] = xk;
@@ -334,7 +351,7 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
 
 int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                       uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
-                      uint64_t* d_len_words) {
+                      uint64_t* d_len_words, const uint32_t* req_base, uint32_t req_shift) {
   if (!offsets || !d_len_keys || !d_len_offsets || !d_len_words)
     return env.fail(kErrArg, "wah_encode_sorted: null output");
   if (n >= (1ull << 30)) return env.fail(kErrArg, "wah_encode_sorted: n must be below 2^30");
@@ -345,13 +362,14 @@ int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, ui
   uint32_t* tv = static_cast<uint32_t*>(env.scratch(4ull * (ntiles ? ntiles : 1)));
   if (!tw || !tv) return env.fail(kErrOom, "wah_encode_sorted: tile counts");
   const bool vec = ((reinterpret_cast<uintptr_t>(skeys) | reinterpret_cast<uintptr_t>(srows)) & 15u) == 0;
+  const BatchRows br{req_base, req_shift};
   int rc;
   if (ntiles) {
     env.prof_begin("wah_count");
     if (vec)
-      k_wah_count<true><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv);
+      k_wah_count<true><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv, br);
     else
-      k_wah_count<false><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv);
+      k_wah_count<false><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv, br);
     env.prof_end("wah_count");
     if ((rc = check_launch(env, "wah_count launch"))) return rc;
   }
@@ -364,10 +382,10 @@ int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, ui
     env.prof_begin("wah_write");
     if (vec)
       k_wah_write<true><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv, keys, offsets,
-                                                                            words);
+                                                                            words, br);
     else
       k_wah_write<false><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv, keys, offsets,
-                                                                             words);
+                                                                             words, br);
     env.prof_end("wah_write");
     if ((rc = check_launch(env, "wah_write launch"))) return rc;
   }

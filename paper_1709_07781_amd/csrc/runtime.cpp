@@ -780,7 +780,7 @@ static int run_kernel_actor(Actor* a, Msg& msg, Msg& out, uint32_t si) {
       }
       const bool dlen = (a->bk && a->bk->device_len((uint32_t)i)) || (d_n != nullptr);
       if (a->bk) {
-        const uint64_t need = a->bk->default_cap((uint32_t)i, n);
+        const uint64_t need = a->bk->default_cap((uint32_t)i, n, args);
         if (cap == 0) cap = need;
         if (cap < need) {
           cleanup();
@@ -1548,6 +1548,129 @@ KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint
   *out = r;
   return KA_OK;
   KA_GUARD_END
+}
+
+// ---- batched index builds --------------------------------------------------------
+KA_API int ka_wah_batch(ka_system* sys, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
+                        uint32_t value_bits, uint32_t flags, ka_wah_batch_result* out) {
+  KA_GUARD_BEGIN
+  if (!sys || !out || !req_off || (n && !values)) return set_error(KA_E_ARG, "null argument");
+  if (nreq == 0) return set_error(KA_E_ARG, "no requests");
+  if (n >= (1ull << 30)) return set_error(KA_E_ARG, "n must be below 2^30");
+  if (value_bits == 0 || value_bits > 32) return set_error(KA_E_ARG, "value_bits must be 1..32");
+  const uint32_t req_bits = nreq > 1 ? 32u - (uint32_t)__builtin_clz(nreq - 1) : 0u;
+  if (value_bits + req_bits > 32) return set_error(KA_E_ARG, "value_bits + bits of nreq - 1 exceed 32");
+  if (req_off[0] != 0 || req_off[nreq] != n) return set_error(KA_E_ARG, "req_off must run from 0 to n");
+  for (uint32_t j = 0; j < nreq; ++j)
+    if (req_off[j + 1] < req_off[j]) return set_error(KA_E_ARG, "req_off must be non-decreasing");
+  int rc = sys->ensure_init();
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> g(sys->wah_mu);
+    if (!sys->builtin) {
+      ka_program* p = nullptr;
+      if ((rc = ka_program_builtin(sys, &p))) return rc;
+      sys->builtin = p;  // released by ka_system_destroy
+    }
+  }
+  ka_arg sig[8] = {};
+  sig[0] = {KA_IN, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
+  sig[1] = {KA_IN, KA_U32, KA_VAL, KA_REF, 0, nullptr, nullptr, nullptr};
+  sig[2] = {KA_PRIV, KA_U32, KA_VAL, KA_VAL, 1, nullptr, nullptr, &value_bits};
+  for (int i = 3; i < 8; ++i) sig[i] = {KA_OUT, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
+  ka_nd_range r{};
+  r.dims = 1;
+  ka_actor* act = nullptr;
+  if ((rc = ka_spawn(sys, static_cast<ka_program*>(sys->builtin), "wah_index_batch", &r, sig, 8, &act))) return rc;
+  ka_ref* in = nullptr;
+  if (flags & KA_WAH_INPUT_DEVICE) {
+    rc = ka_ref_wrap(sys, const_cast<uint32_t*>(values), KA_U32, n, KA_ACCESS_READ, &in);
+  } else {
+    MsgVal v;
+    v.mode = KA_VAL;
+    v.dtype = KA_U32;
+    v.host = values;
+    v.count = n;
+    Ref* rr = nullptr;
+    rc = upload(sys, v, act->stream, &rr);
+    in = static_cast<ka_ref*>(rr);
+  }
+  if (rc) {
+    ka_actor_release(act);
+    return rc;
+  }
+  ka_value msg[2] = {};
+  msg[0].mode = KA_REF;
+  msg[0].ref = in;
+  msg[1].mode = KA_VAL;
+  msg[1].dtype = KA_U32;
+  msg[1].ptr = const_cast<uint32_t*>(req_off);
+  msg[1].count = (uint64_t)nreq + 1;
+  ka_ticket* t = nullptr;
+  rc = ka_send(act, msg, 2, &t);
+  ka_ref_release(in);
+  ka_actor_release(act);
+  if (rc) return rc;
+  ka_value res[5] = {};
+  rc = ka_receive(t, res, 5, -1);
+  ka_ticket_release(t);
+  if (rc) return rc;
+  uint64_t len[5] = {};
+  for (int i = 0; i < 5 && !rc; ++i) rc = ref_length(res[i].ref, &len[i]);
+  if (!rc && len[3] == 0) rc = set_error(KA_E_ARG, "a value is at or above 2^value_bits");
+  if (!rc && (len[1] != len[0] + nreq || len[3] != nreq + 1ull || len[4] != nreq + 1ull))
+    rc = set_error(KA_E_DEVICE, "inconsistent batch index lengths");
+  ka_wah_batch_result br{};
+  br.nreq = nreq;
+  br.n = n;
+  if (!rc) {
+    br.D = len[0];
+    br.W = len[2];
+    if (flags & KA_WAH_OUTPUT_REFS) {
+      br.keys_ref = res[0].ref;
+      br.offsets_ref = res[1].ref;
+      br.words_ref = res[2].ref;
+      br.key_start_ref = res[3].ref;
+      br.word_start_ref = res[4].ref;
+      *out = br;
+      return KA_OK;
+    }
+    uint32_t** dst[5] = {&br.keys, &br.offsets, &br.words, &br.key_start, &br.word_start};
+    for (int i = 0; i < 5 && !rc; ++i) {
+      *dst[i] = static_cast<uint32_t*>(std::malloc(std::max<uint64_t>(len[i], 1) * 4));
+      if (!*dst[i])
+        rc = set_error(KA_E_OOM, "host allocation failed");
+      else
+        rc = ka_ref_read(res[i].ref, *dst[i], len[i] * 4);
+    }
+  }
+  for (auto& v : res)
+    if (v.ref) ka_ref_release(v.ref);
+  if (rc) {
+    std::free(br.keys);
+    std::free(br.offsets);
+    std::free(br.words);
+    std::free(br.key_start);
+    std::free(br.word_start);
+    return rc;
+  }
+  *out = br;
+  return KA_OK;
+  KA_GUARD_END
+}
+
+KA_API int ka_wah_batch_result_free(ka_wah_batch_result* res) {
+  if (!res) return set_error(KA_E_ARG, "null result");
+  std::free(res->keys);
+  std::free(res->offsets);
+  std::free(res->words);
+  std::free(res->key_start);
+  std::free(res->word_start);
+  ka_ref* refs[5] = {res->keys_ref, res->offsets_ref, res->words_ref, res->key_start_ref, res->word_start_ref};
+  for (auto* r : refs)
+    if (r) ka_ref_release(r);
+  std::memset(res, 0, sizeof(*res));
+  return KA_OK;
 }
 
 KA_API int ka_wah_result_free(ka_wah_result* res) {

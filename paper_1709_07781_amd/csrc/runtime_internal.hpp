@@ -173,8 +173,9 @@ struct LaunchCtx {
 struct BuiltinKernel {
   const char* name;
   std::vector<std::pair<uint32_t, uint32_t>> sig;  // (dir, dtype)
-  // default capacity of the out/in_out argument at signature index i
-  uint64_t (*default_cap)(uint32_t i, uint64_t n);
+  // default capacity of the out/in_out argument at signature index i, given
+  // the work-item count and the bound arguments (inputs are bound by then)
+  uint64_t (*default_cap)(uint32_t i, uint64_t n, const std::vector<Bound>& args);
   bool (*device_len)(uint32_t i);  // output length written by the kernel
   bool needs_host_n;               // work-item count must be known on the host
   int (*launch)(LaunchCtx& c);

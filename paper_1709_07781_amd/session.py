@@ -10,7 +10,7 @@ from ctypes import byref, c_void_p
 
 import numpy as np
 
-from . import (KA_IN, KA_IN_OUT, KA_OUT, KA_PRIV, KA_REF, KA_SYS_PROFILE, KA_U32, KA_VAL, KA_WAH_INPUT_DEVICE,
+from . import (ka_wah_batch_result, KA_IN, KA_IN_OUT, KA_OUT, KA_PRIV, KA_REF, KA_SYS_PROFILE, KA_U32, KA_VAL, KA_WAH_INPUT_DEVICE,
                KA_WAH_OUTPUT_REFS, arg, check, ka_nd_range, ka_system_config, ka_value, ka_wah_result, lib,
                nd_range, ref, sig, val, values)
 
@@ -158,6 +158,37 @@ class Session:
         words = np.ctypeslib.as_array(res.words, shape=(max(W, 1),))[:W].copy()
         check(lib.ka_wah_result_free(byref(res)), "ka_wah_result_free")
         return keys, offs, words
+
+    def wah_batch(self, values_, req_off, value_bits: int, refs: bool = False):
+        """Index of every request of a batch (ka_wah_batch).  values_: numpy
+        uint32 array (host) or device tensor of the concatenated requests;
+        req_off: nreq + 1 request boundaries.  Returns a list of per-request
+        (keys, offsets, words), or the result struct with refs."""
+        off = np.ascontiguousarray(req_off, dtype=np.uint32)
+        nreq = off.size - 1
+        res = ka_wah_batch_result()
+        flags = KA_WAH_OUTPUT_REFS if refs else 0
+        if isinstance(values_, np.ndarray):
+            v = np.ascontiguousarray(values_, dtype=np.uint32)
+            check(lib.ka_wah_batch(self.sys, v.ctypes.data if v.size else None, v.size, off.ctypes.data, nreq,
+                                   value_bits, flags, byref(res)), "ka_wah_batch")
+        else:
+            check(lib.ka_wah_batch(self.sys, c_void_p(values_.data_ptr()), values_.numel(), off.ctypes.data, nreq,
+                                   value_bits, flags | KA_WAH_INPUT_DEVICE, byref(res)), "ka_wah_batch")
+        if refs:
+            return res
+        D, W = res.D, res.W
+        keys = np.ctypeslib.as_array(res.keys, shape=(max(D, 1),))[:D].copy()
+        offs = np.ctypeslib.as_array(res.offsets, shape=(D + nreq,)).copy()
+        words = np.ctypeslib.as_array(res.words, shape=(max(W, 1),))[:W].copy()
+        ks = np.ctypeslib.as_array(res.key_start, shape=(nreq + 1,)).copy()
+        ws = np.ctypeslib.as_array(res.word_start, shape=(nreq + 1,)).copy()
+        check(lib.ka_wah_batch_result_free(byref(res)), "ka_wah_batch_result_free")
+        out = []
+        for j in range(nreq):
+            k0, k1, w0, w1 = int(ks[j]), int(ks[j + 1]), int(ws[j]), int(ws[j + 1])
+            out.append((keys[k0:k1], offs[k0 + j:k1 + j + 1], words[w0:w1]))
+        return out
 
     def stream_handle(self, i: int = 0) -> int:
         s = c_void_p()
