@@ -26,44 +26,86 @@ namespace ka {
 namespace {
 
 constexpr int kKeyBlock = 256;
-constexpr int kKeyItems = 16;  // consecutive values per work-item
+constexpr int kKeyVecs = 4;                        // 16-byte vectors per work-item
+constexpr int kKeyTile = kKeyBlock * kKeyVecs * 4;  // 4096 values
+constexpr int kKeyReqs = 1024;                     // requests per tile searched in LDS
 constexpr int kSplitBlock = 256;
 constexpr uint32_t kSplitGrid = 1024;
 
 __device__ __forceinline__ uint32_t tag_shift_ok(uint32_t value_bits) { return value_bits < 32; }
 
-// key[i] = request(i) << value_bits | values[i]; any value with bits at or
-// above value_bits sets *bad.
-__global__ __launch_bounds__(kKeyBlock) void k_batch_keys(const uint32_t* __restrict__ values, uint32_t n,
-                                                          const uint32_t* __restrict__ req_off, uint32_t nreq,
-                                                          uint32_t value_bits, uint32_t* __restrict__ keys,
-                                                          uint32_t* __restrict__ bad) {
-  const uint64_t i0 = ((uint64_t)blockIdx.x * kKeyBlock + threadIdx.x) * kKeyItems;
-  if (i0 >= n) return;
-  // request of i0: the last j with req_off[j] <= i0 (binary search over [0, nreq))
-  uint32_t lo = 0, hi = nreq;
+// Last j in [lo, hi) with off[j] <= i, given off[lo] <= i (binary search).
+template <typename T>
+__device__ __forceinline__ uint32_t request_of(const T* off, uint32_t lo, uint32_t hi, uint64_t i) {
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) / 2;
-    if (req_off[mid] <= i0)
+    if (off[mid] <= i)
       lo = mid;
     else
       hi = mid;
   }
-  uint32_t j = lo;
-  uint32_t next = j + 1 < nreq ? req_off[j + 1] : n;
-  uint32_t over = 0;
+  return lo;
+}
+
+// key[i] = request(i) << value_bits | values[i] over tiles of kKeyTile values
+// (16-byte loads and stores); any value with bits at or above value_bits sets
+// *bad.  The tile's requests j0..j1 are found once; when there are at most
+// kKeyReqs of them their boundaries are searched in LDS.
+__global__ __launch_bounds__(kKeyBlock) void k_batch_keys(const uint32_t* __restrict__ values, uint32_t n,
+                                                          const uint32_t* __restrict__ req_off, uint32_t nreq,
+                                                          uint32_t value_bits, uint32_t* __restrict__ keys,
+                                                          uint32_t* __restrict__ bad) {
+  __shared__ uint32_t s_off[kKeyReqs + 1];
+  __shared__ uint32_t s_j[2];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t b0 = (uint64_t)blockIdx.x * kKeyTile;
+  const uint32_t len = (uint32_t)min((uint64_t)kKeyTile, n - b0);
+  if (tid < 2) s_j[tid] = request_of(req_off, 0, nreq, tid == 0 ? b0 : b0 + len - 1);
+  __syncthreads();
+  const uint32_t j0 = s_j[0], cnt = s_j[1] - j0 + 1;  // requests met by this tile
+  const bool local = cnt <= (uint32_t)kKeyReqs;
+  if (local)
+    for (uint32_t k = tid; k <= cnt; k += kKeyBlock) s_off[k] = j0 + k < nreq ? req_off[j0 + k] : n;
+  __syncthreads();
   const bool tagged = tag_shift_ok(value_bits);
+  const bool vec = len == (uint32_t)kKeyTile && ((reinterpret_cast<uintptr_t>(values) |
+                                                    reinterpret_cast<uintptr_t>(keys)) & 15u) == 0;
+  uint32_t over = 0;
 #pragma unroll
-  for (int c = 0; c < kKeyItems; ++c) {
-    const uint64_t i = i0 + c;
-    if (i < n) {
-      while (i >= next && j + 1 < nreq) {  // crossing into the next (possibly empty) requests
-        ++j;
-        next = j + 1 < nreq ? req_off[j + 1] : n;
+  for (int r = 0; r < kKeyVecs; ++r) {
+    const uint32_t e = 4 * (r * kKeyBlock + tid);  // tile-local index of this vector's first value
+    uint32_t v[4], k[4];
+    if (vec) {
+      const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(values + b0 + e));
+      v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = e + c < len ? values[b0 + e + c] : 0u;
+    }
+    // request of the vector's first value; the others may cross into later requests
+    uint32_t j = e < len ? (local ? j0 + request_of(s_off, 0, cnt, b0 + e) : request_of(req_off, j0, nreq, b0 + e))
+                         : 0u;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (e + c < len) {
+        for (;;) {  // advance past requests that end before this value (empty ones included)
+          if (j + 1 >= nreq || (local && j + 1 - j0 > cnt)) break;
+          const uint32_t next = local ? s_off[j + 1 - j0] : req_off[j + 1];
+          if (b0 + e + c < next) break;
+          ++j;
+        }
+        over |= tagged ? v[c] >> value_bits : 0u;
       }
-      const uint32_t v = values[i];
-      over |= tagged ? v >> value_bits : 0u;
-      keys[i] = (tagged ? j << value_bits : 0u) | v;
+      k[c] = (tagged ? j << value_bits : 0u) | v[c];
+    }
+    if (vec) {
+      u32x4 q;
+      q.x = k[0], q.y = k[1], q.z = k[2], q.w = k[3];
+      __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(keys + b0 + e));
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (e + c < len) keys[b0 + e + c] = k[c];
     }
   }
   if (over) *bad = 1u;
@@ -150,7 +192,7 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
   int rc = launch_fill_u32(env, bad, 1, 0);
   if (rc) return rc;
   if (n) {
-    const uint64_t blocks = (n + (uint64_t)kKeyBlock * kKeyItems - 1) / ((uint64_t)kKeyBlock * kKeyItems);
+    const uint64_t blocks = (n + kKeyTile - 1) / kKeyTile;
     env.prof_begin("batch_keys");
     k_batch_keys<<<dim3((uint32_t)blocks), dim3(kKeyBlock), 0, env.stream()>>>(values, nn, req_off, nreq, value_bits,
                                                                               tkeys, bad);
