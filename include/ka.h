@@ -73,6 +73,8 @@ typedef struct ka_program ka_program;
 typedef struct ka_actor ka_actor;
 typedef struct ka_ref ka_ref;
 typedef struct ka_ticket ka_ticket;
+typedef struct ka_server ka_server;
+typedef struct ka_srv_req ka_srv_req;
 
 /* System configuration (the actor_system_config that loads the device module,
  * Sec. 3.4).  HIP is initialised lazily on the first call that needs the
@@ -323,6 +325,65 @@ KA_API int ka_wah_batch(ka_system* sys, const uint32_t* values, uint64_t n, cons
                         uint32_t value_bits, uint32_t flags, ka_wah_batch_result* out);
 /* Frees the host arrays and releases the refs of a batch result. */
 KA_API int ka_wah_batch_result_free(ka_wah_batch_result* res);
+
+/* ---- the served form (Sec. 3.3: the mailbox buffers messages in order of
+ * arrival; Sec. 3.4: an OpenCL actor feeds its device's command queue) ------------ */
+/* Request kinds: the WAH index of the values (outputs keys, offsets, words, as
+ * ka_wah_index), their exclusive scan mod 2^32 (one output), or the server's
+ * affine chain x <- a_i x + b_i, i = 0..chain_len-1 (one output). */
+enum { KA_REQ_WAH = 0, KA_REQ_SCAN = 1, KA_REQ_CHAIN = 2 };
+
+typedef struct ka_server_config {
+  uint32_t streams;          /* batches in flight at once, one per system stream (0 = 2; at most
+                                the system's n_streams) */
+  uint32_t max_batch;        /* requests merged into one batch (0 = 1024; 1 = no batching) */
+  uint64_t hbm_budget_bytes; /* device memory the server's batches may hold together (0 = 64 GiB) */
+  uint32_t value_bits;       /* index requests: every value below 2^value_bits (0 = 12) */
+  uint32_t chain_len;        /* affine chain stages and their parameters (a_i odd) */
+  const uint32_t* chain_a;
+  const uint32_t* chain_b;
+} ka_server_config;
+
+typedef struct ka_server_stats {
+  uint64_t completed;      /* requests finished since the last reset */
+  uint64_t failed;
+  uint64_t elements;       /* input elements of the completed requests */
+  uint64_t batches;
+  double mean_batch;       /* requests per batch */
+  double p50_us, p99_us, max_us, mean_us; /* latency: arrival to completion seen on the host */
+  uint64_t queued;         /* requests waiting in the mailbox now */
+  uint64_t budget_in_use;  /* bytes admitted now, and the peak since the reset */
+  uint64_t budget_peak;
+} ka_server_stats;
+
+/* Starts a server on `sys`: a mailbox thread that forms a batch from the
+ * oldest waiting requests whenever a stream slot is free and the HBM budget
+ * admits them (continuous batching: requests that arrive while batches run
+ * wait for the next slot), and a completion thread.  Index requests of a batch
+ * run as one batched index build, scans as one scan rebased per request,
+ * chains as one chain over their concatenation; batches on different streams
+ * overlap.  Each result is the one the request gets alone. */
+KA_API int ka_server_create(ka_system* sys, const ka_server_config* cfg, ka_server** out);
+/* Queues a request (the data are copied before return).  arrival_us is its
+ * arrival time on the ka_server_clock_us clock (0 = now); latency is measured
+ * from it.  KA_E_BUDGET if the request alone exceeds the budget, KA_E_ARG for
+ * an index value at or above 2^value_bits.  n < 2^30. */
+KA_API int ka_server_submit(ka_server* srv, uint32_t kind, const uint32_t* data, uint64_t n, double arrival_us,
+                            ka_srv_req** out);
+/* Waits for a request (timeout_us < 0: no limit); KA_E_TIMEOUT leaves it
+ * pending; a failed request returns its error (KA_E_CANCELLED if the server
+ * was destroyed before it ran). */
+KA_API int ka_server_wait(ka_srv_req* req, int64_t timeout_us);
+/* Output i of a finished request: *count elements, copied to host[0..cap)
+ * when host is given (KA_E_ARG if cap is too small). */
+KA_API int ka_server_result(ka_srv_req* req, uint32_t i, uint32_t* host, uint64_t cap, uint64_t* count);
+KA_API int ka_server_request_release(ka_srv_req* req);
+KA_API int ka_server_get_stats(ka_server* srv, ka_server_stats* out);
+KA_API int ka_server_reset_stats(ka_server* srv);
+/* Now on the clock of arrival times (CLOCK_MONOTONIC, microseconds). */
+KA_API int ka_server_clock_us(double* now);
+/* Cancels waiting requests, waits for batches in flight, stops the threads. */
+KA_API int ka_server_destroy(ka_server* srv);
 
 /* ---- profiling (KA_SYS_PROFILE) -------------------------------------------------- */
 /* Launch count and summed device time of every kernel named `kernel` since

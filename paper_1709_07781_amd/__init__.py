@@ -86,6 +86,22 @@ class ka_wah_batch_result(ctypes.Structure):
                 ("word_start_ref", ctypes.c_void_p)]
 
 
+class ka_server_config(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("value_bits", ctypes.c_uint32), ("chain_len", ctypes.c_uint32),
+                ("chain_a", ctypes.POINTER(ctypes.c_uint32)), ("chain_b", ctypes.POINTER(ctypes.c_uint32))]
+
+
+class ka_server_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64), ("elements", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("mean_batch", ctypes.c_double), ("p50_us", ctypes.c_double),
+                ("p99_us", ctypes.c_double), ("max_us", ctypes.c_double), ("mean_us", ctypes.c_double),
+                ("queued", ctypes.c_uint64), ("budget_in_use", ctypes.c_uint64), ("budget_peak", ctypes.c_uint64)]
+
+
+KA_REQ_WAH, KA_REQ_SCAN, KA_REQ_CHAIN = 0, 1, 2
+
+
 SIGNATURES = {
     "ka_system_create": [ctypes.POINTER(ka_system_config), _PP],
     "ka_system_destroy": [_P],
@@ -118,6 +134,15 @@ SIGNATURES = {
     "ka_wah_result_free": [ctypes.POINTER(ka_wah_result)],
     "ka_wah_batch": [_P, _P, _U64, _P, _U32, _U32, _U32, ctypes.POINTER(ka_wah_batch_result)],
     "ka_wah_batch_result_free": [ctypes.POINTER(ka_wah_batch_result)],
+    "ka_server_create": [_P, ctypes.POINTER(ka_server_config), _PP],
+    "ka_server_submit": [_P, _U32, _P, _U64, ctypes.c_double, _PP],
+    "ka_server_wait": [_P, _I64],
+    "ka_server_result": [_P, _U32, _P, _U64, _U64P],
+    "ka_server_request_release": [_P],
+    "ka_server_get_stats": [_P, ctypes.POINTER(ka_server_stats)],
+    "ka_server_reset_stats": [_P],
+    "ka_server_clock_us": [_DBLP],
+    "ka_server_destroy": [_P],
     "ka_profile_get": [_P, ctypes.c_char_p, _U64P, _DBLP],
     "ka_profile_reset": [_P],
 }

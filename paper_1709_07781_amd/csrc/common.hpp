@@ -78,6 +78,10 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
                      uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
                      uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
                      uint64_t* len_key_start, uint64_t* len_word_start);
+// Exclusive scan of each of nreq requests concatenated in in[0..n) (req_off as
+// for the batched index).
+int launch_segmented_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* req_off,
+                          uint32_t nreq);
 int launch_fill_u64(Env& env, uint64_t* p, uint64_t count, uint64_t value);
 int launch_fill_u32(Env& env, uint32_t* p, uint64_t count, uint32_t value);
 int launch_set_len(Env& env, uint64_t* d_len, uint64_t value);

@@ -47,14 +47,28 @@ __device__ __forceinline__ uint32_t request_of(const T* off, uint32_t lo, uint32
   return lo;
 }
 
-// key[i] = request(i) << value_bits | values[i] over tiles of kKeyTile values
-// (16-byte loads and stores); any value with bits at or above value_bits sets
-// *bad.  The tile's requests j0..j1 are found once; when there are at most
-// kKeyReqs of them their boundaries are searched in LDS.
-__global__ __launch_bounds__(kKeyBlock) void k_batch_keys(const uint32_t* __restrict__ values, uint32_t n,
-                                                          const uint32_t* __restrict__ req_off, uint32_t nreq,
-                                                          uint32_t value_bits, uint32_t* __restrict__ keys,
-                                                          uint32_t* __restrict__ bad) {
+// Per-value maps that need the request of each value.
+struct TagOp {  // key = request << value_bits | value; flags values with bits at or above value_bits
+  uint32_t value_bits;
+  __device__ __forceinline__ uint32_t operator()(uint32_t v, uint32_t j, uint32_t& over) const {
+    if (!tag_shift_ok(value_bits)) return v;
+    over |= v >> value_bits;
+    return j << value_bits | v;
+  }
+};
+struct RebaseOp {  // a batch-wide exclusive scan minus its value at the request's first position
+  const uint32_t* base;
+  __device__ __forceinline__ uint32_t operator()(uint32_t v, uint32_t j, uint32_t&) const { return v - base[j]; }
+};
+
+// out[i] = op(in[i], request(i)) over tiles of kKeyTile values (16-byte loads
+// and stores; in == out is allowed).  The tile's requests j0..j1 are found
+// once; when there are at most kKeyReqs of them their boundaries are searched
+// in LDS.  Any `over` bit an op reports sets *bad.
+template <class Op>
+__global__ __launch_bounds__(kKeyBlock) void k_batch_map(const uint32_t* in, uint32_t* out, uint32_t n,
+                                                         const uint32_t* __restrict__ req_off, uint32_t nreq, Op op,
+                                                         uint32_t* __restrict__ bad) {
   __shared__ uint32_t s_off[kKeyReqs + 1];
   __shared__ uint32_t s_j[2];
   const uint32_t tid = threadIdx.x;
@@ -67,26 +81,26 @@ __global__ __launch_bounds__(kKeyBlock) void k_batch_keys(const uint32_t* __rest
   if (local)
     for (uint32_t k = tid; k <= cnt; k += kKeyBlock) s_off[k] = j0 + k < nreq ? req_off[j0 + k] : n;
   __syncthreads();
-  const bool tagged = tag_shift_ok(value_bits);
-  const bool vec = len == (uint32_t)kKeyTile && ((reinterpret_cast<uintptr_t>(values) |
-                                                    reinterpret_cast<uintptr_t>(keys)) & 15u) == 0;
+  const bool vec = len == (uint32_t)kKeyTile &&
+                   ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
   uint32_t over = 0;
 #pragma unroll
   for (int r = 0; r < kKeyVecs; ++r) {
     const uint32_t e = 4 * (r * kKeyBlock + tid);  // tile-local index of this vector's first value
     uint32_t v[4], k[4];
     if (vec) {
-      const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(values + b0 + e));
+      const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(in + b0 + e));
       v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
     } else {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = e + c < len ? values[b0 + e + c] : 0u;
+      for (int c = 0; c < 4; ++c) v[c] = e + c < len ? in[b0 + e + c] : 0u;
     }
     // request of the vector's first value; the others may cross into later requests
     uint32_t j = e < len ? (local ? j0 + request_of(s_off, 0, cnt, b0 + e) : request_of(req_off, j0, nreq, b0 + e))
                          : 0u;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
+      k[c] = 0;
       if (e + c < len) {
         for (;;) {  // advance past requests that end before this value (empty ones included)
           if (j + 1 >= nreq || (local && j + 1 - j0 > cnt)) break;
@@ -94,21 +108,28 @@ __global__ __launch_bounds__(kKeyBlock) void k_batch_keys(const uint32_t* __rest
           if (b0 + e + c < next) break;
           ++j;
         }
-        over |= tagged ? v[c] >> value_bits : 0u;
+        k[c] = op(v[c], j, over);
       }
-      k[c] = (tagged ? j << value_bits : 0u) | v[c];
     }
     if (vec) {
       u32x4 q;
       q.x = k[0], q.y = k[1], q.z = k[2], q.w = k[3];
-      __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(keys + b0 + e));
+      __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(out + b0 + e));
     } else {
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        if (e + c < len) keys[b0 + e + c] = k[c];
+        if (e + c < len) out[b0 + e + c] = k[c];
     }
   }
-  if (over) *bad = 1u;
+  if (over && bad) *bad = 1u;
+}
+
+// base[j] = scan[req_off[j]] for every non-empty request.
+__global__ __launch_bounds__(kSplitBlock) void k_batch_bases(const uint32_t* __restrict__ scan, uint32_t n,
+                                                             const uint32_t* __restrict__ req_off, uint32_t nreq,
+                                                             uint32_t* __restrict__ base) {
+  for (uint32_t j = blockIdx.x * kSplitBlock + threadIdx.x; j < nreq; j += gridDim.x * kSplitBlock)
+    base[j] = req_off[j] < n ? scan[req_off[j]] : 0u;
 }
 
 // key_start[j] = first lookup entry whose request is >= j (lower bound of the
@@ -194,8 +215,8 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
   if (n) {
     const uint64_t blocks = (n + kKeyTile - 1) / kKeyTile;
     env.prof_begin("batch_keys");
-    k_batch_keys<<<dim3((uint32_t)blocks), dim3(kKeyBlock), 0, env.stream()>>>(values, nn, req_off, nreq, value_bits,
-                                                                              tkeys, bad);
+    k_batch_map<TagOp><<<dim3((uint32_t)blocks), dim3(kKeyBlock), 0, env.stream()>>>(values, tkeys, nn, req_off, nreq,
+                                                                                    TagOp{value_bits}, bad);
     env.prof_end("batch_keys");
     if ((rc = check_launch(env, "batch_keys launch"))) return rc;
     if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n))) return rc;
@@ -214,6 +235,30 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
       len_key_start, len_word_start);
   env.prof_end("batch_split");
   return check_launch(env, "batch_tables launch");
+}
+
+// Exclusive scan of each of nreq requests concatenated in in[0..n): one scan
+// of the whole batch, then every value minus the batch scan at its request's
+// first position (mod 2^32 the difference is the request's own scan).
+int launch_segmented_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* req_off,
+                          uint32_t nreq) {
+  if (n == 0) return kOk;
+  if (!in || !out || !req_off || nreq == 0) return env.fail(kErrArg, "segmented scan: null buffer");
+  if (n >= (1ull << 32)) return env.fail(kErrArg, "segmented scan: n must be below 2^32");
+  uint32_t* base = static_cast<uint32_t*>(env.scratch(4ull * nreq));
+  if (!base) return env.fail(kErrOom, "segmented scan: scratch");
+  int rc = launch_exclusive_scan(env, in, out, n, nullptr);
+  if (rc) return rc;
+  const uint32_t nn = (uint32_t)n;
+  const uint32_t sgrid = std::min<uint32_t>(kSplitGrid, (nreq + kSplitBlock - 1) / kSplitBlock);
+  env.prof_begin("segment_rebase");
+  k_batch_bases<<<dim3(sgrid), dim3(kSplitBlock), 0, env.stream()>>>(out, nn, req_off, nreq, base);
+  if ((rc = check_launch(env, "batch_bases launch"))) return rc;
+  const uint64_t blocks = (n + kKeyTile - 1) / kKeyTile;
+  k_batch_map<RebaseOp><<<dim3((uint32_t)blocks), dim3(kKeyBlock), 0, env.stream()>>>(out, out, nn, req_off, nreq,
+                                                                                     RebaseOp{base}, nullptr);
+  env.prof_end("segment_rebase");
+  return check_launch(env, "batch_map launch");
 }
 
 }  // namespace ka

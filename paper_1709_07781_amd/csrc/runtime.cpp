@@ -395,73 +395,6 @@ int ref_use_on(Ref* r, uint32_t si) {
 // ---------------------------------------------------------------------------------
 // the launch environment
 // ---------------------------------------------------------------------------------
-class CmdEnv final : public Env {
- public:
-  // The stream's lock is held for the whole command, so the stream's
-  // look-back arena (ticket counter, status words, epochs) serves one launch
-  // at a time, in stream order.
-  CmdEnv(System* sys, uint32_t si) : sys_(sys), si_(si), lock_(sys->streams[si]->mu) {}
-  ~CmdEnv() override {
-    for (auto& s : scratch_) sys_->pool.release(s.first, s.second, si_, 1ull << si_);
-  }
-  hipStream_t stream() override { return sys_->streams[si_]->s; }
-  void* scratch(uint64_t bytes) override {
-    void* p = nullptr;
-    uint64_t got = 0;
-    if (sys_->pool.alloc(bytes, si_, &p, &got) != KA_OK) return nullptr;
-    scratch_.emplace_back(p, got);
-    return p;
-  }
-  bool lookback(uint64_t words, LbArgs* out) override {
-    LookbackArena& ar = sys_->streams[si_]->arena;
-    if (words > ar.status_words) {
-      uint64_t nw = std::max<uint64_t>(words, 2 * ar.status_words);
-      nw = std::max<uint64_t>(nw, 1 << 16);
-      void* p = nullptr;
-      uint64_t got = 0;
-      if (sys_->pool.alloc(nw * 8, si_, &p, &got) != KA_OK) return false;
-      if (ar.status) sys_->pool.release(ar.status, ar.status_bytes, si_, 1ull << si_);
-      ar.status = static_cast<uint64_t*>(p);
-      ar.status_words = got / 8;
-      ar.status_bytes = got;
-      if (launch_fill_u64(*this, ar.status, ar.status_words, 0) != KA_OK) return false;
-    }
-    if (ar.epoch + 1 >= (1u << 30)) {
-      if (launch_fill_u64(*this, ar.status, ar.status_words, 0) != KA_OK) return false;
-      ar.epoch = 0;
-    }
-    ar.epoch += 1;
-    out->ticket = ar.ticket;
-    out->status = ar.status;
-    out->epoch = ar.epoch;
-    return true;
-  }
-  LookbackArena* arena() override { return &sys_->streams[si_]->arena; }
-  void prof_begin(const char* kernel) override {
-    if (!sys_->profile) return;
-    (void)kernel;
-    ev0_ = sys_->get_event(true);
-    if (ev0_) hipEventRecord(ev0_, stream());
-  }
-  void prof_end(const char* kernel) override {
-    if (!sys_->profile || !ev0_) return;
-    hipEvent_t ev1 = sys_->get_event(true);
-    if (!ev1) return;
-    hipEventRecord(ev1, stream());
-    std::lock_guard<std::mutex> g(sys_->prof_mu);
-    sys_->prof_pending.push_back({kernel, ev0_, ev1});
-    ev0_ = nullptr;
-  }
-  int fail(int code, const char* msg) override { return set_error(code, msg); }
-  uint32_t si() const { return si_; }
-
- private:
-  System* sys_;
-  uint32_t si_;
-  std::lock_guard<std::mutex> lock_;
-  std::vector<std::pair<void*, uint64_t>> scratch_;
-  hipEvent_t ev0_ = nullptr;
-};
 
 // ---------------------------------------------------------------------------------
 // messages

@@ -1,0 +1,542 @@
+// The served form: an actor's mailbox (Sec. 3.3: messages are buffered and
+// processed in order of arrival; Sec. 3.4: an OpenCL actor maps its mailbox
+// onto the device's command queue) turned into continuous batching.
+//
+//  * ka_server_submit copies the request's data and appends it to the
+//    mailbox with its arrival time.
+//  * The mailbox thread forms a batch from the oldest waiting requests as soon
+//    as a stream slot is free and the HBM budget admits them (at most
+//    max_batch requests; a request that arrives while batches run waits for
+//    the next slot).  It packs the batch's inputs into one pinned buffer, one
+//    copy to the device, then launches per kind, all on the batch's stream:
+//    the index requests as one batched index build, the scans as one scan of
+//    their concatenation rebased per request, the affine chains as the chain
+//    over their concatenation (an elementwise map needs no per-request work);
+//    the outputs go back in one copy per kind region, then an event.
+//  * The completion thread waits for batches in launch order, splits the
+//    outputs per request, releases device memory and budget, and records
+//    each request's latency from its arrival time.
+// Batches on different streams overlap on the device; max_batch = 1 with one
+// stream is the plain per-request form of the same kernels.
+#include <time.h>
+
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+
+#include "runtime_internal.hpp"
+
+namespace ka {
+
+double clock_us() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return ts.tv_sec * 1e6 + ts.tv_nsec * 1e-3;
+}
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Device bytes a request holds while its batch runs (inputs, outputs and the
+// pipeline's scratch), an upper bound used for admission.
+uint64_t request_bytes(uint32_t kind, uint64_t n) {
+  switch (kind) {
+    case KA_REQ_WAH:
+      // values, tagged keys, sorted pairs, ping-pong pairs, tile offsets,
+      // keys, offsets, 2n words, tables
+      return 4 * n + 4 * n + 8 * n + 8 * n + 4 * n + 4 * n + 4 * n + 8 * n + 64 + n / 8;
+    case KA_REQ_SCAN:
+      return 8 * n + 64;
+    default:
+      return 4 * n + 64;
+  }
+}
+
+}  // namespace
+
+struct SrvReq {
+  virtual ~SrvReq() = default;
+  std::atomic<int> refs{2};  // the caller's handle and the server's
+  uint32_t kind = 0;
+  std::vector<uint32_t> in;
+  double arrival_us = 0;
+  std::vector<uint32_t> out[3];
+  std::mutex mu;
+  std::condition_variable cv;
+  bool done = false;
+  int rc = KA_OK;
+  void finish(int code) {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      rc = code;
+      done = true;
+    }
+    cv.notify_all();
+  }
+  void release() {
+    if (refs.fetch_sub(1) == 1) delete this;
+  }
+};
+
+struct Batch {
+  uint32_t si = 0;
+  hipEvent_t done = nullptr;
+  uint64_t budget = 0;
+  std::vector<SrvReq*> reqs[3];  // by kind
+  uint64_t n[3] = {0, 0, 0};
+  void* d_buf = nullptr;
+  uint64_t d_bytes = 0;
+  void* h_in = nullptr;
+  void* h_out = nullptr;
+  // host output layout
+  uint64_t o_keys = 0, o_offs = 0, o_words = 0, o_ks = 0, o_ws = 0, o_lens = 0, o_scan = 0, o_chain = 0;
+  int rc = KA_OK;
+};
+
+struct Server {
+  System* sys = nullptr;
+  uint32_t streams = 2, max_batch = 1024, value_bits = 12;
+  uint64_t budget = 64ull << 30;
+  std::vector<uint32_t> chain_a, chain_b;
+
+  std::mutex mu;
+  std::condition_variable cv_loop, cv_done;
+  std::deque<SrvReq*> mailbox;
+  std::deque<Batch*> inflight;
+  uint64_t budget_in_use = 0, budget_peak = 0;
+  uint32_t next_stream = 0;
+  bool stop = false;
+  bool loop_done = false;  // the mailbox thread has exited: no batch will be added
+  std::thread loop, completion;
+
+  std::mutex st_mu;
+  std::vector<double> lat_us;
+  uint64_t completed = 0, failed = 0, elements = 0, batches = 0, batched_requests = 0;
+
+  void run_loop();
+  void run_completion();
+  Batch* launch(std::vector<SrvReq*>& take, uint64_t bytes);
+  void complete(Batch* b);
+};
+
+// Packs, copies and launches one batch on its stream; returns it with an
+// event recorded after its output copies (b->rc holds a launch failure).
+Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
+  Batch* b = new Batch();
+  b->budget = bytes;
+  b->si = next_stream;
+  next_stream = (next_stream + 1) % streams;
+  for (auto* r : take) {
+    b->reqs[r->kind].push_back(r);
+    b->n[r->kind] += r->in.size();
+  }
+  const uint64_t nw = b->n[KA_REQ_WAH], ns = b->n[KA_REQ_SCAN], nc = b->n[KA_REQ_CHAIN];
+  const uint32_t rw = (uint32_t)b->reqs[KA_REQ_WAH].size(), rs = (uint32_t)b->reqs[KA_REQ_SCAN].size();
+
+  // ---- device layout: inputs (values by kind, request tables), outputs, lengths ----
+  uint64_t off = 0;
+  auto place = [&](uint64_t bytes_) {
+    const uint64_t o = off;
+    off += align_up(bytes_ ? bytes_ : 4);
+    return o;
+  };
+  const uint64_t d_vw = place(4 * nw), d_vs = place(4 * ns), d_vc = place(4 * nc);
+  const uint64_t d_rw = place(4 * (rw + 1ull)), d_rs = place(4 * (rs + 1ull));
+  const uint64_t in_bytes = off;
+  const uint64_t d_keys = place(4 * nw), d_offs = place(4 * (nw + rw)), d_words = place(8 * nw);
+  const uint64_t d_ks = place(4 * (rw + 1ull)), d_ws = place(4 * (rw + 1ull)), d_lens = place(5 * 8);
+  const uint64_t d_scan = place(4 * ns);
+  const uint64_t total = off;
+  // host output layout: the WAH outputs and lengths in device order, then scan, then chain
+  b->o_keys = 0;
+  b->o_offs = d_offs - d_keys;
+  b->o_words = d_words - d_keys;
+  b->o_ks = d_ks - d_keys;
+  b->o_ws = d_ws - d_keys;
+  b->o_lens = d_lens - d_keys;
+  b->o_scan = d_scan - d_keys;
+  b->o_chain = total - d_keys;
+  const uint64_t out_bytes = b->o_chain + 4 * nc;
+
+  int rc = sys->pool.alloc(total, b->si, &b->d_buf, &b->d_bytes);
+  if (rc) {
+    b->rc = rc;
+    return b;
+  }
+  b->h_in = sys->stage.get(sys, in_bytes);
+  b->h_out = sys->stage.get(sys, std::max<uint64_t>(out_bytes, 4));
+  if (!b->h_in || !b->h_out) {
+    b->rc = set_error(KA_E_OOM, "server: pinned staging");
+    return b;
+  }
+  // ---- pack the inputs ------------------------------------------------------------------
+  char* hi = static_cast<char*>(b->h_in);
+  const uint64_t kind_off[3] = {d_vw, d_vs, d_vc};
+  for (int k = 0; k < 3; ++k) {
+    uint64_t pos = 0;
+    for (auto* r : b->reqs[k]) {
+      std::memcpy(hi + kind_off[k] + 4 * pos, r->in.data(), 4 * r->in.size());
+      pos += r->in.size();
+    }
+  }
+  auto table = [&](int k, uint64_t at) {
+    uint32_t* t = reinterpret_cast<uint32_t*>(hi + at);
+    uint64_t pos = 0;
+    uint32_t j = 0;
+    for (auto* r : b->reqs[k]) {
+      t[j++] = (uint32_t)pos;
+      pos += r->in.size();
+    }
+    t[j] = (uint32_t)pos;
+  };
+  table(KA_REQ_WAH, d_rw);
+  table(KA_REQ_SCAN, d_rs);
+
+  char* dev = static_cast<char*>(b->d_buf);
+  auto u32 = [&](uint64_t o) { return reinterpret_cast<uint32_t*>(dev + o); };
+  {
+    CmdEnv env(sys, b->si);
+    hipStream_t s = env.stream();
+    if (hipMemcpyAsync(dev, b->h_in, in_bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
+      (void)hipGetLastError();
+      b->rc = set_error(KA_E_DEVICE, "server: input copy");
+      return b;
+    }
+    uint64_t* lens = reinterpret_cast<uint64_t*>(dev + d_lens);
+    if (rw)
+      rc = launch_wah_batch(env, u32(d_vw), nw, u32(d_rw), rw, value_bits, u32(d_keys), u32(d_offs), u32(d_words),
+                            u32(d_ks), u32(d_ws), lens, lens + 1, lens + 2, lens + 3, lens + 4);
+    if (!rc && rs) rc = launch_segmented_scan(env, u32(d_vs), u32(d_scan), ns, u32(d_rs), rs);
+    for (size_t i = 0; !rc && nc && i < chain_a.size(); ++i)
+      rc = launch_affine(env, u32(d_vc), nc, nullptr, 0, chain_a[i], chain_b[i]);
+    if (rc) {
+      b->rc = rc;
+      return b;
+    }
+    // outputs back: the WAH and scan region in one copy, the chain region in another
+    hipError_t e = hipMemcpyAsync(b->h_out, dev + d_keys, b->o_chain, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && nc)
+      e = hipMemcpyAsync(static_cast<char*>(b->h_out) + b->o_chain, dev + d_vc, 4 * nc, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) {
+      b->done = sys->get_event(false);
+      e = b->done ? hipEventRecord(b->done, s) : hipErrorOutOfMemory;
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b->rc = set_error(KA_E_DEVICE, "server: output copy");
+    }
+  }
+  return b;
+}
+
+// Splits a finished batch's outputs per request and frees its resources.
+void Server::complete(Batch* b) {
+  if (b->done && hipEventSynchronize(b->done) != hipSuccess) {
+    (void)hipGetLastError();
+    if (!b->rc) b->rc = KA_E_DEVICE;
+  }
+  if (b->rc && hipStreamSynchronize(sys->streams[b->si]->s) != hipSuccess)  // nothing may still read the staging
+    (void)hipGetLastError();
+  const double now = clock_us();
+  const char* ho = static_cast<const char*>(b->h_out);
+  auto u32 = [&](uint64_t o) { return reinterpret_cast<const uint32_t*>(ho + o); };
+  uint64_t lens[5] = {0, 0, 0, 0, 0};
+  if (!b->rc && !b->reqs[KA_REQ_WAH].empty()) {
+    std::memcpy(lens, ho + b->o_lens, sizeof(lens));
+    if (lens[3] == 0) b->rc = KA_E_DEVICE;  // rejected on the device (values are checked at submit)
+  }
+  uint64_t done_ok = 0, done_bad = 0, elems = 0;
+  std::vector<double> lat;
+  for (int k = 0; k < 3; ++k) {
+    uint64_t pos = 0;
+    for (size_t j = 0; j < b->reqs[k].size(); ++j) {
+      SrvReq* r = b->reqs[k][j];
+      const uint64_t n = r->in.size();
+      if (!b->rc) {
+        if (k == KA_REQ_WAH) {
+          const uint32_t* ks = u32(b->o_ks);
+          const uint32_t* ws = u32(b->o_ws);
+          const uint32_t k0 = ks[j], k1 = ks[j + 1], w0 = ws[j], w1 = ws[j + 1];
+          r->out[0].assign(u32(b->o_keys) + k0, u32(b->o_keys) + k1);
+          r->out[1].assign(u32(b->o_offs) + k0 + j, u32(b->o_offs) + k1 + j + 1);
+          r->out[2].assign(u32(b->o_words) + w0, u32(b->o_words) + w1);
+        } else {
+          const uint64_t base = k == KA_REQ_SCAN ? b->o_scan : b->o_chain;
+          r->out[0].assign(u32(base) + pos, u32(base) + pos + n);
+        }
+        ++done_ok;
+        elems += n;
+        lat.push_back(now - r->arrival_us);
+      } else {
+        ++done_bad;
+      }
+      pos += n;
+      r->in.clear();
+      r->in.shrink_to_fit();
+      r->finish(b->rc ? b->rc : KA_OK);
+      r->release();
+    }
+  }
+  if (b->d_buf) sys->pool.release(b->d_buf, b->d_bytes, b->si, 1ull << b->si);
+  if (b->h_in) sys->stage.give_back(b->h_in);
+  if (b->h_out) sys->stage.give_back(b->h_out);
+  if (b->done) sys->put_event(b->done);
+  {
+    std::lock_guard<std::mutex> g(st_mu);
+    completed += done_ok;
+    failed += done_bad;
+    elements += elems;
+    batches += 1;
+    batched_requests += done_ok + done_bad;
+    lat_us.insert(lat_us.end(), lat.begin(), lat.end());
+  }
+  delete b;
+}
+
+void Server::run_loop() {
+  (void)sys->use_device();
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_loop.wait(lk, [&] { return stop || (!mailbox.empty() && inflight.size() < streams); });
+    if (stop) break;
+    // admission: the oldest requests, while the budget holds them (one request
+    // is admitted whenever nothing else holds memory)
+    std::vector<SrvReq*> take;
+    uint64_t bytes = 0;
+    while (!mailbox.empty() && take.size() < max_batch) {
+      SrvReq* r = mailbox.front();
+      const uint64_t need = request_bytes(r->kind, r->in.size());
+      if (budget_in_use + bytes + need > budget && !(take.empty() && budget_in_use == 0)) break;
+      take.push_back(r);
+      bytes += need;
+      mailbox.pop_front();
+    }
+    if (take.empty()) {  // wait for memory to be freed
+      cv_loop.wait(lk, [&] { return stop || inflight.empty() || budget_in_use == 0; });
+      continue;
+    }
+    budget_in_use += bytes;
+    budget_peak = std::max(budget_peak, budget_in_use);
+    lk.unlock();
+    Batch* b = launch(take, bytes);
+    lk.lock();
+    inflight.push_back(b);
+    cv_done.notify_all();
+  }
+  loop_done = true;
+  cv_done.notify_all();
+}
+
+void Server::run_completion() {
+  (void)sys->use_device();
+  for (;;) {
+    Batch* b = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_done.wait(lk, [&] { return !inflight.empty() || loop_done; });
+      if (inflight.empty()) break;
+      b = inflight.front();
+    }
+    const uint64_t bytes = b->budget;
+    complete(b);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      inflight.pop_front();
+      budget_in_use -= bytes;
+    }
+    cv_loop.notify_all();
+  }
+}
+
+}  // namespace ka
+
+using namespace ka;
+
+struct ka_server : Server {};
+struct ka_srv_req : SrvReq {};
+
+#define KA_GUARD_BEGIN try {
+#define KA_GUARD_END                                              \
+  }                                                               \
+  catch (const std::bad_alloc&) {                                 \
+    return set_error(KA_E_OOM, "host allocation failed");         \
+  }                                                               \
+  catch (...) {                                                   \
+    return set_error(KA_E_DEVICE, "internal error");              \
+  }
+
+KA_API int ka_server_clock_us(double* now) {
+  if (!now) return set_error(KA_E_ARG, "null argument");
+  *now = clock_us();
+  return KA_OK;
+}
+
+KA_API int ka_server_create(ka_system* sys, const ka_server_config* cfg, ka_server** out) {
+  KA_GUARD_BEGIN
+  if (!sys || !out) return set_error(KA_E_ARG, "null argument");
+  int rc = sys->ensure_init();
+  if (rc) return rc;
+  ka_server* s = new ka_server();
+  s->sys = sys;
+  const uint32_t want = cfg && cfg->streams ? cfg->streams : 2;
+  s->streams = std::max<uint32_t>(1, std::min<uint32_t>(want, (uint32_t)sys->streams.size()));
+  s->max_batch = cfg && cfg->max_batch ? cfg->max_batch : 1024;
+  s->budget = cfg && cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (64ull << 30);
+  s->value_bits = cfg && cfg->value_bits ? cfg->value_bits : 12;
+  const uint32_t req_bits = s->max_batch > 1 ? 32u - (uint32_t)__builtin_clz(s->max_batch - 1) : 0u;
+  if (s->value_bits > 32 || s->value_bits + req_bits > 32) {
+    delete s;
+    return set_error(KA_E_ARG, "value_bits + bits of max_batch - 1 exceed 32");
+  }
+  const uint32_t len = cfg && cfg->chain_len ? cfg->chain_len : 0;
+  if (len && (!cfg->chain_a || !cfg->chain_b)) {
+    delete s;
+    return set_error(KA_E_ARG, "chain parameters missing");
+  }
+  for (uint32_t i = 0; i < len; ++i) {
+    s->chain_a.push_back(cfg->chain_a[i]);
+    s->chain_b.push_back(cfg->chain_b[i]);
+  }
+  sys->retain();
+  s->loop = std::thread([s] { s->run_loop(); });
+  s->completion = std::thread([s] { s->run_completion(); });
+  *out = s;
+  return KA_OK;
+  KA_GUARD_END
+}
+
+KA_API int ka_server_submit(ka_server* srv, uint32_t kind, const uint32_t* data, uint64_t n, double arrival_us,
+                            ka_srv_req** out) {
+  KA_GUARD_BEGIN
+  if (!srv || !out || (n && !data)) return set_error(KA_E_ARG, "null argument");
+  if (kind > KA_REQ_CHAIN) return set_error(KA_E_ARG, "unknown request kind");
+  if (n >= (1ull << 30)) return set_error(KA_E_ARG, "n must be below 2^30");
+  if (request_bytes(kind, n) > srv->budget) return set_error(KA_E_BUDGET, "request larger than the server budget");
+  if (kind == KA_REQ_WAH && srv->value_bits < 32) {
+    uint32_t over = 0;
+    for (uint64_t i = 0; i < n; ++i) over |= data[i] >> srv->value_bits;
+    if (over) return set_error(KA_E_ARG, "an index value is at or above 2^value_bits");
+  }
+  ka_srv_req* r = new ka_srv_req();
+  r->kind = kind;
+  r->in.assign(data, data + n);
+  r->arrival_us = arrival_us > 0 ? arrival_us : clock_us();
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (srv->stop) {
+      delete r;
+      return set_error(KA_E_STATE, "server is shutting down");
+    }
+    srv->mailbox.push_back(r);
+  }
+  srv->cv_loop.notify_all();
+  *out = r;
+  return KA_OK;
+  KA_GUARD_END
+}
+
+KA_API int ka_server_wait(ka_srv_req* req, int64_t timeout_us) {
+  if (!req) return set_error(KA_E_ARG, "null request");
+  std::unique_lock<std::mutex> lk(req->mu);
+  if (timeout_us < 0) {
+    req->cv.wait(lk, [&] { return req->done; });
+  } else if (!req->cv.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return req->done; })) {
+    return set_error(KA_E_TIMEOUT, "request not finished");
+  }
+  if (req->rc) return set_error(req->rc, "request failed");
+  return KA_OK;
+}
+
+KA_API int ka_server_result(ka_srv_req* req, uint32_t i, uint32_t* host, uint64_t cap, uint64_t* count) {
+  if (!req || !count) return set_error(KA_E_ARG, "null argument");
+  {
+    std::lock_guard<std::mutex> g(req->mu);
+    if (!req->done) return set_error(KA_E_STATE, "request not finished");
+    if (req->rc) return set_error(req->rc, "request failed");
+  }
+  const uint32_t outs = req->kind == KA_REQ_WAH ? 3 : 1;
+  if (i >= outs) return set_error(KA_E_ARG, "no such output");
+  const auto& v = req->out[i];
+  *count = v.size();
+  if (!host) return KA_OK;
+  if (cap < v.size()) return set_error(KA_E_ARG, "buffer too small");
+  if (!v.empty()) std::memcpy(host, v.data(), 4 * v.size());
+  return KA_OK;
+}
+
+KA_API int ka_server_request_release(ka_srv_req* req) {
+  if (!req) return set_error(KA_E_ARG, "null request");
+  req->release();
+  return KA_OK;
+}
+
+KA_API int ka_server_get_stats(ka_server* srv, ka_server_stats* out) {
+  if (!srv || !out) return set_error(KA_E_ARG, "null argument");
+  std::vector<double> lat;
+  ka_server_stats st{};
+  {
+    std::lock_guard<std::mutex> g(srv->st_mu);
+    lat = srv->lat_us;
+    st.completed = srv->completed;
+    st.failed = srv->failed;
+    st.elements = srv->elements;
+    st.batches = srv->batches;
+    st.mean_batch = srv->batches ? (double)srv->batched_requests / srv->batches : 0.0;
+  }
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    st.queued = srv->mailbox.size();
+    st.budget_in_use = srv->budget_in_use;
+    st.budget_peak = srv->budget_peak;
+  }
+  if (!lat.empty()) {
+    std::sort(lat.begin(), lat.end());
+    auto pct = [&](double p) { return lat[std::min<size_t>(lat.size() - 1, (size_t)(p * (lat.size() - 1) + 0.5))]; };
+    st.p50_us = pct(0.50);
+    st.p99_us = pct(0.99);
+    st.max_us = lat.back();
+    double s = 0;
+    for (double x : lat) s += x;
+    st.mean_us = s / lat.size();
+  }
+  *out = st;
+  return KA_OK;
+}
+
+KA_API int ka_server_reset_stats(ka_server* srv) {
+  if (!srv) return set_error(KA_E_ARG, "null argument");
+  std::lock_guard<std::mutex> g(srv->st_mu);
+  srv->lat_us.clear();
+  srv->completed = srv->failed = srv->elements = srv->batches = srv->batched_requests = 0;
+  {
+    std::lock_guard<std::mutex> g2(srv->mu);
+    srv->budget_peak = srv->budget_in_use;
+  }
+  return KA_OK;
+}
+
+KA_API int ka_server_destroy(ka_server* srv) {
+  if (!srv) return set_error(KA_E_ARG, "null server");
+  std::deque<SrvReq*> cancelled;
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    srv->stop = true;
+    cancelled.swap(srv->mailbox);
+  }
+  srv->cv_loop.notify_all();
+  srv->cv_done.notify_all();
+  if (srv->loop.joinable()) srv->loop.join();  // no batch is launched after this
+  srv->cv_done.notify_all();
+  if (srv->completion.joinable()) srv->completion.join();  // in-flight batches finish first
+  for (auto* r : cancelled) {
+    r->finish(KA_E_CANCELLED);
+    r->release();
+  }
+  System* sys = srv->sys;
+  delete srv;
+  sys->release();
+  return KA_OK;
+}

@@ -235,3 +235,67 @@ def sig_out(mode=KA_REF, count=0):
 
 
 __all__ = ["Session", "sig_in", "sig_out", "val", "ref", "KA_VAL", "KA_REF"]
+
+
+class Server:
+    """The served form (ka_server_*): submit requests, wait for them, read
+    their outputs and the latency statistics."""
+
+    def __init__(self, session: Session, streams: int = 2, max_batch: int = 0, budget_bytes: int = 0,
+                 value_bits: int = 12, chain_a=None, chain_b=None):
+        from . import ka_server_config
+        cfg = ka_server_config()
+        cfg.streams = streams
+        cfg.max_batch = max_batch
+        cfg.hbm_budget_bytes = budget_bytes
+        cfg.value_bits = value_bits
+        self._a = np.ascontiguousarray(chain_a if chain_a is not None else [], dtype=np.uint32)
+        self._b = np.ascontiguousarray(chain_b if chain_b is not None else [], dtype=np.uint32)
+        cfg.chain_len = self._a.size
+        if self._a.size:
+            cfg.chain_a = self._a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+            cfg.chain_b = self._b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        self.srv = c_void_p()
+        check(lib.ka_server_create(session.sys, byref(cfg), byref(self.srv)), "ka_server_create")
+
+    @staticmethod
+    def clock_us() -> float:
+        t = ctypes.c_double()
+        check(lib.ka_server_clock_us(byref(t)), "ka_server_clock_us")
+        return t.value
+
+    def submit(self, kind: int, data: np.ndarray, arrival_us: float = 0.0):
+        d = np.ascontiguousarray(data, dtype=np.uint32)
+        r = c_void_p()
+        check(lib.ka_server_submit(self.srv, kind, d.ctypes.data if d.size else None, d.size, arrival_us, byref(r)),
+              "ka_server_submit")
+        return r
+
+    def wait(self, req, timeout_us: int = -1) -> int:
+        return lib.ka_server_wait(req, timeout_us)
+
+    def result(self, req, i: int = 0) -> np.ndarray:
+        n = ctypes.c_uint64()
+        check(lib.ka_server_result(req, i, None, 0, byref(n)), "ka_server_result")
+        out = np.empty(n.value, dtype=np.uint32)
+        check(lib.ka_server_result(req, i, out.ctypes.data if out.size else None, out.size, byref(n)),
+              "ka_server_result")
+        return out
+
+    def release(self, req):
+        check(lib.ka_server_request_release(req), "ka_server_request_release")
+
+    def stats(self):
+        from . import ka_server_stats
+        st = ka_server_stats()
+        check(lib.ka_server_get_stats(self.srv, byref(st)), "ka_server_get_stats")
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def reset_stats(self):
+        check(lib.ka_server_reset_stats(self.srv), "ka_server_reset_stats")
+
+    def close(self):
+        if self.srv:
+            check(lib.ka_server_destroy(self.srv), "ka_server_destroy")
+            self.srv = None
+

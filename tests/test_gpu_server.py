@@ -1,0 +1,137 @@
+"""GPU tests of the served form (ka_server_*): a mix of index, scan and
+affine-chain requests submitted together is batched, and every result equals
+both the oracle's and the result of the same request served alone (a server
+with batching off), bit for bit.  Inputs: workloads.served_requests /
+served_payload (the served mix) at sizes small enough for the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sess():
+    from paper_1709_07781_amd.session import Session
+    s = Session(n_streams=4)
+    yield s
+    s.close()
+
+
+def _chain():
+    return workloads.chain_params()
+
+
+def _expected(ora, kind, x, a, b):
+    if kind == workloads.KIND_WAH:
+        return ora.wah_index(x)
+    if kind == workloads.KIND_SCAN:
+        return (ora.exclusive_scan(x),)
+    return (ora.affine_chain(x, a, b),)
+
+
+def _results(srv, req, kind):
+    return tuple(srv.result(req, i) for i in range(3 if kind == workloads.KIND_WAH else 1))
+
+
+def _mix(count, seed, lo=4, hi=14):
+    _, sizes, kinds, dseeds = workloads.served_requests(seed=seed, count=count, lo_log2=lo, hi_log2=hi)
+    return [(int(k), workloads.served_payload(int(k), int(s), int(d))) for k, s, d in zip(kinds, sizes, dseeds)]
+
+
+def test_mix_equals_alone_and_oracle(sess):
+    from paper_1709_07781_amd.session import Server
+    a, b = _chain()
+    ora = oracle.default()
+    reqs = _mix(120, seed=61)
+    reqs += [(workloads.KIND_WAH, np.zeros(0, np.uint32)), (workloads.KIND_SCAN, np.zeros(0, np.uint32)),
+             (workloads.KIND_CHAIN, np.zeros(0, np.uint32)), (workloads.KIND_WAH, np.array([4095], np.uint32))]
+    mixed = Server(sess, streams=3, max_batch=64, chain_a=a, chain_b=b)
+    alone = Server(sess, streams=1, max_batch=1, chain_a=a, chain_b=b)
+    try:
+        hm = [mixed.submit(k, x) for k, x in reqs]  # all queued at once: batched
+        for k, x in reqs:  # the same requests one at a time
+            h = alone.submit(k, x)
+            assert alone.wait(h) == 0
+            r_alone = _results(alone, h, k)
+            alone.release(h)
+            exp = _expected(ora, k, x, a, b)
+            for got, e in zip(r_alone, exp):
+                np.testing.assert_array_equal(got, e)
+        for (k, x), h in zip(reqs, hm):
+            assert mixed.wait(h) == 0
+            got = _results(mixed, h, k)
+            mixed.release(h)
+            for g, e in zip(got, _expected(ora, k, x, a, b)):
+                np.testing.assert_array_equal(g, e)
+        st = mixed.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+        assert st["mean_batch"] > 1.0  # requests were merged
+        assert 0 < st["p50_us"] <= st["p99_us"] <= st["max_us"]
+        assert alone.stats()["mean_batch"] == 1.0
+    finally:
+        mixed.close()
+        alone.close()
+
+
+def test_budget_admission_and_rejection(sess):
+    """A budget that holds about one request at a time still serves them all;
+    a request larger than the budget is refused at submission."""
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import Server
+    a, b = _chain()
+    srv = Server(sess, streams=2, max_batch=32, budget_bytes=48 * 20_000, chain_a=a, chain_b=b)
+    ora = oracle.default()
+    try:
+        reqs = [(workloads.KIND_WAH, workloads.uniform_values(70 + i, 15_000, 4096)) for i in range(6)]
+        hs = [srv.submit(k, x) for k, x in reqs]
+        for (k, x), h in zip(reqs, hs):
+            assert srv.wait(h) == 0
+            got = _results(srv, h, k)
+            srv.release(h)
+            for g, e in zip(got, ora.wah_index(x)):
+                np.testing.assert_array_equal(g, e)
+        st = srv.stats()
+        assert st["budget_peak"] <= 48 * 20_000 and st["mean_batch"] <= 1.5
+        with pytest.raises(ka.KaError) as e:
+            srv.submit(workloads.KIND_WAH, workloads.uniform_values(79, 30_000, 4096))
+        assert e.value.code == ka.KA_E_BUDGET
+    finally:
+        srv.close()
+
+
+def test_value_bits_checked_at_submit(sess):
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import Server
+    srv = Server(sess)
+    try:
+        with pytest.raises(ka.KaError) as e:
+            srv.submit(workloads.KIND_WAH, np.array([1, 2, 4096], np.uint32))
+        assert e.value.code == ka.KA_E_ARG
+    finally:
+        srv.close()
+
+
+def test_destroy_cancels_or_finishes_everything(sess):
+    """Destroying a server with a full mailbox ends every request: finished
+    (with the right result) or cancelled."""
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd import lib
+    from paper_1709_07781_amd.session import Server
+    a, b = _chain()
+    srv = Server(sess, streams=1, max_batch=2, chain_a=a, chain_b=b)
+    reqs = [(workloads.KIND_SCAN, workloads.u32(90 + i, 50_000)) for i in range(40)]
+    hs = [srv.submit(k, x) for k, x in reqs]
+    srv.close()
+    ora = oracle.default()
+    done = 0
+    for (k, x), h in zip(reqs, hs):
+        rc = lib.ka_server_wait(h, 10_000_000)
+        assert rc in (0, ka.KA_E_CANCELLED)
+        if rc == 0:
+            np.testing.assert_array_equal(srv.result(h, 0), ora.exclusive_scan(x))
+            done += 1
+        lib.ka_server_request_release(h)
+    assert done >= 1
