@@ -175,6 +175,81 @@ def bench_batched(args) -> int:
     return 0 if parity in (None, "bit-exact (requests sampled)") else 1
 
 
+def bench_served(args) -> int:
+    """The served mix at each rate: request j arrives at its scheduled Poisson
+    time (sizes log-uniform in [2^8, 2^22], 40% index of values below 2^12,
+    30% scan, 30% 8-stage affine chain); latency runs from the scheduled
+    arrival to completion seen on the host.  The batched server (continuous
+    batching, 3 streams, 64 GiB budget) against the plain server (one request
+    at a time, same kernels)."""
+    import torch
+    from paper_1709_07781_amd.session import Server, Session
+    import workloads
+
+    torch.cuda.set_device(0)
+    sess = Session(n_streams=4)
+    a, b = workloads.chain_params()
+    # payloads are slices of two pre-generated pools (values below 2^12 for
+    # the index requests, full 32-bit values for the others)
+    pool_n = 1 << 23
+    pool_idx = workloads.uniform_values(workloads.derive(5, 10), pool_n, 1 << 12)
+    pool_u32 = workloads.u32(workloads.derive(5, 11), pool_n)
+    rates = [float(r) for r in args.rates.split(",") if r]
+    rows = []
+    for rate in rates:
+        count = int(min(args.served_max, max(50, rate * args.served_seconds)))
+        t, sizes, kinds, dseeds = workloads.served_requests(seed=5, count=count, rate_per_s=rate)
+        sizes = np.minimum(sizes, pool_n)
+        starts = (dseeds % np.uint64(pool_n)).astype(np.int64)
+        starts = np.minimum(starts, pool_n - sizes)
+        res = {"rate_per_s": rate, "requests": count}
+        for form, kw in (("batched", dict(streams=3, max_batch=1024)), ("plain", dict(streams=1, max_batch=1))):
+            srv = Server(sess, chain_a=a, chain_b=b, **kw)
+            handles = []
+            t0 = Server.clock_us() + 20_000.0  # first arrival 20 ms from now
+            w0 = time.perf_counter()
+            for j in range(count):
+                due = t0 + t[j] * 1e6
+                while True:
+                    now = Server.clock_us()
+                    if now >= due:
+                        break
+                    if due - now > 200:
+                        time.sleep((due - now - 100) * 1e-6)
+                pool = pool_idx if kinds[j] == workloads.KIND_WAH else pool_u32
+                handles.append(srv.submit(int(kinds[j]), pool[starts[j]:starts[j] + sizes[j]], arrival_us=due))
+            for h in handles:
+                rc = srv.wait(h)
+                if rc != 0:
+                    raise RuntimeError(f"served request failed: {rc}")
+                srv.release(h)
+            wall = time.perf_counter() - w0
+            st = srv.stats()
+            srv.close()
+            span_s = max(wall - 0.02, 1e-9)
+            res[form] = {"p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3, "max_ms": st["max_us"] / 1e3,
+                         "elements_per_s": st["elements"] / span_s, "requests_per_s": st["completed"] / span_s,
+                         "mean_batch": st["mean_batch"], "batches": st["batches"]}
+            log(f"[bench] served rate={rate:.0f}/s {form}: p50={res[form]['p50_ms']:.2f} ms "
+                f"p99={res[form]['p99_ms']:.2f} ms, {res[form]['requests_per_s']:.0f} req/s, "
+                f"batch={st['mean_batch']:.1f}")
+        rows.append(res)
+    sess.close()
+    top = max(rows, key=lambda r: r["batched"]["elements_per_s"])
+    out = {
+        "metric": METRIC, "value": top["batched"]["elements_per_s"], "unit": "elements/s", "n_gpus": 1,
+        "steps": len(rates), "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "served: Poisson arrivals, sizes log-uniform in [2^8, 2^22], 40% WAH index "
+                               "(values below 2^12) / 30% exclusive scan / 30% 8-stage affine chain, host data, "
+                               "latency from the scheduled arrival to completion on the host",
+                   "rates": rates, "budget_bytes": 64 << 30},
+        "served": rows,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,9 +259,16 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--workload", choices=("large", "batched"), default="large",
+    ap.add_argument("--workload", choices=("large", "batched", "served"), default="large",
                     help="large: the 2^26 Zipf request (default); batched: 4096 requests of 2^10..2^20 values, "
-                         "one batched pass against 4096 plain per-request pipelines")
+                         "one batched pass against 4096 plain per-request pipelines; served: Poisson arrivals of "
+                         "the 40/30/30 index/scan/chain mix at several rates, batched server against the plain "
+                         "one-request-at-a-time server")
+    ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000",
+                    help="served: arrival rates in requests/s")
+    ap.add_argument("--served-seconds", type=float, default=2.0,
+                    help="served: seconds of arrivals per rate (at most --served-max requests)")
+    ap.add_argument("--served-max", type=int, default=4000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run the in-place affine kernel over 2^n words 3 times "
                          "(a plain copy of known size, for scaling the HBM counters)")
@@ -197,6 +279,8 @@ def main() -> int:
         return 2
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
 
     import torch
     import paper_1709_07781_amd as ka

@@ -337,6 +337,7 @@ typedef struct ka_server_config {
   uint32_t streams;          /* batches in flight at once, one per system stream (0 = 2; at most
                                 the system's n_streams) */
   uint32_t max_batch;        /* requests merged into one batch (0 = 1024; 1 = no batching) */
+  uint64_t max_batch_bytes;  /* input bytes merged into one batch (0 = 64 MiB; a larger request runs alone) */
   uint64_t hbm_budget_bytes; /* device memory the server's batches may hold together (0 = 64 GiB) */
   uint32_t value_bits;       /* index requests: every value below 2^value_bits (0 = 12) */
   uint32_t chain_len;        /* affine chain stages and their parameters (a_i odd) */
@@ -377,6 +378,9 @@ KA_API int ka_server_wait(ka_srv_req* req, int64_t timeout_us);
 /* Output i of a finished request: *count elements, copied to host[0..cap)
  * when host is given (KA_E_ARG if cap is too small). */
 KA_API int ka_server_result(ka_srv_req* req, uint32_t i, uint32_t* host, uint64_t cap, uint64_t* count);
+/* Releases a request handle (its outputs live in pinned host memory shared
+ * with its batch until every request of the batch is released).  Release
+ * requests before destroying the system. */
 KA_API int ka_server_request_release(ka_srv_req* req);
 KA_API int ka_server_get_stats(ka_server* srv, ka_server_stats* out);
 KA_API int ka_server_reset_stats(ka_server* srv);

@@ -87,7 +87,8 @@ class ka_wah_batch_result(ctypes.Structure):
 
 
 class ka_server_config(ctypes.Structure):
-    _fields_ = [("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
+    _fields_ = [("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("max_batch_bytes", ctypes.c_uint64),
+                ("hbm_budget_bytes", ctypes.c_uint64),
                 ("value_bits", ctypes.c_uint32), ("chain_len", ctypes.c_uint32),
                 ("chain_a", ctypes.POINTER(ctypes.c_uint32)), ("chain_b", ctypes.POINTER(ctypes.c_uint32))]
 

@@ -2,20 +2,24 @@
 // processed in order of arrival; Sec. 3.4: an OpenCL actor maps its mailbox
 // onto the device's command queue) turned into continuous batching.
 //
-//  * ka_server_submit copies the request's data and appends it to the
-//    mailbox with its arrival time.
+//  * ka_server_submit copies the request's data into pinned host memory
+//    (recycled by size class) and appends it to the mailbox with its arrival
+//    time.
 //  * The mailbox thread forms a batch from the oldest waiting requests as soon
 //    as a stream slot is free and the HBM budget admits them (at most
-//    max_batch requests; a request that arrives while batches run waits for
-//    the next slot).  It packs the batch's inputs into one pinned buffer, one
-//    copy to the device, then launches per kind, all on the batch's stream:
+//    max_batch requests and max_batch_bytes of input; a request that arrives
+//    while batches run waits for the next slot).  Each request's data is
+//    copied straight from its pinned buffer to its place in the batch's
+//    device layout, then the kernels run per kind, all on the batch's stream:
 //    the index requests as one batched index build, the scans as one scan of
 //    their concatenation rebased per request, the affine chains as the chain
 //    over their concatenation (an elementwise map needs no per-request work);
-//    the outputs go back in one copy per kind region, then an event.
-//  * The completion thread waits for batches in launch order, splits the
-//    outputs per request, releases device memory and budget, and records
-//    each request's latency from its arrival time.
+//    the outputs go back to one pinned buffer, then an event.
+//  * The completion thread waits for batches in launch order, points each
+//    request at its slices of the batch's pinned outputs (no copy; the buffer
+//    is recycled once every request of the batch is released), releases
+//    device memory and budget, and records each request's latency from its
+//    arrival time.
 // Batches on different streams overlap on the device; max_batch = 1 with one
 // stream is the plain per-request form of the same kernels.
 #include <time.h>
@@ -57,13 +61,33 @@ uint64_t request_bytes(uint32_t kind, uint64_t n) {
 
 }  // namespace
 
+// Pinned output buffer of one batch, shared by its requests.
+struct OutBuf {
+  System* sys = nullptr;
+  void* p = nullptr;
+  std::atomic<int> refs{0};
+  void release() {
+    if (refs.fetch_sub(1) == 1) {
+      if (p) sys->stage.give_back(p);
+      delete this;
+    }
+  }
+};
+
 struct SrvReq {
-  virtual ~SrvReq() = default;
+  virtual ~SrvReq() {
+    if (pin) sys->stage.give_back(pin);
+    if (outbuf) outbuf->release();
+  }
   std::atomic<int> refs{2};  // the caller's handle and the server's
+  System* sys = nullptr;
   uint32_t kind = 0;
-  std::vector<uint32_t> in;
+  uint64_t n = 0;
+  void* pin = nullptr;  // the input, pinned
   double arrival_us = 0;
-  std::vector<uint32_t> out[3];
+  OutBuf* outbuf = nullptr;  // outputs: slices of the batch's pinned buffer
+  const uint32_t* out[3] = {nullptr, nullptr, nullptr};
+  uint64_t out_n[3] = {0, 0, 0};
   std::mutex mu;
   std::condition_variable cv;
   bool done = false;
@@ -89,8 +113,8 @@ struct Batch {
   uint64_t n[3] = {0, 0, 0};
   void* d_buf = nullptr;
   uint64_t d_bytes = 0;
-  void* h_in = nullptr;
-  void* h_out = nullptr;
+  void* h_tab = nullptr;  // pinned request tables
+  OutBuf* out = nullptr;
   // host output layout
   uint64_t o_keys = 0, o_offs = 0, o_words = 0, o_ks = 0, o_ws = 0, o_lens = 0, o_scan = 0, o_chain = 0;
   int rc = KA_OK;
@@ -100,6 +124,7 @@ struct Server {
   System* sys = nullptr;
   uint32_t streams = 2, max_batch = 1024, value_bits = 12;
   uint64_t budget = 64ull << 30;
+  uint64_t max_batch_bytes = 64ull << 20;
   std::vector<uint32_t> chain_a, chain_b;
 
   std::mutex mu;
@@ -131,7 +156,7 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
   next_stream = (next_stream + 1) % streams;
   for (auto* r : take) {
     b->reqs[r->kind].push_back(r);
-    b->n[r->kind] += r->in.size();
+    b->n[r->kind] += r->n;
   }
   const uint64_t nw = b->n[KA_REQ_WAH], ns = b->n[KA_REQ_SCAN], nc = b->n[KA_REQ_CHAIN];
   const uint32_t rw = (uint32_t)b->reqs[KA_REQ_WAH].size(), rs = (uint32_t)b->reqs[KA_REQ_SCAN].size();
@@ -145,7 +170,6 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
   };
   const uint64_t d_vw = place(4 * nw), d_vs = place(4 * ns), d_vc = place(4 * nc);
   const uint64_t d_rw = place(4 * (rw + 1ull)), d_rs = place(4 * (rs + 1ull));
-  const uint64_t in_bytes = off;
   const uint64_t d_keys = place(4 * nw), d_offs = place(4 * (nw + rw)), d_words = place(8 * nw);
   const uint64_t d_ks = place(4 * (rw + 1ull)), d_ws = place(4 * (rw + 1ull)), d_lens = place(5 * 8);
   const uint64_t d_scan = place(4 * ns);
@@ -166,41 +190,47 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
     b->rc = rc;
     return b;
   }
-  b->h_in = sys->stage.get(sys, in_bytes);
-  b->h_out = sys->stage.get(sys, std::max<uint64_t>(out_bytes, 4));
-  if (!b->h_in || !b->h_out) {
+  b->h_tab = sys->stage.get(sys, 4 * (rw + 1ull) + 4 * (rs + 1ull));
+  b->out = new OutBuf();
+  b->out->sys = sys;
+  b->out->p = sys->stage.get(sys, std::max<uint64_t>(out_bytes, 4));
+  if (!b->h_tab || !b->out->p) {
     b->rc = set_error(KA_E_OOM, "server: pinned staging");
     return b;
   }
-  // ---- pack the inputs ------------------------------------------------------------------
-  char* hi = static_cast<char*>(b->h_in);
-  const uint64_t kind_off[3] = {d_vw, d_vs, d_vc};
-  for (int k = 0; k < 3; ++k) {
-    uint64_t pos = 0;
-    for (auto* r : b->reqs[k]) {
-      std::memcpy(hi + kind_off[k] + 4 * pos, r->in.data(), 4 * r->in.size());
-      pos += r->in.size();
-    }
-  }
-  auto table = [&](int k, uint64_t at) {
-    uint32_t* t = reinterpret_cast<uint32_t*>(hi + at);
+  // ---- request tables -----------------------------------------------------------------
+  uint32_t* tab = static_cast<uint32_t*>(b->h_tab);
+  auto table = [&](int k, uint32_t* t) {
     uint64_t pos = 0;
     uint32_t j = 0;
     for (auto* r : b->reqs[k]) {
       t[j++] = (uint32_t)pos;
-      pos += r->in.size();
+      pos += r->n;
     }
     t[j] = (uint32_t)pos;
   };
-  table(KA_REQ_WAH, d_rw);
-  table(KA_REQ_SCAN, d_rs);
+  table(KA_REQ_WAH, tab);
+  table(KA_REQ_SCAN, tab + rw + 1);
 
   char* dev = static_cast<char*>(b->d_buf);
   auto u32 = [&](uint64_t o) { return reinterpret_cast<uint32_t*>(dev + o); };
   {
     CmdEnv env(sys, b->si);
     hipStream_t s = env.stream();
-    if (hipMemcpyAsync(dev, b->h_in, in_bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
+    // each request's data from its pinned buffer to its place; then the tables
+    hipError_t e = hipSuccess;
+    const uint64_t kind_off[3] = {d_vw, d_vs, d_vc};
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+      uint64_t pos = 0;
+      for (auto* r : b->reqs[k]) {
+        if (r->n && e == hipSuccess)
+          e = hipMemcpyAsync(dev + kind_off[k] + 4 * pos, r->pin, 4 * r->n, hipMemcpyHostToDevice, s);
+        pos += r->n;
+      }
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(dev + d_rw, tab, 4 * (rw + 1ull), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dev + d_rs, tab + rw + 1, 4 * (rs + 1ull), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
       (void)hipGetLastError();
       b->rc = set_error(KA_E_DEVICE, "server: input copy");
       return b;
@@ -217,9 +247,9 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
       return b;
     }
     // outputs back: the WAH and scan region in one copy, the chain region in another
-    hipError_t e = hipMemcpyAsync(b->h_out, dev + d_keys, b->o_chain, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(b->out->p, dev + d_keys, b->o_chain, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && nc)
-      e = hipMemcpyAsync(static_cast<char*>(b->h_out) + b->o_chain, dev + d_vc, 4 * nc, hipMemcpyDeviceToHost, s);
+      e = hipMemcpyAsync(static_cast<char*>(b->out->p) + b->o_chain, dev + d_vc, 4 * nc, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) {
       b->done = sys->get_event(false);
       e = b->done ? hipEventRecord(b->done, s) : hipErrorOutOfMemory;
@@ -241,7 +271,8 @@ void Server::complete(Batch* b) {
   if (b->rc && hipStreamSynchronize(sys->streams[b->si]->s) != hipSuccess)  // nothing may still read the staging
     (void)hipGetLastError();
   const double now = clock_us();
-  const char* ho = static_cast<const char*>(b->h_out);
+  if (b->out) b->out->refs.fetch_add(1);  // the batch's own hold while requests are finished
+  const char* ho = b->out && b->out->p ? static_cast<const char*>(b->out->p) : nullptr;
   auto u32 = [&](uint64_t o) { return reinterpret_cast<const uint32_t*>(ho + o); };
   uint64_t lens[5] = {0, 0, 0, 0, 0};
   if (!b->rc && !b->reqs[KA_REQ_WAH].empty()) {
@@ -254,19 +285,24 @@ void Server::complete(Batch* b) {
     uint64_t pos = 0;
     for (size_t j = 0; j < b->reqs[k].size(); ++j) {
       SrvReq* r = b->reqs[k][j];
-      const uint64_t n = r->in.size();
+      const uint64_t n = r->n;
       if (!b->rc) {
         if (k == KA_REQ_WAH) {
           const uint32_t* ks = u32(b->o_ks);
           const uint32_t* ws = u32(b->o_ws);
           const uint32_t k0 = ks[j], k1 = ks[j + 1], w0 = ws[j], w1 = ws[j + 1];
-          r->out[0].assign(u32(b->o_keys) + k0, u32(b->o_keys) + k1);
-          r->out[1].assign(u32(b->o_offs) + k0 + j, u32(b->o_offs) + k1 + j + 1);
-          r->out[2].assign(u32(b->o_words) + w0, u32(b->o_words) + w1);
+          r->out[0] = u32(b->o_keys) + k0;
+          r->out_n[0] = k1 - k0;
+          r->out[1] = u32(b->o_offs) + k0 + j;
+          r->out_n[1] = k1 - k0 + 1;
+          r->out[2] = u32(b->o_words) + w0;
+          r->out_n[2] = w1 - w0;
         } else {
-          const uint64_t base = k == KA_REQ_SCAN ? b->o_scan : b->o_chain;
-          r->out[0].assign(u32(base) + pos, u32(base) + pos + n);
+          r->out[0] = u32(k == KA_REQ_SCAN ? b->o_scan : b->o_chain) + pos;
+          r->out_n[0] = n;
         }
+        b->out->refs.fetch_add(1);
+        r->outbuf = b->out;
         ++done_ok;
         elems += n;
         lat.push_back(now - r->arrival_us);
@@ -274,15 +310,17 @@ void Server::complete(Batch* b) {
         ++done_bad;
       }
       pos += n;
-      r->in.clear();
-      r->in.shrink_to_fit();
+      if (r->pin) {
+        sys->stage.give_back(r->pin);
+        r->pin = nullptr;
+      }
       r->finish(b->rc ? b->rc : KA_OK);
       r->release();
     }
   }
   if (b->d_buf) sys->pool.release(b->d_buf, b->d_bytes, b->si, 1ull << b->si);
-  if (b->h_in) sys->stage.give_back(b->h_in);
-  if (b->h_out) sys->stage.give_back(b->h_out);
+  if (b->h_tab) sys->stage.give_back(b->h_tab);
+  if (b->out) b->out->release();  // the requests hold the pinned outputs from here on
   if (b->done) sys->put_event(b->done);
   {
     std::lock_guard<std::mutex> g(st_mu);
@@ -305,13 +343,15 @@ void Server::run_loop() {
     // admission: the oldest requests, while the budget holds them (one request
     // is admitted whenever nothing else holds memory)
     std::vector<SrvReq*> take;
-    uint64_t bytes = 0;
+    uint64_t bytes = 0, in_bytes = 0;
     while (!mailbox.empty() && take.size() < max_batch) {
       SrvReq* r = mailbox.front();
-      const uint64_t need = request_bytes(r->kind, r->in.size());
+      const uint64_t need = request_bytes(r->kind, r->n);
       if (budget_in_use + bytes + need > budget && !(take.empty() && budget_in_use == 0)) break;
+      if (!take.empty() && in_bytes + 4 * r->n > max_batch_bytes) break;
       take.push_back(r);
       bytes += need;
+      in_bytes += 4 * r->n;
       mailbox.pop_front();
     }
     if (take.empty()) {  // wait for memory to be freed
@@ -384,6 +424,7 @@ KA_API int ka_server_create(ka_system* sys, const ka_server_config* cfg, ka_serv
   const uint32_t want = cfg && cfg->streams ? cfg->streams : 2;
   s->streams = std::max<uint32_t>(1, std::min<uint32_t>(want, (uint32_t)sys->streams.size()));
   s->max_batch = cfg && cfg->max_batch ? cfg->max_batch : 1024;
+  s->max_batch_bytes = cfg && cfg->max_batch_bytes ? cfg->max_batch_bytes : (64ull << 20);
   s->budget = cfg && cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (64ull << 30);
   s->value_bits = cfg && cfg->value_bits ? cfg->value_bits : 12;
   const uint32_t req_bits = s->max_batch > 1 ? 32u - (uint32_t)__builtin_clz(s->max_batch - 1) : 0u;
@@ -421,8 +462,17 @@ KA_API int ka_server_submit(ka_server* srv, uint32_t kind, const uint32_t* data,
     if (over) return set_error(KA_E_ARG, "an index value is at or above 2^value_bits");
   }
   ka_srv_req* r = new ka_srv_req();
+  r->sys = srv->sys;
   r->kind = kind;
-  r->in.assign(data, data + n);
+  r->n = n;
+  if (n) {
+    r->pin = srv->sys->stage.get(srv->sys, 4 * n);
+    if (!r->pin) {
+      delete r;
+      return set_error(KA_E_OOM, "server: pinned staging");
+    }
+    std::memcpy(r->pin, data, 4 * n);
+  }
   r->arrival_us = arrival_us > 0 ? arrival_us : clock_us();
   {
     std::lock_guard<std::mutex> g(srv->mu);
@@ -459,11 +509,10 @@ KA_API int ka_server_result(ka_srv_req* req, uint32_t i, uint32_t* host, uint64_
   }
   const uint32_t outs = req->kind == KA_REQ_WAH ? 3 : 1;
   if (i >= outs) return set_error(KA_E_ARG, "no such output");
-  const auto& v = req->out[i];
-  *count = v.size();
+  *count = req->out_n[i];
   if (!host) return KA_OK;
-  if (cap < v.size()) return set_error(KA_E_ARG, "buffer too small");
-  if (!v.empty()) std::memcpy(host, v.data(), 4 * v.size());
+  if (cap < req->out_n[i]) return set_error(KA_E_ARG, "buffer too small");
+  if (req->out_n[i]) std::memcpy(host, req->out[i], 4 * req->out_n[i]);
   return KA_OK;
 }
 

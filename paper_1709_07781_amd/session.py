@@ -242,11 +242,12 @@ class Server:
     their outputs and the latency statistics."""
 
     def __init__(self, session: Session, streams: int = 2, max_batch: int = 0, budget_bytes: int = 0,
-                 value_bits: int = 12, chain_a=None, chain_b=None):
+                 value_bits: int = 12, chain_a=None, chain_b=None, max_batch_bytes: int = 0):
         from . import ka_server_config
         cfg = ka_server_config()
         cfg.streams = streams
         cfg.max_batch = max_batch
+        cfg.max_batch_bytes = max_batch_bytes
         cfg.hbm_budget_bytes = budget_bytes
         cfg.value_bits = value_bits
         self._a = np.ascontiguousarray(chain_a if chain_a is not None else [], dtype=np.uint32)
