@@ -75,6 +75,7 @@ typedef struct ka_ref ka_ref;
 typedef struct ka_ticket ka_ticket;
 typedef struct ka_server ka_server;
 typedef struct ka_srv_req ka_srv_req;
+typedef struct ka_batch_plan ka_batch_plan;
 
 /* System configuration (the actor_system_config that loads the device module,
  * Sec. 3.4).  HIP is initialised lazily on the first call that needs the
@@ -325,6 +326,26 @@ KA_API int ka_wah_batch(ka_system* sys, const uint32_t* values, uint64_t n, cons
                         uint32_t value_bits, uint32_t flags, ka_wah_batch_result* out);
 /* Frees the host arrays and releases the refs of a batch result. */
 KA_API int ka_wah_batch_result_free(ka_wah_batch_result* res);
+
+/* Batch plans: the batched index build of one fixed batch shape (request
+ * boundaries req_off[0..nreq], n = req_off[nreq]) recorded once into a HIP graph
+ * on the plan's own stream and replayed by each run (Sec. 3.6: with the stages
+ * composed, the per-stage launch work is the overhead left).  The plan owns
+ * its input, outputs and scratch (nothing is allocated per run); outputs are
+ * those of ka_wah_batch.  Requirements on req_off and value_bits as there. */
+KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_t nreq, uint32_t value_bits,
+                                ka_batch_plan** out);
+/* The device buffer (n uint32) the graph reads the values from. */
+KA_API int ka_batch_plan_input(ka_batch_plan* plan, uint32_t** values_dev);
+/* The plan's hipStream_t (runs are ordered on it). */
+KA_API int ka_batch_plan_stream(ka_batch_plan* plan, void** stream);
+/* Copies values (host memory, or device memory with KA_WAH_INPUT_DEVICE; NULL:
+ * the input buffer already holds them) and launches the graph; does not wait. */
+KA_API int ka_batch_plan_run(ka_batch_plan* plan, const uint32_t* values, uint32_t flags);
+/* Waits for the last run and returns its outputs as host arrays (free with
+ * ka_wah_batch_result_free); KA_E_ARG if a value was at or above 2^value_bits. */
+KA_API int ka_batch_plan_result(ka_batch_plan* plan, ka_wah_batch_result* out);
+KA_API int ka_batch_plan_destroy(ka_batch_plan* plan);
 
 /* ---- the served form (Sec. 3.3: the mailbox buffers messages in order of
  * arrival; Sec. 3.4: an OpenCL actor feeds its device's command queue) ------------ */

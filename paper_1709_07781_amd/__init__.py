@@ -135,6 +135,12 @@ SIGNATURES = {
     "ka_wah_result_free": [ctypes.POINTER(ka_wah_result)],
     "ka_wah_batch": [_P, _P, _U64, _P, _U32, _U32, _U32, ctypes.POINTER(ka_wah_batch_result)],
     "ka_wah_batch_result_free": [ctypes.POINTER(ka_wah_batch_result)],
+    "ka_batch_plan_create": [_P, _P, _U32, _U32, _PP],
+    "ka_batch_plan_input": [_P, _PP],
+    "ka_batch_plan_stream": [_P, _PP],
+    "ka_batch_plan_run": [_P, _P, _U32],
+    "ka_batch_plan_result": [_P, ctypes.POINTER(ka_wah_batch_result)],
+    "ka_batch_plan_destroy": [_P],
     "ka_server_create": [_P, ctypes.POINTER(ka_server_config), _PP],
     "ka_server_submit": [_P, _U32, _P, _U64, ctypes.c_double, _PP],
     "ka_server_wait": [_P, _I64],

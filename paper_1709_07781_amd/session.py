@@ -300,3 +300,54 @@ class Server:
             check(lib.ka_server_destroy(self.srv), "ka_server_destroy")
             self.srv = None
 
+
+class BatchPlan:
+    """A batch shape recorded into a HIP graph (ka_batch_plan_*)."""
+
+    def __init__(self, session: Session, req_off, value_bits: int):
+        self.off = np.ascontiguousarray(req_off, dtype=np.uint32)
+        self.nreq = self.off.size - 1
+        self.plan = c_void_p()
+        check(lib.ka_batch_plan_create(session.sys, self.off.ctypes.data, self.nreq, value_bits, byref(self.plan)),
+              "ka_batch_plan_create")
+
+    def stream_handle(self) -> int:
+        s = c_void_p()
+        check(lib.ka_batch_plan_stream(self.plan, byref(s)), "ka_batch_plan_stream")
+        return s.value or 0
+
+    def input_ptr(self) -> int:
+        p = c_void_p()
+        check(lib.ka_batch_plan_input(self.plan, byref(p)), "ka_batch_plan_input")
+        return p.value or 0
+
+    def run(self, values=None):
+        """values: numpy uint32 (host), a device tensor, or None (input buffer already filled)."""
+        if values is None:
+            check(lib.ka_batch_plan_run(self.plan, None, 0), "ka_batch_plan_run")
+        elif isinstance(values, np.ndarray):
+            v = np.ascontiguousarray(values, dtype=np.uint32)
+            check(lib.ka_batch_plan_run(self.plan, v.ctypes.data if v.size else None, 0), "ka_batch_plan_run")
+        else:
+            check(lib.ka_batch_plan_run(self.plan, c_void_p(values.data_ptr()), KA_WAH_INPUT_DEVICE),
+                  "ka_batch_plan_run")
+
+    def result(self):
+        """Per-request (keys, offsets, words) of the last run."""
+        res = ka_wah_batch_result()
+        check(lib.ka_batch_plan_result(self.plan, byref(res)), "ka_batch_plan_result")
+        nreq, D, W = self.nreq, res.D, res.W
+        keys = np.ctypeslib.as_array(res.keys, shape=(max(D, 1),))[:D].copy()
+        offs = np.ctypeslib.as_array(res.offsets, shape=(D + nreq,)).copy()
+        words = np.ctypeslib.as_array(res.words, shape=(max(W, 1),))[:W].copy()
+        ks = np.ctypeslib.as_array(res.key_start, shape=(nreq + 1,)).copy()
+        ws = np.ctypeslib.as_array(res.word_start, shape=(nreq + 1,)).copy()
+        check(lib.ka_wah_batch_result_free(byref(res)), "ka_wah_batch_result_free")
+        return [(keys[ks[j]:ks[j + 1]], offs[ks[j] + j:ks[j + 1] + j + 1], words[ws[j]:ws[j + 1]])
+                for j in range(nreq)]
+
+    def close(self):
+        if self.plan:
+            check(lib.ka_batch_plan_destroy(self.plan), "ka_batch_plan_destroy")
+            self.plan = None
+

@@ -1,0 +1,104 @@
+"""GPU tests of batch plans (ka_batch_plan_*): the batched index build
+recorded into a HIP graph and replayed.  Every replay is checked against the
+oracle and against the eager batched build (ka_wah_batch) of the same values,
+with the program's own eager work and synchronisations between replays."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sess():
+    from paper_1709_07781_amd.session import Session
+    s = Session()
+    yield s
+    s.close()
+
+
+def _same(a, b):
+    assert len(a) == len(b)
+    for (k1, o1, w1), (k2, o2, w2) in zip(a, b):
+        np.testing.assert_array_equal(k1, k2)
+        np.testing.assert_array_equal(o1, o2)
+        np.testing.assert_array_equal(w1, w2)
+
+
+def _oracle(off, v):
+    o = oracle.default()
+    return [o.wah_index(v[off[j]:off[j + 1]]) for j in range(len(off) - 1)]
+
+
+def test_plan_replays_match_eager_and_oracle(sess):
+    import torch
+    from paper_1709_07781_amd.session import BatchPlan
+    off, v1 = workloads.batched_requests(seed=81, count=50, lo_log2=0, hi_log2=13)
+    n = int(off[-1])
+    v2 = workloads.uniform_values(82, n, 1 << 12)
+    v3 = workloads.structured("alternating_chunks", n, seed=83) & np.uint32(0xFFF)
+    plan = BatchPlan(sess, off, 12)
+    try:
+        for rep, v in enumerate([v1, v2, v1, v3, v2, v1]):
+            plan.run(v)
+            got = plan.result()
+            # eager work between replays: the same batch without the graph, a torch op, a sync
+            eager = sess.wah_batch(v, off, 12)
+            t = torch.arange(1000, device="cuda").sum().item()
+            assert t == 499500
+            torch.cuda.synchronize()
+            _same(got, eager)
+            _same(got, _oracle(off, v))
+    finally:
+        plan.close()
+
+
+def test_plan_device_input_and_prefilled_buffer(sess):
+    import torch
+    from paper_1709_07781_amd.session import BatchPlan
+    sizes = [0, 1, 31, 0, 4097, 5000, 0]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    v = workloads.uniform_values(91, int(off[-1]), 1 << 10)
+    plan = BatchPlan(sess, off, 10)
+    try:
+        dv = torch.from_numpy(v.view(np.int32)).to("cuda")
+        for _ in range(3):
+            plan.run(dv)  # device-to-device copy into the plan's input, then the graph
+            _same(plan.result(), _oracle(off, v))
+        assert plan.input_ptr() != 0
+        for _ in range(2):
+            plan.run(None)  # the input buffer still holds v
+            _same(plan.result(), _oracle(off, v))
+    finally:
+        plan.close()
+
+
+def test_plan_rejects_out_of_range_values(sess):
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import BatchPlan
+    off = np.array([0, 100, 300], dtype=np.uint32)
+    v = workloads.uniform_values(95, 300, 1 << 8)
+    plan = BatchPlan(sess, off, 8)
+    try:
+        v[150] = 256
+        plan.run(v)
+        with pytest.raises(ka.KaError) as e:
+            plan.result()
+        assert e.value.code == ka.KA_E_ARG
+        v[150] = 255  # the next replay is fine again
+        plan.run(v)
+        _same(plan.result(), _oracle(off, v))
+    finally:
+        plan.close()
+
+
+def test_plan_argument_errors(sess):
+    import ctypes
+    import paper_1709_07781_amd as ka
+    p = ctypes.c_void_p()
+    for off, nreq, vb in [([0, 5, 3], 2, 8), ([1, 5], 1, 8), ([0, 5, 10, 12, 20], 4, 31), ([0, 4], 1, 0)]:
+        a = np.array(off, dtype=np.uint32)
+        assert ka.lib.ka_batch_plan_create(sess.sys, a.ctypes.data, nreq, vb, ctypes.byref(p)) == ka.KA_E_ARG
