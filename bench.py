@@ -302,6 +302,116 @@ def bench_served(args) -> int:
     return 0
 
 
+def bench_chain(args) -> int:
+    """The actor-overhead chain: 8 affine actors composed with device-resident
+    refs, the same stages with a host round trip per stage (values in and out),
+    and the raw launch sequence of the same kernels (ka_affine_chain_raw), at
+    m = 2^10 .. 2^24.  Per chain: device time in a back-to-back stream of
+    chains, and latency of one chain waited for on the host (median)."""
+    import ctypes
+
+    import torch
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import Session
+    import oracle
+    import workloads
+
+    torch.cuda.set_device(0)
+    sess = Session()
+    a, b = workloads.chain_params()
+    ca = np.ascontiguousarray(a, dtype=np.uint32)
+    cb = np.ascontiguousarray(b, dtype=np.uint32)
+    ref_actors = [sess.affine_actor(int(a[i]), int(b[i])) for i in range(8)]
+    chain = ref_actors[0]
+    composed = []
+    for i in range(1, 8):
+        chain = sess.compose(ref_actors[i], chain)
+        composed.append(chain)
+    val_actors = [sess.affine_actor(int(a[i]), int(b[i]), in_mode=ka.KA_VAL, out_mode=ka.KA_VAL) for i in range(8)]
+    stream = torch.cuda.current_stream()
+    o = oracle.default()
+    rows = []
+    for lg in (10, 14, 18, 22, 24):
+        m = 1 << lg
+        x0 = workloads.chain_input(seed=2, m=m)
+        exp = o.affine_chain(x0, a, b)
+        reps = max(5, min(200, (1 << 26) // m))
+
+        def dev_ms(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        def lat_us(fn, sync=True):
+            ts = []
+            for _ in range(min(reps, 50)):
+                t0 = time.perf_counter()
+                fn()
+                if sync:
+                    torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e6)
+            return float(np.median(ts))
+
+        dv = sess.upload(x0)
+        vin = sess.wrap(dv)
+
+        def refs_chain():
+            (r,) = sess.request(chain, ka.ref(vin), n_out=1)
+            sess.release_ref(r)
+
+        def raw_chain():
+            ka.check(ka.lib.ka_affine_chain_raw(sess.sys, ctypes.c_void_p(dv.data_ptr()), m, ca.ctypes.data,
+                                                cb.ctypes.data, 8))
+
+        def host_chain():
+            x = x0
+            for act in val_actors:
+                (x,) = sess.request(act, ka.val(x.ctypes.data, x.size), n_out=1)
+            return x
+
+        # parity of each form, from the same input
+        dv.copy_(torch.from_numpy(x0.view(np.int32)))
+        refs_chain()
+        ok = np.array_equal(sess.read(vin), exp)
+        dv.copy_(torch.from_numpy(x0.view(np.int32)))
+        raw_chain()
+        torch.cuda.synchronize()
+        ok &= np.array_equal(dv.cpu().numpy().view(np.uint32), exp)
+        ok &= np.array_equal(host_chain(), exp)
+        row = {"m": m, "parity": "bit-exact" if ok else "MISMATCH",
+               "refs_device_ms": dev_ms(refs_chain), "raw_device_ms": dev_ms(raw_chain),
+               "refs_latency_us": lat_us(refs_chain), "raw_latency_us": lat_us(raw_chain),
+               "host_round_trip_latency_us": lat_us(host_chain, sync=False),
+               "roofline_GBs_refs": 64.0 * m / 1e9 / 1e-3}
+        row["roofline_GBs_refs"] = 64.0 * m / (row["refs_device_ms"] * 1e-3) / 1e9
+        row["refs_overhead_us"] = row["refs_latency_us"] - row["raw_latency_us"]
+        row["refs_overhead_pct"] = 100.0 * row["refs_overhead_us"] / row["raw_latency_us"]
+        log(f"[bench] chain m=2^{lg}: refs {row['refs_latency_us']:.1f} us, raw {row['raw_latency_us']:.1f} us, "
+            f"host round trip {row['host_round_trip_latency_us']:.1f} us, device {row['refs_device_ms']:.4f} ms "
+            f"({row['roofline_GBs_refs']:.0f} GB/s), {row['parity']}")
+        rows.append(row)
+        sess.release_ref(vin)
+        del dv
+    for act in composed + ref_actors + val_actors:
+        sess.release_actor(act)
+    sess.close()
+    big = rows[-1]
+    out = {"metric": METRIC, "value": big["m"] / (big["refs_device_ms"] * 1e-3), "unit": "elements/s",
+           "n_gpus": 1, "steps": None, "warmup": 1, "ms_per_step": big["refs_device_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "actor-overhead chain: 8 composed affine actors x <- a_i x + b_i over uint32[m], "
+                                  "device-resident refs vs host round trip per stage vs raw launch sequence"},
+           "chain": rows}
+    print(json.dumps(out), flush=True)
+    return 0 if all(r["parity"] == "bit-exact" for r in rows) else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,7 +421,7 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--workload", choices=("large", "batched", "served"), default="large",
+    ap.add_argument("--workload", choices=("large", "batched", "served", "chain"), default="large",
                     help="large: the 2^26 Zipf request (default); batched: 4096 requests of 2^10..2^20 values, "
                          "one batched pass against 4096 plain per-request pipelines; served: Poisson arrivals of "
                          "the 40/30/30 index/scan/chain mix at several rates, batched server against the plain "
@@ -333,6 +443,8 @@ def main() -> int:
         return bench_batched(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "chain":
+        return bench_chain(args)
 
     import torch
     import paper_1709_07781_amd as ka

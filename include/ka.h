@@ -410,6 +410,14 @@ KA_API int ka_server_clock_us(double* now);
 /* Cancels waiting requests, waits for batches in flight, stops the threads. */
 KA_API int ka_server_destroy(ka_server* srv);
 
+/* ---- the actor-overhead baseline (Sec. 3.6) ---------------------------------------- */
+/* Queues `stages` launches of the affine kernel (x <- a[i] x + b[i] mod 2^32)
+ * over the device array x[0..n) on stream 0, without actors or messages: the
+ * raw launch sequence against which a chain of affine actors is measured.
+ * Does not wait. */
+KA_API int ka_affine_chain_raw(ka_system* sys, uint32_t* x, uint64_t n, const uint32_t* a, const uint32_t* b,
+                               uint32_t stages);
+
 /* ---- profiling (KA_SYS_PROFILE) -------------------------------------------------- */
 /* Launch count and summed device time of every kernel named `kernel` since
  * the last reset (waits for the device). */

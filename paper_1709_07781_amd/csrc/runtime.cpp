@@ -1646,6 +1646,19 @@ KA_API int ka_profile_get(ka_system* sys, const char* kernel, uint64_t* launches
   KA_GUARD_END
 }
 
+KA_API int ka_affine_chain_raw(ka_system* sys, uint32_t* x, uint64_t n, const uint32_t* a, const uint32_t* b,
+                               uint32_t stages) {
+  KA_GUARD_BEGIN
+  if (!sys || (n && !x) || (stages && (!a || !b))) return set_error(KA_E_ARG, "null argument");
+  int rc = sys->ensure_init();
+  if (rc) return rc;
+  if ((rc = sys->use_device())) return rc;
+  CmdEnv env(sys, 0);
+  for (uint32_t i = 0; i < stages && !rc; ++i) rc = launch_affine(env, x, n, nullptr, 0, a[i], b[i]);
+  return rc;
+  KA_GUARD_END
+}
+
 KA_API int ka_profile_reset(ka_system* sys) {
   KA_GUARD_BEGIN
   if (!sys) return set_error(KA_E_ARG, "null system");
