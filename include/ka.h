@@ -423,6 +423,9 @@ KA_API int ka_affine_chain_raw(ka_system* sys, uint32_t* x, uint64_t n, const ui
  * the last reset (waits for the device). */
 KA_API int ka_profile_get(ka_system* sys, const char* kernel, uint64_t* launches, double* total_ms);
 KA_API int ka_profile_reset(ka_system* sys);
+/* Switches the per-launch timing of KA_SYS_PROFILE on or off (each timed launch
+ * is bracketed by two events on its stream). */
+KA_API int ka_profile_enable(ka_system* sys, int on);
 
 #ifdef __cplusplus
 }

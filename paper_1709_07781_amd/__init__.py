@@ -153,6 +153,7 @@ SIGNATURES = {
     "ka_server_destroy": [_P],
     "ka_profile_get": [_P, ctypes.c_char_p, _U64P, _DBLP],
     "ka_profile_reset": [_P],
+    "ka_profile_enable": [_P, ctypes.c_int],
 }
 
 

@@ -1659,6 +1659,12 @@ KA_API int ka_affine_chain_raw(ka_system* sys, uint32_t* x, uint64_t n, const ui
   KA_GUARD_END
 }
 
+KA_API int ka_profile_enable(ka_system* sys, int on) {
+  if (!sys) return set_error(KA_E_ARG, "null system");
+  sys->profile = on != 0;
+  return KA_OK;
+}
+
 KA_API int ka_profile_reset(ka_system* sys) {
   KA_GUARD_BEGIN
   if (!sys) return set_error(KA_E_ARG, "null system");

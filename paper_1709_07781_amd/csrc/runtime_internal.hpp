@@ -104,7 +104,7 @@ struct System {
   std::vector<std::unique_ptr<StreamCtx>> streams;
   Pool pool;
   HostStage stage;
-  bool profile = false;
+  std::atomic<bool> profile{false};
   std::mutex ev_mu;
   std::vector<hipEvent_t> events;  // pool of timing-disabled events
   std::mutex prof_mu;
