@@ -330,11 +330,16 @@ KA_API int ka_wah_batch_result_free(ka_wah_batch_result* res);
 /* Batch plans: the batched index build of one fixed batch shape (request
  * boundaries req_off[0..nreq], n = req_off[nreq]) recorded once into a HIP graph
  * on the plan's own stream and replayed by each run (Sec. 3.6: with the stages
- * composed, the per-stage launch work is the overhead left).  The plan owns
+ * composed, the per-stage launch work is the overhead left).  With
+ * KA_PLAN_AUTOTUNE it records one graph per sort tile shape (8192 keys as
+ * 1024 x 8 or 512 x 16 work-items x keys, 4096 keys as 512 x 8) and its first
+ * run times them all on the real values and keeps the fastest.  The plan owns
  * its input, outputs and scratch (nothing is allocated per run); outputs are
  * those of ka_wah_batch.  Requirements on req_off and value_bits as there. */
+#define KA_PLAN_AUTOTUNE 1u /* record one graph per sort tile shape; the first run picks the fastest */
+#define KA_PLAN_SHAPE(s) (((uint32_t)(s) + 1u) << 8) /* record tile shape s only (0, 1 or 2) */
 KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_t nreq, uint32_t value_bits,
-                                ka_batch_plan** out);
+                                uint32_t flags, ka_batch_plan** out);
 /* The device buffer (n uint32) the graph reads the values from. */
 KA_API int ka_batch_plan_input(ka_batch_plan* plan, uint32_t** values_dev);
 /* The plan's hipStream_t (runs are ordered on it). */
@@ -345,6 +350,10 @@ KA_API int ka_batch_plan_run(ka_batch_plan* plan, const uint32_t* values, uint32
 /* Waits for the last run and returns its outputs as host arrays (free with
  * ka_wah_batch_result_free); KA_E_ARG if a value was at or above 2^value_bits. */
 KA_API int ka_batch_plan_result(ka_batch_plan* plan, ka_wah_batch_result* out);
+/* The tile shape the runs use (-1 before the first run of an autotuned plan)
+ * and, for an autotuned plan, the time of its first run with each shape
+ * (ms[0..nms), 0 for shapes not tried). */
+KA_API int ka_batch_plan_shape(ka_batch_plan* plan, int* shape, float* ms, uint32_t nms);
 KA_API int ka_batch_plan_destroy(ka_batch_plan* plan);
 
 /* ---- the served form (Sec. 3.3: the mailbox buffers messages in order of

@@ -101,6 +101,7 @@ class ka_server_stats(ctypes.Structure):
 
 
 KA_REQ_WAH, KA_REQ_SCAN, KA_REQ_CHAIN = 0, 1, 2
+KA_PLAN_AUTOTUNE = 1
 
 
 SIGNATURES = {
@@ -136,7 +137,8 @@ SIGNATURES = {
     "ka_wah_batch": [_P, _P, _U64, _P, _U32, _U32, _U32, ctypes.POINTER(ka_wah_batch_result)],
     "ka_wah_batch_result_free": [ctypes.POINTER(ka_wah_batch_result)],
     "ka_affine_chain_raw": [_P, _P, _U64, _P, _P, _U32],
-    "ka_batch_plan_create": [_P, _P, _U32, _U32, _PP],
+    "ka_batch_plan_create": [_P, _P, _U32, _U32, _U32, _PP],
+    "ka_batch_plan_shape": [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float), _U32],
     "ka_batch_plan_input": [_P, _PP],
     "ka_batch_plan_stream": [_P, _PP],
     "ka_batch_plan_run": [_P, _P, _U32],

@@ -68,7 +68,9 @@ int launch_exclusive_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t 
 int launch_compact_nonzero(Env& env, const uint32_t* in, uint32_t* out, uint64_t n_cap, const uint64_t* d_n,
                            uint64_t* d_out_len);
 int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows, uint32_t* skeys,
-                            uint32_t* srows, uint64_t n);
+                            uint32_t* srows, uint64_t n, int shape = 0);
+// Number of tile shapes launch_radix_sort_pairs offers (shape 0 is the default).
+int sort_shape_count();
 int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                       uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
                       uint64_t* d_len_words, const uint32_t* req_base = nullptr, uint32_t req_shift = 32);
@@ -77,7 +79,7 @@ int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, ui
 int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
                      uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
                      uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
-                     uint64_t* len_key_start, uint64_t* len_word_start);
+                     uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape = 0);
 // Exclusive scan of each of nreq requests concatenated in in[0..n) (req_off as
 // for the batched index).
 int launch_segmented_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* req_off,

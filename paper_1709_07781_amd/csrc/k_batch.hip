@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kSplitBlock) void k_batch_tables(
 int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
                      uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
                      uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
-                     uint64_t* len_key_start, uint64_t* len_word_start) {
+                     uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape) {
   if (!req_off || !offsets || !key_start || !word_start || !len_keys || !len_offsets || !len_words || !len_key_start ||
       !len_word_start)
     return env.fail(kErrArg, "wah_index_batch: null buffer");
@@ -219,7 +219,7 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
                                                                                     TagOp{value_bits}, bad);
     env.prof_end("batch_keys");
     if ((rc = check_launch(env, "batch_keys launch"))) return rc;
-    if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n))) return rc;
+    if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n, sort_shape))) return rc;
   }
   // The tagged keys are the encoder's keys; rows become request-relative.
   if ((rc = launch_wah_encode(env, skeys, srows, n, keys, g_off, words, len_keys, g_len, len_words, req_off,

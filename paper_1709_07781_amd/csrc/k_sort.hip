@@ -43,10 +43,13 @@ constexpr int kPasses = 32 / kRadixBits;
 #ifndef KA_XCD_MAP
 #define KA_XCD_MAP 1
 #endif
-constexpr int kBlock = KA_SORT_BLOCK;
-constexpr int kWaves = kBlock / 64;
-constexpr int kItems = KA_SORT_ITEMS;
-constexpr int kTile = kBlock * kItems;  // 8192 keys per tile
+// Tile shapes (work-items x keys per work-item of the scatter), chosen per
+// launch: variant 0 is the default, the others are candidates for autotuning.
+struct SortShape {
+  int block, items;
+};
+constexpr SortShape kShapes[] = {{KA_SORT_BLOCK, KA_SORT_ITEMS}, {512, 16}, {512, 8}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 }  // namespace
 
@@ -124,17 +127,17 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles) {
 // ---------------------------------------------------------------------------------
 constexpr int kUpBlock = kRadix;                  // one work-item per digit when the counts are written
 constexpr int kUpWaves = kUpBlock / 64;
-constexpr int kUpVecs = kTile / 4 / kUpBlock;     // 16-byte loads per work-item
 
 // table[d * ntiles + tile] = number of keys of the tile with digit d.  The
 // exclusive scan of the table in this digit-major order is, entry by entry,
 // the position in the pass's output of the tile's first key with digit d.
 // All of a work-item's loads are issued before the first key is counted; the
 // pass-0 instance also writes the OR and the AND of the tile's keys.
-template <bool kFirst>
+template <bool kFirst, int kTile>
 __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, const SortPlan* __restrict__ plan,
                                                             uint32_t* __restrict__ table, uint32_t* __restrict__ orand,
                                                             uint32_t pass, uint32_t n) {
+  constexpr int kUpVecs = kTile / 4 / kUpBlock;  // 16-byte loads per work-item
   __shared__ uint32_t s_hist[kUpWaves][kRadix];
   __shared__ uint32_t s_or[kUpWaves], s_and[kUpWaves];
   const uint32_t tid = threadIdx.x, w = tid / 64;
@@ -250,9 +253,12 @@ __global__ __launch_bounds__(kPlanBlock) void k_radix_plan(const uint32_t* __res
 // ---------------------------------------------------------------------------------
 // scatter: one tile, ranked in LDS, written to its offsets
 // ---------------------------------------------------------------------------------
+template <int kBlock, int kItems>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const SortPlan* __restrict__ plan,
                                                           const uint32_t* __restrict__ table, uint32_t pass,
                                                           uint32_t n) {
+  constexpr int kWaves = kBlock / 64;
+  constexpr int kTile = kBlock * kItems;
   // Reorder buffers.
   __shared__ __align__(16) uint32_t s_keys[kTile];
   __shared__ uint32_t s_rows[kTile];
@@ -372,11 +378,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
 
 }  // namespace
 
-int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows, uint32_t* skeys,
-                            uint32_t* srows, uint64_t n) {
-  if (n == 0) return kOk;
-  if (!keys || !skeys || !srows) return env.fail(kErrArg, "radix_sort: null buffer");
-  if (n >= (1ull << 31)) return env.fail(kErrArg, "radix_sort: n must be below 2^31");
+namespace {
+
+template <int kBlock, int kItems>
+int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32_t* skeys, uint32_t* srows,
+                    uint64_t n) {
+  constexpr int kTile = kBlock * kItems;
   SortPlan* plan = reinterpret_cast<SortPlan*>(env.arena()->plan);
   const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
   const uint32_t nn = (uint32_t)n;
@@ -395,7 +402,8 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
   for (uint32_t pass = 0; pass < (uint32_t)kPasses; ++pass) {
     if (pass == 0) {
       env.prof_begin("radix_upsweep0");
-      k_radix_upsweep<true><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand, pass, nn);
+      k_radix_upsweep<true, kTile><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand, pass,
+                                                                                       nn);
       env.prof_end("radix_upsweep0");
       int rc = check_launch(env, "radix_upsweep launch");
       if (rc) return rc;
@@ -406,7 +414,8 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
       if (rc) return rc;
     } else {
       env.prof_begin("radix_upsweep");
-      k_radix_upsweep<false><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand, pass, nn);
+      k_radix_upsweep<false, kTile><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand,
+                                                                                        pass, nn);
       env.prof_end("radix_upsweep");
       int rc = check_launch(env, "radix_upsweep launch");
       if (rc) return rc;
@@ -416,13 +425,34 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
     int rc = launch_exclusive_scan(env, table, table, (uint64_t)ntiles * kRadix, &plan->scan_len[pass]);
     if (rc) return rc;
     env.prof_begin("radix_scatter");
-    k_radix_scatter<<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(buf, static_cast<const SortPlan*>(plan), table,
-                                                                     pass, nn);
+    k_radix_scatter<kBlock, kItems><<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(
+        buf, static_cast<const SortPlan*>(plan), table, pass, nn);
     env.prof_end("radix_scatter");
     rc = check_launch(env, "radix_scatter launch");
     if (rc) return rc;
   }
   return kOk;
+}
+
+}  // namespace
+
+int sort_shape_count() { return kNumShapes; }
+
+int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows, uint32_t* skeys,
+                            uint32_t* srows, uint64_t n, int shape) {
+  if (n == 0) return kOk;
+  if (!keys || !skeys || !srows) return env.fail(kErrArg, "radix_sort: null buffer");
+  if (n >= (1ull << 31)) return env.fail(kErrArg, "radix_sort: n must be below 2^31");
+  switch (shape) {
+    case 0:
+      return sort_with_shape<kShapes[0].block, kShapes[0].items>(env, keys, rows, skeys, srows, n);
+    case 1:
+      return sort_with_shape<kShapes[1].block, kShapes[1].items>(env, keys, rows, skeys, srows, n);
+    case 2:
+      return sort_with_shape<kShapes[2].block, kShapes[2].items>(env, keys, rows, skeys, srows, n);
+    default:
+      return env.fail(kErrArg, "radix_sort: unknown tile shape");
+  }
 }
 
 }  // namespace ka

@@ -60,8 +60,13 @@ struct Plan {
   uint32_t *input = nullptr, *req_off = nullptr, *keys = nullptr, *offsets = nullptr, *words = nullptr;
   uint32_t *key_start = nullptr, *word_start = nullptr;
   uint64_t* lens = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // one recorded graph per sort tile shape (only shape 0 without autotuning)
+  hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  int shapes = 1;
+  int chosen = 0;        // index of the graph the runs use; -1 until the first run has timed them all
+  int forced = -1;       // the one shape recorded by KA_PLAN_SHAPE, else -1
+  float shape_ms[4] = {0, 0, 0, 0};
   PlanEnv env;
 };
 
@@ -82,8 +87,10 @@ struct ka_batch_plan : Plan {};
   }
 
 static void plan_free(ka_batch_plan* p) {
-  if (p->exec) (void)hipGraphExecDestroy(p->exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (int i = 0; i < 4; ++i) {
+    if (p->exec[i]) (void)hipGraphExecDestroy(p->exec[i]);
+    if (p->graph[i]) (void)hipGraphDestroy(p->graph[i]);
+  }
   if (p->s) {
     (void)hipStreamSynchronize(p->s);
     (void)hipStreamDestroy(p->s);
@@ -95,7 +102,7 @@ static void plan_free(ka_batch_plan* p) {
 }
 
 KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_t nreq, uint32_t value_bits,
-                                ka_batch_plan** out) {
+                                uint32_t flags, ka_batch_plan** out) {
   KA_GUARD_BEGIN
   if (!sys || !req_off || !out) return set_error(KA_E_ARG, "null argument");
   if (nreq == 0) return set_error(KA_E_ARG, "no requests");
@@ -167,26 +174,39 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
     plan_free(p);
     return set_error(KA_E_DEVICE, "plan: initialisation");
   }
-  // ---- record the pipeline ------------------------------------------------------------
-  if (hipStreamBeginCapture(p->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    (void)hipGetLastError();
+  // ---- record the pipeline, once per tile shape tried ---------------------------------
+  const int forced = (int)((flags >> 8) & 0xFFu) - 1;  // KA_PLAN_SHAPE(s): record shape s only
+  if (forced >= sort_shape_count()) {
     plan_free(p);
-    return set_error(KA_E_DEVICE, "plan: begin capture");
+    return set_error(KA_E_ARG, "unknown tile shape");
   }
-  rc = launch_wah_batch(e, p->input, n, p->req_off, nreq, value_bits, p->keys, p->offsets, p->words, p->key_start,
-                        p->word_start, p->lens, p->lens + 1, p->lens + 2, p->lens + 3, p->lens + 4);
-  hipGraph_t g = nullptr;
-  const hipError_t ec = hipStreamEndCapture(p->s, &g);
-  p->graph = g;
-  if (rc || ec != hipSuccess || !g) {
-    (void)hipGetLastError();
-    plan_free(p);
-    return rc ? rc : set_error(KA_E_DEVICE, "plan: end capture");
-  }
-  if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGetLastError();
-    plan_free(p);
-    return set_error(KA_E_DEVICE, "plan: graph instantiation");
+  p->forced = forced;
+  p->shapes = (flags & KA_PLAN_AUTOTUNE) && forced < 0 ? std::min(sort_shape_count(), 4) : 1;
+  p->chosen = p->shapes > 1 ? -1 : 0;
+  for (int v = 0; v < p->shapes; ++v) {
+    const int shape = forced >= 0 ? forced : v;
+    e.used = 0;  // the shapes' graphs run one at a time on the plan's stream: they share the arena
+    if (hipStreamBeginCapture(p->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      plan_free(p);
+      return set_error(KA_E_DEVICE, "plan: begin capture");
+    }
+    rc = launch_wah_batch(e, p->input, n, p->req_off, nreq, value_bits, p->keys, p->offsets, p->words,
+                          p->key_start, p->word_start, p->lens, p->lens + 1, p->lens + 2, p->lens + 3, p->lens + 4,
+                          shape);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->s, &g);
+    p->graph[v] = g;
+    if (rc || ec != hipSuccess || !g) {
+      (void)hipGetLastError();
+      plan_free(p);
+      return rc ? rc : set_error(KA_E_DEVICE, "plan: end capture");
+    }
+    if (hipGraphInstantiate(&p->exec[v], p->graph[v], nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      plan_free(p);
+      return set_error(KA_E_DEVICE, "plan: graph instantiation");
+    }
   }
   *out = p;
   return KA_OK;
@@ -216,10 +236,43 @@ KA_API int ka_batch_plan_run(ka_batch_plan* plan, const uint32_t* values, uint32
     (void)hipGetLastError();
     return set_error(KA_E_DEVICE, "plan: input copy");
   }
-  if (hipGraphLaunch(plan->exec, plan->s) != hipSuccess) {
+  if (plan->chosen < 0) {
+    // Autotuning: the first run times every recorded shape on these values
+    // (each leaves the same outputs) and keeps the fastest for later runs.
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      (void)hipGetLastError();
+      if (a) (void)hipEventDestroy(a);
+      return set_error(KA_E_DEVICE, "plan: events");
+    }
+    int best = 0;
+    for (int v = 0; v < plan->shapes; ++v) {
+      if (hipEventRecord(a, plan->s) != hipSuccess || hipGraphLaunch(plan->exec[v], plan->s) != hipSuccess ||
+          hipEventRecord(b, plan->s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+          hipEventElapsedTime(&plan->shape_ms[v], a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return set_error(KA_E_LAUNCH, "plan: autotuning run");
+      }
+      if (plan->shape_ms[v] < plan->shape_ms[best]) best = v;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    plan->chosen = best;
+    return KA_OK;
+  }
+  if (hipGraphLaunch(plan->exec[plan->chosen], plan->s) != hipSuccess) {
     (void)hipGetLastError();
     return set_error(KA_E_LAUNCH, "plan: graph launch");
   }
+  return KA_OK;
+}
+
+KA_API int ka_batch_plan_shape(ka_batch_plan* plan, int* shape, float* ms, uint32_t nms) {
+  if (!plan || !shape) return set_error(KA_E_ARG, "null argument");
+  *shape = plan->chosen < 0 ? -1 : (plan->forced >= 0 ? plan->forced : plan->chosen);
+  for (uint32_t i = 0; ms && i < nms; ++i) ms[i] = i < (uint32_t)plan->shapes ? plan->shape_ms[i] : 0.0f;
   return KA_OK;
 }
 

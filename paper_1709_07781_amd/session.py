@@ -304,12 +304,20 @@ class Server:
 class BatchPlan:
     """A batch shape recorded into a HIP graph (ka_batch_plan_*)."""
 
-    def __init__(self, session: Session, req_off, value_bits: int):
+    def __init__(self, session: Session, req_off, value_bits: int, autotune: bool = False, shape: int | None = None):
         self.off = np.ascontiguousarray(req_off, dtype=np.uint32)
         self.nreq = self.off.size - 1
         self.plan = c_void_p()
-        check(lib.ka_batch_plan_create(session.sys, self.off.ctypes.data, self.nreq, value_bits, byref(self.plan)),
-              "ka_batch_plan_create")
+        flags = (1 if autotune else 0) | (((shape + 1) << 8) if shape is not None else 0)
+        check(lib.ka_batch_plan_create(session.sys, self.off.ctypes.data, self.nreq, value_bits, flags,
+                                       byref(self.plan)), "ka_batch_plan_create")
+
+    def shape(self):
+        """(shape used by the runs, first-run times per shape in ms)."""
+        sh = ctypes.c_int()
+        ms = (ctypes.c_float * 4)()
+        check(lib.ka_batch_plan_shape(self.plan, byref(sh), ms, 4), "ka_batch_plan_shape")
+        return sh.value, list(ms)
 
     def stream_handle(self) -> int:
         s = c_void_p()

@@ -101,4 +101,39 @@ def test_plan_argument_errors(sess):
     p = ctypes.c_void_p()
     for off, nreq, vb in [([0, 5, 3], 2, 8), ([1, 5], 1, 8), ([0, 5, 10, 12, 20], 4, 31), ([0, 4], 1, 0)]:
         a = np.array(off, dtype=np.uint32)
-        assert ka.lib.ka_batch_plan_create(sess.sys, a.ctypes.data, nreq, vb, ctypes.byref(p)) == ka.KA_E_ARG
+        assert ka.lib.ka_batch_plan_create(sess.sys, a.ctypes.data, nreq, vb, 0, ctypes.byref(p)) == ka.KA_E_ARG
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_each_tile_shape_matches_oracle(sess, shape):
+    """Every sort tile shape the autotuner chooses from gives the same, correct
+    result (sizes span several tiles of each shape and ragged ends)."""
+    from paper_1709_07781_amd.session import BatchPlan
+    off, v = workloads.batched_requests(seed=100 + shape, count=40, lo_log2=8, hi_log2=15)
+    plan = BatchPlan(sess, off, 12, shape=shape)
+    try:
+        assert plan.shape()[0] == shape
+        for _ in range(2):
+            plan.run(v)
+            _same(plan.result(), _oracle(off, v))
+    finally:
+        plan.close()
+
+
+def test_autotuned_plan(sess):
+    from paper_1709_07781_amd.session import BatchPlan
+    off, v = workloads.batched_requests(seed=110, count=64, lo_log2=10, hi_log2=16)
+    plan = BatchPlan(sess, off, 12, autotune=True)
+    try:
+        assert plan.shape()[0] == -1
+        plan.run(v)  # times every shape
+        chosen, ms = plan.shape()
+        assert chosen in (0, 1, 2) and all(t > 0 for t in ms[:3]) and ms[chosen] == min(ms[:3])
+        _same(plan.result(), _oracle(off, v))
+        v2 = workloads.uniform_values(111, int(off[-1]), 1 << 12)
+        plan.run(v2)
+        assert plan.shape()[0] == chosen
+        _same(plan.result(), _oracle(off, v2))
+    finally:
+        plan.close()
+
