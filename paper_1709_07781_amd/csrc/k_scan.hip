@@ -121,6 +121,7 @@ __global__ __launch_bounds__(kScanBlock) void k_exclusive_scan_u32(const uint32_
   __shared__ uint32_t s_prefix, s_tk;
   __shared__ uint32_t s_wave[kScanRounds][kWaves];
   const uint64_t n = device_count(n_cap, d_n);
+  if (n == 0) return;  // nothing to scan: no work-group draws, the counter stays 0
   const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
   const uint32_t tile = take_tile(lb, ntiles, &s_tk);
   if (tile == kNoTile) return;

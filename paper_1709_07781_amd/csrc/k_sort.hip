@@ -136,7 +136,7 @@ constexpr int kUpWaves = kUpBlock / 64;
 template <bool kFirst, int kTile>
 __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, const SortPlan* __restrict__ plan,
                                                             uint32_t* __restrict__ table, uint32_t* __restrict__ orand,
-                                                            uint32_t pass, uint32_t n) {
+                                                            uint32_t pass, uint32_t n, uint32_t ntiles) {
   constexpr int kUpVecs = kTile / 4 / kUpBlock;  // 16-byte loads per work-item
   __shared__ uint32_t s_hist[kUpWaves][kRadix];
   __shared__ uint32_t s_or[kUpWaves], s_and[kUpWaves];
@@ -147,11 +147,10 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
     if (!((active >> pass) & 1u)) return;  // uniform over the grid
     keys = pass_io(buf, active, pass).src_keys;
   }
-  const uint32_t ntiles = gridDim.x;
+  const uint32_t shift = pass * kRadixBits;
   const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
   const uint32_t base = tile * kTile;
   const uint32_t len = min((uint32_t)kTile, n - base);
-  const uint32_t shift = pass * kRadixBits;
 
   // Key 4 (j * kUpBlock + tid) + c of the tile in k[j][c].
   uint32_t k[kUpVecs][4];
@@ -256,7 +255,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_radix_plan(const uint32_t* __res
 template <int kBlock, int kItems>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const SortPlan* __restrict__ plan,
                                                           const uint32_t* __restrict__ table, uint32_t pass,
-                                                          uint32_t n) {
+                                                          uint32_t n, uint32_t ntiles) {
   constexpr int kWaves = kBlock / 64;
   constexpr int kTile = kBlock * kItems;
   // Reorder buffers.
@@ -272,7 +271,6 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   if (!((active >> pass) & 1u)) return;
   const PassIo io = pass_io(buf, active, pass);
   const uint32_t shift = pass * kRadixBits;
-  const uint32_t ntiles = gridDim.x;
   const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
   const uint32_t base = tile * kTile;
   const uint32_t tile_n = min((uint32_t)kTile, n - base);
@@ -398,12 +396,15 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
   uint32_t* table = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * kRadix * 4));
   uint32_t* orand = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * 2 * 4));
   if (!buf.keys_b || !buf.rows_b || !table || !orand) return env.fail(kErrOom, "radix_sort: scratch buffers");
-
+  // One work-group per tile.  (Grid-stride versions with occupancy-sized
+  // grids made skipped passes cheaper but active scatters 50% slower: the two
+  // work-groups of a CU then run their phases in step instead of interleaved.)
+  const uint32_t g_up0 = ntiles, g_up = ntiles, g_sc = ntiles;
   for (uint32_t pass = 0; pass < (uint32_t)kPasses; ++pass) {
     if (pass == 0) {
       env.prof_begin("radix_upsweep0");
-      k_radix_upsweep<true, kTile><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand, pass,
-                                                                                       nn);
+      k_radix_upsweep<true, kTile><<<dim3(g_up0), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand, pass,
+                                                                                      nn, ntiles);
       env.prof_end("radix_upsweep0");
       int rc = check_launch(env, "radix_upsweep launch");
       if (rc) return rc;
@@ -414,8 +415,8 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
       if (rc) return rc;
     } else {
       env.prof_begin("radix_upsweep");
-      k_radix_upsweep<false, kTile><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand,
-                                                                                        pass, nn);
+      k_radix_upsweep<false, kTile><<<dim3(g_up), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand,
+                                                                                       pass, nn, ntiles);
       env.prof_end("radix_upsweep");
       int rc = check_launch(env, "radix_upsweep launch");
       if (rc) return rc;
@@ -425,8 +426,8 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
     int rc = launch_exclusive_scan(env, table, table, (uint64_t)ntiles * kRadix, &plan->scan_len[pass]);
     if (rc) return rc;
     env.prof_begin("radix_scatter");
-    k_radix_scatter<kBlock, kItems><<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(
-        buf, static_cast<const SortPlan*>(plan), table, pass, nn);
+    k_radix_scatter<kBlock, kItems><<<dim3(g_sc), dim3(kBlock), 0, env.stream()>>>(
+        buf, static_cast<const SortPlan*>(plan), table, pass, nn, ntiles);
     env.prof_end("radix_scatter");
     rc = check_launch(env, "radix_scatter launch");
     if (rc) return rc;

@@ -18,10 +18,12 @@
 // and e emits grp(e) + gap(e) words and seg(e) values.  So the encoding is a
 // reduce-then-scan over tiles of kEncTile pairs, with no wait between tiles:
 //   k_wah_count    counts each tile's words and values,
-//   k_wah_offsets  scans the tile counts (one work-group) and writes W, D,
-//                  offsets[D] and the three output lengths,
-//   k_wah_write    re-derives each tile's groups and writes its words and
-//                  lookup-table entries at the tile's offsets.
+//   k_wah_groups   scans the tile counts inside groups of 1024 tiles and
+//                  writes the group totals,
+//   k_wah_write    adds the totals of the earlier groups to its tile's offset,
+//                  re-derives the tile's groups and writes its words and
+//                  lookup-table entries; the last tile writes W, D, offsets[D]
+//                  and the three output lengths.
 // A group spans at most 31 sorted elements (rows are distinct), so the write
 // kernel finishes a group that runs past its tile by reading at most 30
 // elements ahead (kLook).  Words are staged in LDS (over the staged input,
@@ -42,7 +44,6 @@ constexpr int kLook = 32;                        // >= 30 elements of look-ahead
 constexpr int kStage = kEncTile + 1 + kLook;     // one element of look-behind
 constexpr uint32_t kGroupRows = 31;
 constexpr uint32_t kFill = 0x80000000u;
-constexpr int kOffBlock = 1024;
 
 // Padded LDS index: one spare word every 16 so that a work-item reading its
 // kEncItems consecutive elements does not collide on banks with its neighbours.
@@ -164,48 +165,40 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_count(const uint32_t* __restr
 }
 
 // ---------------------------------------------------------------------------------
-// offsets: exclusive scan of the tile counts (one work-group), totals
+// groups: tile counts -> offsets inside groups of kGroupTiles tiles, group totals
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(kOffBlock) void k_wah_offsets(uint32_t* __restrict__ tile_words,
-                                                           uint32_t* __restrict__ tile_values, uint32_t ntiles,
-                                                           uint32_t* __restrict__ out_offsets,
-                                                           uint64_t* __restrict__ len_keys,
-                                                           uint64_t* __restrict__ len_offsets,
-                                                           uint64_t* __restrict__ len_words) {
-  // Rounds of kOffBlock consecutive tiles (coalesced), eight rounds' loads in
-  // flight at once; the scratch of the block scans alternates between two
-  // buffers, so consecutive rounds need no extra barrier.
-  constexpr int kBatch = 8;
-  __shared__ uint32_t s_w[2][kOffBlock / 64], s_s[2][kOffBlock / 64];
-  const uint32_t tid = threadIdx.x;
-  uint32_t W = 0, D = 0, round = 0;
-  for (uint32_t r0 = 0; r0 < ntiles; r0 += kBatch * kOffBlock) {
-    uint32_t a[kBatch], c[kBatch];
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-      const uint32_t t = r0 + k * kOffBlock + tid;
-      a[k] = t < ntiles ? tile_words[t] : 0u;
-      c[k] = t < ntiles ? tile_values[t] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k, ++round) {
-      uint32_t tw, ts;
-      const uint32_t pw = block_excl_scan<kOffBlock>(a[k], s_w[round & 1], &tw);
-      const uint32_t ps = block_excl_scan<kOffBlock>(c[k], s_s[round & 1], &ts);
-      const uint32_t t = r0 + k * kOffBlock + tid;
-      if (t < ntiles) {
-        tile_words[t] = W + pw;
-        tile_values[t] = D + ps;
-      }
-      W += tw;
-      D += ts;
-    }
+constexpr int kGroupTiles = 1024;  // one work-item per tile of the group
+
+// The write kernel adds the totals of the groups before its own (at most
+// ntiles / kGroupTiles values), so no single work-group scans every tile.
+__global__ __launch_bounds__(kGroupTiles) void k_wah_groups(uint32_t* __restrict__ tile_words,
+                                                            uint32_t* __restrict__ tile_values, uint32_t ntiles,
+                                                            uint32_t* __restrict__ group_words,
+                                                            uint32_t* __restrict__ group_values) {
+  __shared__ uint32_t s_a[kGroupTiles / 64], s_b[kGroupTiles / 64];
+  const uint32_t t = blockIdx.x * kGroupTiles + threadIdx.x;
+  const uint32_t w = t < ntiles ? tile_words[t] : 0u, v = t < ntiles ? tile_values[t] : 0u;
+  uint32_t tw, tv;
+  const uint32_t pw = block_excl_scan<kGroupTiles>(w, s_a, &tw);
+  const uint32_t pv = block_excl_scan<kGroupTiles>(v, s_b, &tv);
+  if (t < ntiles) {
+    tile_words[t] = pw;
+    tile_values[t] = pv;
   }
-  if (tid == 0) {
-    out_offsets[D] = W;
-    *len_keys = D;
-    *len_offsets = (uint64_t)D + 1;
-    *len_words = W;
+  if (threadIdx.x == 0) {
+    group_words[blockIdx.x] = tw;
+    group_values[blockIdx.x] = tv;
+  }
+}
+
+// An empty input: D = 0, W = 0, offsets = [0].
+__global__ void k_wah_empty(uint32_t* __restrict__ out_offsets, uint64_t* __restrict__ len_keys,
+                            uint64_t* __restrict__ len_offsets, uint64_t* __restrict__ len_words) {
+  if (threadIdx.x == 0) {
+    out_offsets[0] = 0;
+    *len_keys = 0;
+    *len_offsets = 1;
+    *len_words = 0;
   }
 }
 
@@ -217,11 +210,17 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
                                                          const uint32_t* __restrict__ srows, uint32_t n,
                                                          const uint32_t* __restrict__ tile_words,
                                                          const uint32_t* __restrict__ tile_values,
+                                                         const uint32_t* __restrict__ group_words,
+                                                         const uint32_t* __restrict__ group_values,
                                                          uint32_t* __restrict__ out_keys,
                                                          uint32_t* __restrict__ out_offsets,
-                                                         uint32_t* __restrict__ out_words, BatchRows br) {
+                                                         uint32_t* __restrict__ out_words, BatchRows br,
+                                                         uint64_t* __restrict__ len_keys,
+                                                         uint64_t* __restrict__ len_offsets,
+                                                         uint64_t* __restrict__ len_words) {
   __shared__ __align__(16) uint32_t s_mem[2 * kStagePadded];
   __shared__ uint32_t s_scan[kEncBlock / 64];
+  __shared__ uint32_t s_pre[2];
   uint32_t* s_k = s_mem;
   uint32_t* s_r = s_mem + kStagePadded;
   uint32_t* s_words = s_mem;  // after the literals are built
@@ -230,7 +229,6 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
   const uint32_t base = tile * kEncTile;
   const uint32_t tile_n = min((uint32_t)kEncTile, n - base);
   const uint32_t avail = min((uint32_t)(kEncTile + kLook), n - base);  // readable from base on
-  const uint32_t wpre = tile_words[tile], dpre = tile_values[tile];
 
   // ---- stage elements base-1 .. base+kEncTile+kLook-1 into slots 0.. --------------
   // Work-items 64..96 also load the look-behind element (slot 0) and the
@@ -247,6 +245,23 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
       xk = ok ? skeys[g] : 0u;
       xr = ok ? br.local(xk, srows[g]) : 0u;
     }
+    // This tile's first word and value: its offset inside its group plus the
+    // totals of the groups before (wave 0, once the tile's loads are issued;
+    // read after the next barrier).
+    if (tid < 64) {
+      const uint32_t grp = tile / kGroupTiles;
+      uint32_t gw = 0, gv = 0;
+      for (uint32_t j = tid; j < grp; j += 64) {
+        gw += group_words[j];
+        gv += group_values[j];
+      }
+      gw = wave_sum(gw);
+      gv = wave_sum(gv);
+      if (tid == 0) {
+        s_pre[0] = gw + tile_words[tile];
+        s_pre[1] = gv + tile_values[tile];
+      }
+    }
 #pragma unroll
     for (int j = 0; j < kVecs; ++j)
 #pragma unroll
@@ -261,6 +276,7 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
     }
   }
   __syncthreads();
+  const uint32_t wpre = s_pre[0], dpre = s_pre[1];
 
   // ---- this work-item's kEncItems consecutive elements, in registers ---------------
   const uint32_t e0 = tid * kEncItems;
@@ -345,6 +361,13 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
   }
   __syncthreads();
   for (uint32_t i = tid; i < tile_nw; i += kEncBlock) out_words[wpre + i] = s_words[i];
+  if (base + tile_n == n && tid == 0) {  // the last tile: totals and lengths
+    const uint32_t D = dpre + (packed_total >> 16), W = wpre + tile_nw;
+    out_offsets[D] = W;
+    *len_keys = D;
+    *len_offsets = (uint64_t)D + 1;
+    *len_words = W;
+  }
 }
 
 }  // namespace
@@ -360,7 +383,10 @@ int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, ui
   const uint32_t nn = (uint32_t)n;
   uint32_t* tw = static_cast<uint32_t*>(env.scratch(4ull * (ntiles ? ntiles : 1)));
   uint32_t* tv = static_cast<uint32_t*>(env.scratch(4ull * (ntiles ? ntiles : 1)));
-  if (!tw || !tv) return env.fail(kErrOom, "wah_encode_sorted: tile counts");
+  const uint64_t ng = (ntiles + kGroupTiles - 1) / kGroupTiles;
+  uint32_t* gw = static_cast<uint32_t*>(env.scratch(4ull * (ng ? ng : 1)));
+  uint32_t* gv = static_cast<uint32_t*>(env.scratch(4ull * (ng ? ng : 1)));
+  if (!tw || !tv || !gw || !gv) return env.fail(kErrOom, "wah_encode_sorted: tile counts");
   const bool vec = ((reinterpret_cast<uintptr_t>(skeys) | reinterpret_cast<uintptr_t>(srows)) & 15u) == 0;
   const BatchRows br{req_base, req_shift};
   int rc;
@@ -373,22 +399,24 @@ int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, ui
     env.prof_end("wah_count");
     if ((rc = check_launch(env, "wah_count launch"))) return rc;
   }
-  env.prof_begin("wah_offsets");
-  k_wah_offsets<<<dim3(1), dim3(kOffBlock), 0, env.stream()>>>(tw, tv, ntiles, offsets, d_len_keys, d_len_offsets,
-                                                               d_len_words);
-  env.prof_end("wah_offsets");
-  if ((rc = check_launch(env, "wah_offsets launch"))) return rc;
-  if (ntiles) {
-    env.prof_begin("wah_write");
-    if (vec)
-      k_wah_write<true><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv, keys, offsets,
-                                                                            words, br);
-    else
-      k_wah_write<false><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv, keys, offsets,
-                                                                             words, br);
-    env.prof_end("wah_write");
-    if ((rc = check_launch(env, "wah_write launch"))) return rc;
+  if (!ntiles) {
+    k_wah_empty<<<dim3(1), dim3(64), 0, env.stream()>>>(offsets, d_len_keys, d_len_offsets, d_len_words);
+    return check_launch(env, "wah_empty launch");
   }
+  const uint32_t ngroups = (ntiles + kGroupTiles - 1) / kGroupTiles;
+  env.prof_begin("wah_offsets");
+  k_wah_groups<<<dim3(ngroups), dim3(kGroupTiles), 0, env.stream()>>>(tw, tv, ntiles, gw, gv);
+  env.prof_end("wah_offsets");
+  if ((rc = check_launch(env, "wah_groups launch"))) return rc;
+  env.prof_begin("wah_write");
+  if (vec)
+    k_wah_write<true><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(
+        skeys, srows, nn, tw, tv, gw, gv, keys, offsets, words, br, d_len_keys, d_len_offsets, d_len_words);
+  else
+    k_wah_write<false><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(
+        skeys, srows, nn, tw, tv, gw, gv, keys, offsets, words, br, d_len_keys, d_len_offsets, d_len_words);
+  env.prof_end("wah_write");
+  if ((rc = check_launch(env, "wah_write launch"))) return rc;
   return kOk;
 }
 
