@@ -245,7 +245,7 @@ def bench_served(args) -> int:
     import workloads
 
     torch.cuda.set_device(0)
-    sess = Session(n_streams=4)
+    sess = Session(n_streams=max(4, args.served_streams))
     a, b = workloads.chain_params()
     # payloads are slices of two pre-generated pools (values below 2^12 for
     # the index requests, full 32-bit values for the others)
@@ -261,7 +261,8 @@ def bench_served(args) -> int:
         starts = (dseeds % np.uint64(pool_n)).astype(np.int64)
         starts = np.minimum(starts, pool_n - sizes)
         res = {"rate_per_s": rate, "requests": count}
-        for form, kw in (("batched", dict(streams=3, max_batch=1024)), ("plain", dict(streams=1, max_batch=1))):
+        batched_kw = dict(streams=args.served_streams, max_batch=1024, max_batch_bytes=args.served_batch_mb << 20)
+        for form, kw in (("batched", batched_kw), ("plain", dict(streams=1, max_batch=1))):
             srv = Server(sess, chain_a=a, chain_b=b, **kw)
             handles = []
             t0 = Server.clock_us() + 20_000.0  # first arrival 20 ms from now
@@ -301,7 +302,8 @@ def bench_served(args) -> int:
         "config": {"workload": "served: Poisson arrivals, sizes log-uniform in [2^8, 2^22], 40% WAH index "
                                "(values below 2^12) / 30% exclusive scan / 30% 8-stage affine chain, host data, "
                                "latency from the scheduled arrival to completion on the host",
-                   "rates": rates, "budget_bytes": 64 << 30},
+                   "rates": rates, "budget_bytes": 64 << 30, "batched_streams": args.served_streams,
+                   "batch_mib": args.served_batch_mb},
         "served": rows,
     }
     print(json.dumps(out), flush=True)
@@ -437,6 +439,8 @@ def main() -> int:
     ap.add_argument("--served-seconds", type=float, default=2.0,
                     help="served: seconds of arrivals per rate (at most --served-max requests)")
     ap.add_argument("--served-max", type=int, default=4000)
+    ap.add_argument("--served-streams", type=int, default=3, help="served: streams of the batched server")
+    ap.add_argument("--served-batch-mb", type=int, default=16, help="served: MiB of input per batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run the in-place affine kernel over 2^n words 3 times "
                          "(a plain copy of known size, for scaling the HBM counters)")

@@ -367,7 +367,7 @@ typedef struct ka_server_config {
   uint32_t streams;          /* batches in flight at once, one per system stream (0 = 2; at most
                                 the system's n_streams) */
   uint32_t max_batch;        /* requests merged into one batch (0 = 1024; 1 = no batching) */
-  uint64_t max_batch_bytes;  /* input bytes merged into one batch (0 = 64 MiB; a larger request runs alone) */
+  uint64_t max_batch_bytes;  /* input bytes merged into one batch (0 = 16 MiB; a larger request runs alone) */
   uint64_t hbm_budget_bytes; /* device memory the server's batches may hold together (0 = 64 GiB) */
   uint32_t value_bits;       /* index requests: every value below 2^value_bits (0 = 12) */
   uint32_t chain_len;        /* affine chain stages and their parameters (a_i odd) */

@@ -45,6 +45,9 @@ constexpr int kPasses = 32 / kRadixBits;
 #endif
 // Tile shapes (work-items x keys per work-item of the scatter), chosen per
 // launch: variant 0 is the default, the others are candidates for autotuning.
+// (Persistent scatters that load the next tile into a second register set
+// while ranking the current one ran 35-60% slower at every shape: the extra
+// registers cost more occupancy than the prefetch saves.)
 struct SortShape {
   int block, items;
 };
@@ -253,35 +256,25 @@ __global__ __launch_bounds__(kPlanBlock) void k_radix_plan(const uint32_t* __res
 // scatter: one tile, ranked in LDS, written to its offsets
 // ---------------------------------------------------------------------------------
 template <int kBlock, int kItems>
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const SortPlan* __restrict__ plan,
-                                                          const uint32_t* __restrict__ table, uint32_t pass,
-                                                          uint32_t n, uint32_t ntiles) {
-  constexpr int kWaves = kBlock / 64;
+struct ScatterLds {
+  static constexpr int kWaves = kBlock / 64;
+  static constexpr int kTile = kBlock * kItems;
+  __align__(16) uint32_t keys[kTile];  // reorder buffers
+  uint32_t rows[kTile];
+  uint16_t wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave offsets
+  uint32_t loff[kRadix];          // tile-local start of each digit
+  uint32_t dbase[kRadix];         // global start minus tile-local start
+  uint32_t scan[kWaves];
+};
+
+// The tile's keys and rows: wave w owns 64*kItems consecutive elements, lane
+// l the elements w*64*kItems + i*64 + l.
+template <int kBlock, int kItems>
+__device__ __forceinline__ void scatter_load(const PassIo& io, uint32_t base, uint32_t tile_n,
+                                             uint32_t (&key)[kItems], uint32_t (&row)[kItems]) {
   constexpr int kTile = kBlock * kItems;
-  // Reorder buffers.
-  __shared__ __align__(16) uint32_t s_keys[kTile];
-  __shared__ uint32_t s_rows[kTile];
-  __shared__ uint16_t s_wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave offsets
-  __shared__ uint32_t s_loff[kRadix];          // tile-local start of each digit
-  __shared__ uint32_t s_dbase[kRadix];         // global start minus tile-local start
-  __shared__ uint32_t s_scan[kWaves];
-
-  const uint32_t tid = threadIdx.x;
-  const uint32_t active = plan->active;
-  if (!((active >> pass) & 1u)) return;
-  const PassIo io = pass_io(buf, active, pass);
-  const uint32_t shift = pass * kRadixBits;
-  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-  const uint32_t base = tile * kTile;
-  const uint32_t tile_n = min((uint32_t)kTile, n - base);
-
-  // This tile's output position for each digit: loaded first, used last.
-  const uint32_t dstart = tid < kRadix ? table[(uint64_t)tid * ntiles + tile] : 0u;
-  for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
-  // ---- load: wave w owns 64*kItems consecutive elements -----------------------
-  const uint32_t w = tid / 64, lane = lane_id();
+  const uint32_t w = threadIdx.x / 64, lane = lane_id();
   const uint32_t wbase = w * 64 * kItems;
-  uint32_t key[kItems], row[kItems];
   if (tile_n == (uint32_t)kTile) {  // uniform: every load of a full tile is issued unconditionally
 #pragma unroll
     for (int i = 0; i < kItems; ++i) key[i] = __builtin_nontemporal_load(io.src_keys + base + wbase + i * 64 + lane);
@@ -303,6 +296,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
       row[i] = valid ? (io.implicit_rows ? g : io.src_rows[g]) : 0u;
     }
   }
+}
+
+// Ranks, reorders and writes one tile whose keys and rows are in registers
+// (their loads may still be in flight); dstart = the table entry of digit
+// threadIdx.x for this tile.  Starts and ends with a barrier.
+template <int kBlock, int kItems>
+__device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, const PassIo& io, uint32_t shift,
+                                             uint32_t tile_n, uint32_t dstart, const uint32_t (&key)[kItems],
+                                             const uint32_t (&row)[kItems]) {
+  constexpr int kWaves = kBlock / 64;
+  const uint32_t tid = threadIdx.x, w = tid / 64, lane = lane_id();
+  const uint32_t wbase = w * 64 * kItems;
+  for (int i = tid; i < kWaves * kRadix; i += kBlock) (&L.wcnt[0][0])[i] = 0;
   __syncthreads();
 
   // ---- rank inside the wave: peers = lanes with the same digit ----------------
@@ -323,8 +329,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
     }
     if (valid) {
       const uint32_t below = (uint32_t)__popcll(peers & lt);
-      const uint32_t old = s_wcnt[w][d];
-      if (below == 0) s_wcnt[w][d] = (uint16_t)(old + (uint32_t)__popcll(peers));
+      const uint32_t old = L.wcnt[w][d];
+      if (below == 0) L.wcnt[w][d] = (uint16_t)(old + (uint32_t)__popcll(peers));
       r = old + below;
     }
     rank[i] = r;
@@ -336,16 +342,16 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   if (tid < kRadix) {
 #pragma unroll
     for (int ww = 0; ww < kWaves; ++ww) {
-      const uint32_t c = s_wcnt[ww][tid];
-      s_wcnt[ww][tid] = (uint16_t)tile_count;
+      const uint32_t c = L.wcnt[ww][tid];
+      L.wcnt[ww][tid] = (uint16_t)tile_count;
       tile_count += c;
     }
   }
   uint32_t total;
-  const uint32_t loff = block_excl_scan<kBlock>(tid < kRadix ? tile_count : 0u, s_scan, &total);
+  const uint32_t loff = block_excl_scan<kBlock>(tid < kRadix ? tile_count : 0u, L.scan, &total);
   if (tid < kRadix) {
-    s_loff[tid] = loff;
-    s_dbase[tid] = dstart - loff;
+    L.loff[tid] = loff;
+    L.dbase[tid] = dstart - loff;
   }
   __syncthreads();
 
@@ -354,9 +360,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   for (int i = 0; i < kItems; ++i) {
     if (wbase + i * 64 + lane < tile_n) {
       const uint32_t d = (key[i] >> shift) & (kRadix - 1);
-      const uint32_t pos = s_loff[d] + s_wcnt[w][d] + rank[i];
-      s_keys[pos] = key[i];
-      s_rows[pos] = row[i];
+      const uint32_t pos = L.loff[d] + L.wcnt[w][d] + rank[i];
+      L.keys[pos] = key[i];
+      L.rows[pos] = row[i];
     }
   }
   __syncthreads();
@@ -366,12 +372,33 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   for (int i = 0; i < kItems; ++i) {
     const uint32_t p = i * kBlock + tid;
     if (p < tile_n) {
-      const uint32_t k = s_keys[p];
-      const uint32_t g = s_dbase[(k >> shift) & (kRadix - 1)] + p;
+      const uint32_t k = L.keys[p];
+      const uint32_t g = L.dbase[(k >> shift) & (kRadix - 1)] + p;
       io.dst_keys[g] = k;
-      io.dst_rows[g] = s_rows[p];
+      io.dst_rows[g] = L.rows[p];
     }
   }
+  __syncthreads();  // the LDS buffers are free again
+}
+
+// One work-group per tile.
+template <int kBlock, int kItems>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const SortPlan* __restrict__ plan,
+                                                          const uint32_t* __restrict__ table, uint32_t pass,
+                                                          uint32_t n, uint32_t ntiles) {
+  constexpr int kTile = kBlock * kItems;
+  __shared__ ScatterLds<kBlock, kItems> L;
+  const uint32_t active = plan->active;
+  if (!((active >> pass) & 1u)) return;
+  const PassIo io = pass_io(buf, active, pass);
+  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+  const uint32_t base = tile * kTile;
+  const uint32_t tile_n = min((uint32_t)kTile, n - base);
+  // This tile's output position for each digit: loaded first, used last.
+  const uint32_t dstart = threadIdx.x < kRadix ? table[(uint64_t)threadIdx.x * ntiles + tile] : 0u;
+  uint32_t key[kItems], row[kItems];
+  scatter_load<kBlock, kItems>(io, base, tile_n, key, row);
+  scatter_tile<kBlock, kItems>(L, io, pass * kRadixBits, tile_n, dstart, key, row);
 }
 
 }  // namespace

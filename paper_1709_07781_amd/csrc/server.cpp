@@ -124,7 +124,7 @@ struct Server {
   System* sys = nullptr;
   uint32_t streams = 2, max_batch = 1024, value_bits = 12;
   uint64_t budget = 64ull << 30;
-  uint64_t max_batch_bytes = 64ull << 20;
+  uint64_t max_batch_bytes = 16ull << 20;
   std::vector<uint32_t> chain_a, chain_b;
 
   std::mutex mu;
@@ -170,7 +170,9 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
   };
   const uint64_t d_vw = place(4 * nw), d_vs = place(4 * ns), d_vc = place(4 * nc);
   const uint64_t d_rw = place(4 * (rw + 1ull)), d_rs = place(4 * (rs + 1ull));
-  const uint64_t d_keys = place(4 * nw), d_offs = place(4 * (nw + rw)), d_words = place(8 * nw);
+  // a request has at most 2^value_bits distinct values: that bounds the lookup tables
+  const uint64_t dcap = value_bits >= 32 ? nw : std::min<uint64_t>(nw, (uint64_t)rw << value_bits);
+  const uint64_t d_keys = place(4 * dcap), d_offs = place(4 * (dcap + rw)), d_words = place(8 * nw);
   const uint64_t d_ks = place(4 * (rw + 1ull)), d_ws = place(4 * (rw + 1ull)), d_lens = place(5 * 8);
   const uint64_t d_scan = place(4 * ns);
   const uint64_t total = off;
@@ -424,7 +426,7 @@ KA_API int ka_server_create(ka_system* sys, const ka_server_config* cfg, ka_serv
   const uint32_t want = cfg && cfg->streams ? cfg->streams : 2;
   s->streams = std::max<uint32_t>(1, std::min<uint32_t>(want, (uint32_t)sys->streams.size()));
   s->max_batch = cfg && cfg->max_batch ? cfg->max_batch : 1024;
-  s->max_batch_bytes = cfg && cfg->max_batch_bytes ? cfg->max_batch_bytes : (64ull << 20);
+  s->max_batch_bytes = cfg && cfg->max_batch_bytes ? cfg->max_batch_bytes : (16ull << 20);
   s->budget = cfg && cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (64ull << 30);
   s->value_bits = cfg && cfg->value_bits ? cfg->value_bits : 12;
   const uint32_t req_bits = s->max_batch > 1 ? 32u - (uint32_t)__builtin_clz(s->max_batch - 1) : 0u;
