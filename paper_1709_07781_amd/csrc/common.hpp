@@ -98,30 +98,6 @@ inline int check_launch(Env& env, const char* what) {
   return kOk;
 }
 
-// Work-groups of `kernel` that fit on the device at once (occupancy x CUs).
-int coresident_blocks(const void* kernel, int block_threads);
-
-// Persistent look-back kernels: the grid is the number of work-groups that fit
-// on the device at once (or the tile count, if smaller), each taking tiles
-// from the stream's ticket counter until they run out.
-template <typename... Args>
-int launch_persistent(Env& env, const char* name, void (*kernel)(Args...), uint32_t tiles, uint32_t block,
-                      Args... args) {
-  int cap = coresident_blocks(reinterpret_cast<const void*>(kernel), (int)block);
-  if (cap <= 0) return env.fail(kErrLaunch, "persistent launch: no resident work-group fits");
-  const uint32_t grid = tiles < (uint32_t)cap ? (tiles ? tiles : 1u) : (uint32_t)cap;
-  void* params[] = {reinterpret_cast<void*>(&args)...};
-  env.prof_begin(name);
-  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(block), params,
-                                            0, env.stream());
-  env.prof_end(name);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return env.fail(kErrLaunch, name);
-  }
-  return kOk;
-}
-
 // ------------------------------------------------------------------------------
 // Device side.
 // ------------------------------------------------------------------------------

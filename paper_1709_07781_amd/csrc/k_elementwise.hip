@@ -2,8 +2,6 @@
 // per-stage workload of the kernel-stage overhead experiments (Sec. 3.6 empty
 // stage probe, Sec. 5.2-5.3), and small fill kernels used instead of
 // hipMemsetAsync so that the queued work stays capturable in a hipGraph.
-#include <map>
-#include <mutex>
 
 #include "common.hpp"
 
@@ -113,32 +111,6 @@ int launch_fill_u32(Env& env, uint32_t* p, uint64_t count, uint32_t value) {
 int launch_set_len(Env& env, uint64_t* d_len, uint64_t value) {
   k_set_len<<<dim3(1), dim3(64), 0, env.stream()>>>(d_len, value);
   return check_launch(env, "set_len launch");
-}
-
-int coresident_blocks(const void* kernel, int block_threads) {
-  // Cached per (device, kernel, block size); the device's CU count and the
-  // kernel's occupancy do not change during the process.
-  struct Key {
-    int dev;
-    const void* k;
-    int b;
-    bool operator<(const Key& o) const {
-      return dev != o.dev ? dev < o.dev : (k != o.k ? k < o.k : b < o.b);
-    }
-  };
-  static std::mutex mu;
-  static std::map<Key, int> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return -1;
-  std::lock_guard<std::mutex> g(mu);
-  auto it = cache.find({dev, kernel, block_threads});
-  if (it != cache.end()) return it->second;
-  int cus = 0, per_cu = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block_threads, 0) != hipSuccess) return -1;
-  const int cap = per_cu * cus;
-  cache[{dev, kernel, block_threads}] = cap;
-  return cap;
 }
 
 int launch_copy_len(Env& env, uint64_t* dst, const uint64_t* src) {
