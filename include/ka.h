@@ -148,7 +148,12 @@ KA_API const char* ka_last_error(void); /* thread-local message of the last fail
 
 /* ---- system ---------------------------------------------------------------------- */
 /* Creates a system.  cfg may be NULL (defaults).  Touches no device until
- * needed; a later call fails with KA_E_DEVICE if the device is not gfx950. */
+ * needed; a later call fails with KA_E_DEVICE if the device is not gfx950.
+ * The environment variable KA_LOOKBACK_SPIN, read when the device is first
+ * used, sets how many times a scan tile polls a predecessor tile that has not
+ * published its total before computing that total from its input (default
+ * 16; 1 takes that path at once, which tests use).  Results never depend on
+ * it. */
 KA_API int ka_system_create(const ka_system_config* cfg, ka_system** out);
 /* Waits for all work in flight, then frees every resource the system holds.
  * Objects still referenced by the caller become unusable (KA_E_STATE). */

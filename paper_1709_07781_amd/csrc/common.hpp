@@ -1,6 +1,6 @@
 // Shared internals of the kernel library: launch environment handed from the
-// runtime to the kernel launchers, and device helpers (wave64 scans, tile
-// tickets and decoupled look-back).
+// runtime to the kernel launchers, and device helpers (wave64 scans and
+// decoupled look-back).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,35 +13,30 @@ namespace ka {
 // Host side: what a launcher needs from the runtime.
 // ------------------------------------------------------------------------------
 
-// Look-back state of one stream.  Work-groups of a look-back kernel take their
-// tiles from a ticket counter, in order, so a tile only ever waits for tiles
-// that running work-groups hold -- no co-residency guarantee (and no
-// cooperative launch) is needed.  The counter is 0 between launches: a launch
-// draws a number of tickets fixed by its grid and tile count, and the draw of
-// the last one puts the counter back to 0.  Status words are tagged with a per-launch epoch, so
+// Look-back state of one stream.  A look-back kernel numbers its tiles by
+// work-group id, and every wait in its look-back is bounded (see
+// lb_lookback), so it needs no co-residency guarantee, no cooperative launch
+// and no ticket counter.  Status words are tagged with a per-launch epoch, so
 // stale words from earlier launches read as "not yet published" and nothing
 // has to be cleared between launches.
 struct LookbackArena {
-  unsigned long long* ticket = nullptr;  // device counter, 0 between launches
-  uint64_t* status = nullptr;            // device status words
+  uint64_t* status = nullptr;  // device status words
   uint64_t status_words = 0;
-  uint64_t status_bytes = 0;             // size of the pool block holding `status`
-  uint32_t epoch = 0;                    // last epoch handed out (1 .. 2^30-1)
-  uint32_t* hist[2] = {nullptr, nullptr};  // radix digit histograms, double-buffered
-  uint32_t hist_turn = 0;
-  void* plan = nullptr;                    // radix sort plan (kSortPlanBytes)
+  uint64_t status_bytes = 0;   // size of the pool block holding `status`
+  uint32_t epoch = 0;          // last epoch handed out (1 .. 2^30-1)
+  void* plan = nullptr;        // radix sort plan: kSortPlanBytes of device memory
 };
 
-// Device memory of one arena: ticket counter, two histograms, the sort plan.
-constexpr uint32_t kArenaTicketBytes = 256, kArenaHistBytes = 4096, kSortPlanBytes = 8192;
-constexpr uint32_t kArenaBytes = kArenaTicketBytes + 2 * kArenaHistBytes + kSortPlanBytes;
+constexpr uint32_t kSortPlanBytes = 8192;
 
 // Per-launch arguments of a look-back kernel.
 struct LbArgs {
-  unsigned long long* ticket;
   uint64_t* status;
   uint32_t epoch;
+  uint32_t spin_limit;  // polls of a silent predecessor before the fallback (>= 1)
 };
+
+constexpr uint32_t kLbSpinLimit = 16;  // the default spin_limit
 
 class Env {
  public:
@@ -154,22 +149,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wave
   return before + inc - x;
 }
 
-// ---- tickets and look-back ----------------------------------------------------
+// ---- decoupled look-back -------------------------------------------------------
 
 constexpr uint32_t kNoTile = 0xFFFFFFFFu;
-
-// One lane draws a ticket: the tile to process, or kNoTile once the tiles are
-// used up.  `last` is the launch's final draw -- gridDim.x - 1 when every
-// work-group draws once, ntiles + gridDim.x - 1 when work-groups draw until
-// they get a ticket past the last tile -- and its draw returns the counter to
-// 0.  A work-group must not hold an unstarted ticket while it waits in a
-// look-back: tiles after it would wait for it in turn, and those waits add up
-// from one tile to the next.
-__device__ __forceinline__ uint32_t lb_draw(const LbArgs& a, uint64_t ntiles, uint64_t last) {
-  const unsigned long long t = atomicAdd(a.ticket, 1ull);
-  if (t == last) __hip_atomic_store(a.ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return t < ntiles ? (uint32_t)t : kNoTile;
-}
 
 __device__ __forceinline__ uint64_t lb_pack(uint32_t value, uint32_t epoch, uint32_t flag) {
   return ((uint64_t)value << 32) | ((uint64_t)epoch << 2) | flag;
@@ -188,28 +170,35 @@ __device__ __forceinline__ uint32_t lb_flag(uint64_t w, uint32_t epoch) {
   return (((uint32_t)w >> 2) == epoch) ? ((uint32_t)w & 3u) : 0u;
 }
 
-// Decoupled look-back by one whole wave over a single channel whose status
-// word for tile t is status[t * stride].  In a round, lane l inspects the
-// kDepth predecessors j - kDepth*l .. j - kDepth*l - kDepth + 1, so one round
-// trip to memory covers 64*kDepth tiles; the window slides back until an
-// inclusive prefix is found.  Returns the exclusive prefix of `tile` in every
-// lane.  Every lane of the wave must call it.
-template <int kDepth>
-__device__ __forceinline__ uint32_t lb_lookback_wave(const uint64_t* status, uint32_t stride, uint32_t tile,
-                                                     uint32_t epoch) {
+// Decoupled look-back with fallback by one whole wave; status[t] is tile t's
+// status word.  In a round, lane l inspects the kDepth predecessors
+// j - kDepth*l .. j - kDepth*l - kDepth + 1, so one round trip to memory covers
+// 64*kDepth tiles; the window slides back until an inclusive prefix is found.
+// A predecessor that has published nothing after spin_limit polls is no
+// longer waited for: the wave computes its total itself with reduce(t) --
+// every lane calls it, and it returns the tile's total in every lane -- adds
+// it and goes on from the tile before it.  Every wait is therefore bounded
+// whatever order the work-groups run in, so tiles can be numbered by
+// work-group id.  reduce(t) may only read data that no work-group of the
+// launch writes.  Returns the exclusive prefix of `tile` in every lane.
+template <int kDepth, class Reduce>
+__device__ __forceinline__ uint32_t lb_lookback(const uint64_t* status, uint32_t tile, uint32_t epoch,
+                                                uint32_t spin_limit, Reduce&& reduce) {
   const uint32_t lane = lane_id();
   uint32_t excl = 0;
   int64_t j = (int64_t)tile - 1;
+  uint32_t spins = 0;
   while (j >= 0) {
     uint64_t w[kDepth];
 #pragma unroll
     for (int k = 0; k < kDepth; ++k) {
       const int64_t idx = j - (int64_t)(kDepth * lane + k);
-      w[k] = idx >= 0 ? lb_load(status + (uint64_t)idx * stride) : 0ull;
+      w[k] = idx >= 0 ? lb_load(status + idx) : 0ull;
     }
-    // This lane's run of predecessors, nearest first: 2 = reaches an inclusive
-    // prefix (or the start), 1 = all aggregates, 0 = meets an unpublished tile.
-    uint32_t state = 1, sum = 0;
+    // This lane's run of predecessors, nearest first: state 2 = reaches an
+    // inclusive prefix (or the start), 1 = all aggregates, 0 = meets an
+    // unpublished tile, at position `gap`; sum = the values before it.
+    uint32_t state = 1, sum = 0, gap = 0;
 #pragma unroll
     for (int k = 0; k < kDepth; ++k) {
       if (state != 1) break;
@@ -221,6 +210,7 @@ __device__ __forceinline__ uint32_t lb_lookback_wave(const uint64_t* status, uin
       const uint32_t f = lb_flag(w[k], epoch);
       if (f == 0) {
         state = 0;
+        gap = (uint32_t)k;
         break;
       }
       sum += (uint32_t)(w[k] >> 32);
@@ -230,13 +220,27 @@ __device__ __forceinline__ uint32_t lb_lookback_wave(const uint64_t* status, uin
     const uint64_t stall = __ballot(state == 0);
     const uint32_t stop = inc ? (uint32_t)__builtin_ctzll(inc) : 63u;
     const uint64_t need = (stop == 63u) ? ~0ull : ((2ull << stop) - 1ull);
-    if (stall & need) {
-      __builtin_amdgcn_s_sleep(1);
+    const uint64_t blocked = stall & need;
+    if (blocked) {
+      if (++spins < spin_limit) {
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      // The nearest unpublished tile u: lanes below s saw aggregates only,
+      // lane s those before u.  Take u's total from its input.
+      const uint32_t s = (uint32_t)__builtin_ctzll(blocked);
+      const uint32_t gs = (uint32_t)__builtin_amdgcn_readlane((int)gap, (int)s);
+      excl += wave_sum(lane <= s ? sum : 0u);
+      const int64_t u = j - (int64_t)(kDepth * s + gs);
+      excl += reduce((uint32_t)u);
+      j = u - 1;
+      spins = 0;
       continue;
     }
     excl += wave_sum(lane <= stop ? sum : 0u);
     if (inc) break;
     j -= 64 * kDepth;
+    spins = 0;
   }
   return excl;
 }

@@ -9,9 +9,9 @@
 //    the tile's keys, from which k_radix_plan forms the sort plan: a pass whose
 //    digit is the same in every key (equal in the OR and the AND) is the
 //    identity of a stable sort and is skipped, so 16-bit keys cost two passes.
-//  * the exclusive scan of the table (the look-back scan kernel, in place)
-//    turns every count into the output position of the tile's first key with
-//    that digit.
+//  * the exclusive scan of the table (the look-back scan kernel, into a
+//    second table) turns every count into the output position of the tile's
+//    first key with that digit.
 //  * k_radix_scatter (one work-group per tile) ranks its keys by digit inside
 //    each wave -- the lanes holding the same digit are found with one ballot
 //    per digit bit, and a key's rank is the number of such lanes below it
@@ -421,8 +421,10 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
   buf.keys_b = static_cast<uint32_t*>(env.scratch(n * 4));
   buf.rows_b = static_cast<uint32_t*>(env.scratch(n * 4));
   uint32_t* table = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * kRadix * 4));
+  uint32_t* offs = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * kRadix * 4));
   uint32_t* orand = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * 2 * 4));
-  if (!buf.keys_b || !buf.rows_b || !table || !orand) return env.fail(kErrOom, "radix_sort: scratch buffers");
+  if (!buf.keys_b || !buf.rows_b || !table || !offs || !orand)
+    return env.fail(kErrOom, "radix_sort: scratch buffers");
   // One work-group per tile.  (Grid-stride versions with occupancy-sized
   // grids made skipped passes cheaper but active scatters 50% slower: the two
   // work-groups of a CU then run their phases in step instead of interleaved.)
@@ -448,13 +450,14 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
       int rc = check_launch(env, "radix_upsweep launch");
       if (rc) return rc;
     }
-    // Offsets: exclusive scan of the digit-major table, in place; the plan
-    // gives a skipped pass a scan of length 0.
-    int rc = launch_exclusive_scan(env, table, table, (uint64_t)ntiles * kRadix, &plan->scan_len[pass]);
+    // Offsets: exclusive scan of the digit-major table into offs (the scan's
+    // input and output must not overlap); the plan gives a skipped pass a
+    // scan of length 0.
+    int rc = launch_exclusive_scan(env, table, offs, (uint64_t)ntiles * kRadix, &plan->scan_len[pass]);
     if (rc) return rc;
     env.prof_begin("radix_scatter");
     k_radix_scatter<kBlock, kItems><<<dim3(g_sc), dim3(kBlock), 0, env.stream()>>>(
-        buf, static_cast<const SortPlan*>(plan), table, pass, nn, ntiles);
+        buf, static_cast<const SortPlan*>(plan), offs, pass, nn, ntiles);
     env.prof_end("radix_scatter");
     rc = check_launch(env, "radix_scatter launch");
     if (rc) return rc;

@@ -6,10 +6,10 @@
 // The plan owns every buffer the pipeline touches -- the input, the request
 // table, the outputs and one scratch arena handed out by a bump allocator --
 // so nothing is allocated while the graph is captured or replayed.  Look-back
-// kernels get the plan's own ticket counter (returned to 0 by each launch's
-// last draw) and status words, which a fill kernel inside the graph clears
-// before each look-back launch: the epoch baked into a replayed launch is
-// always the same, so stale words must not survive from the previous replay.
+// kernels get the plan's own status words, which a fill kernel inside the
+// graph clears before each look-back launch: the epoch baked into a replayed
+// launch is always the same, so stale words must not survive from the
+// previous replay.
 #include <cstring>
 
 #include "runtime_internal.hpp"
@@ -38,9 +38,9 @@ class PlanEnv final : public Env {
   bool lookback(uint64_t words, LbArgs* out) override {
     if (words > lb.status_words) return false;
     if (launch_fill_u64(*this, lb.status, words, 0) != kOk) return false;
-    out->ticket = lb.ticket;
     out->status = lb.status;
     out->epoch = 1;
+    out->spin_limit = kLbSpinLimit;
     return true;
   }
   LookbackArena* arena() override { return &lb; }
@@ -127,8 +127,8 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
   // ---- one allocation: input, table, outputs, look-back state, scratch arena -----------
   const uint64_t n1 = n ? n : 1;
   const uint64_t sort_tiles = (n + 8191) / 8192, enc_tiles = (n + 4095) / 4096;
-  const uint64_t scan_tiles = 2 * ((256 * sort_tiles + 4095) / 4096) + 2;  // margin for smaller sort tiles
-  const uint64_t arena_bytes = 24 * n1 + 2 * sort_tiles * 1040 + 8 * enc_tiles + (64ull << 10);
+  const uint64_t scan_tiles = 2 * ((256 * sort_tiles + 4095) / 4096) + 2;  // scan tiles hold >= 4096 entries
+  const uint64_t arena_bytes = 24 * n1 + 2 * sort_tiles * 2064 + 8 * enc_tiles + (64ull << 10);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     const uint64_t o = off;
@@ -137,7 +137,7 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
   };
   const uint64_t o_in = take(4 * n1), o_req = take(4 * (nreq + 1ull)), o_keys = take(4 * n1);
   const uint64_t o_offs = take(4 * (n + nreq)), o_words = take(8 * n1), o_ks = take(4 * (nreq + 1ull));
-  const uint64_t o_ws = take(4 * (nreq + 1ull)), o_lens = take(5 * 8), o_ticket = take(256);
+  const uint64_t o_ws = take(4 * (nreq + 1ull)), o_lens = take(5 * 8);
   const uint64_t o_plan = take(kSortPlanBytes), o_status = take(8 * scan_tiles), o_arena = take(arena_bytes);
   if (hipMalloc(&p->mem, off) != hipSuccess) {
     (void)hipGetLastError();
@@ -154,7 +154,6 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
   p->word_start = reinterpret_cast<uint32_t*>(m + o_ws);
   p->lens = reinterpret_cast<uint64_t*>(m + o_lens);
   PlanEnv& e = p->env;
-  e.lb.ticket = reinterpret_cast<unsigned long long*>(m + o_ticket);
   e.lb.plan = m + o_plan;
   e.lb.status = reinterpret_cast<uint64_t*>(m + o_status);
   e.lb.status_words = scan_tiles;
@@ -166,9 +165,8 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
     return set_error(KA_E_DEVICE, "plan: stream creation");
   }
   e.s = p->s;
-  // the ticket counter starts at 0; the request table is uploaded once
-  if (hipMemsetAsync(m + o_ticket, 0, 256, p->s) != hipSuccess ||
-      hipMemcpyAsync(p->req_off, req_off, 4 * (nreq + 1ull), hipMemcpyHostToDevice, p->s) != hipSuccess ||
+  // the request table is uploaded once
+  if (hipMemcpyAsync(p->req_off, req_off, 4 * (nreq + 1ull), hipMemcpyHostToDevice, p->s) != hipSuccess ||
       hipStreamSynchronize(p->s) != hipSuccess) {
     (void)hipGetLastError();
     plan_free(p);

@@ -98,16 +98,18 @@ int System::ensure_init() {
     streams.push_back(std::move(sc));
   }
   pool.init(this, cfg.hbm_budget_bytes);
-  // Per-stream look-back arenas: ticket counter and two zeroed histograms.
+  // Look-back spin limit: polls of a silent predecessor tile before its total
+  // is computed from its input instead (1 = at once; for tests of that path).
+  if (const char* e = std::getenv("KA_LOOKBACK_SPIN")) {
+    const long v = std::strtol(e, nullptr, 10);
+    lb_spin = v < 1 ? 1u : v > 1000000 ? 1000000u : (uint32_t)v;
+  }
+  // Per-stream sort plan storage (the status words come from the pool on first use).
   for (auto& sc : streams) {
     void* p = nullptr;
-    if (hipMalloc(&p, kArenaBytes) != hipSuccess) return fail(KA_E_OOM, "arena allocation failed");
-    if (hipMemset(p, 0, kArenaBytes) != hipSuccess) return fail(KA_E_DEVICE, "arena clear failed");
-    char* b = static_cast<char*>(p);
-    sc->arena.ticket = reinterpret_cast<unsigned long long*>(b);
-    sc->arena.hist[0] = reinterpret_cast<uint32_t*>(b + kArenaTicketBytes);
-    sc->arena.hist[1] = reinterpret_cast<uint32_t*>(b + kArenaTicketBytes + kArenaHistBytes);
-    sc->arena.plan = b + kArenaTicketBytes + 2 * kArenaHistBytes;
+    if (hipMalloc(&p, kSortPlanBytes) != hipSuccess) return fail(KA_E_OOM, "arena allocation failed");
+    if (hipMemset(p, 0, kSortPlanBytes) != hipSuccess) return fail(KA_E_DEVICE, "arena clear failed");
+    sc->arena.plan = p;
   }
   init_rc = KA_OK;
   return KA_OK;
@@ -905,7 +907,7 @@ KA_API int ka_system_destroy(ka_system* sys) {
     sys->stage.destroy(sys);
     for (auto& sc : sys->streams) {
       sc->arena.status = nullptr;  // a pool block, freed with the pool below
-      hipFree(sc->arena.ticket);
+      hipFree(sc->arena.plan);
     }
     sys->pool.destroy();
     {

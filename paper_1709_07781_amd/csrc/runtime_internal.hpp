@@ -105,6 +105,7 @@ struct System {
   Pool pool;
   HostStage stage;
   std::atomic<bool> profile{false};
+  uint32_t lb_spin = kLbSpinLimit;  // look-back spin limit (KA_LOOKBACK_SPIN)
   std::mutex ev_mu;
   std::vector<hipEvent_t> events;  // pool of timing-disabled events
   std::mutex prof_mu;
@@ -130,7 +131,7 @@ struct System {
 class CmdEnv final : public Env {
  public:
   // The stream's lock is held for the whole command, so the stream's
-  // look-back arena (ticket counter, status words, epochs) serves one launch
+  // look-back arena (status words, epochs, sort plan) serves one launch
   // at a time, in stream order.
   CmdEnv(System* sys, uint32_t si) : sys_(sys), si_(si), lock_(sys->streams[si]->mu) {}
   ~CmdEnv() override {
@@ -163,9 +164,9 @@ class CmdEnv final : public Env {
       ar.epoch = 0;
     }
     ar.epoch += 1;
-    out->ticket = ar.ticket;
     out->status = ar.status;
     out->epoch = ar.epoch;
+    out->spin_limit = sys_->lb_spin;
     return true;
   }
   LookbackArena* arena() override { return &sys_->streams[si_]->arena; }

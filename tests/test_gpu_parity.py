@@ -9,7 +9,8 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-SCAN_TILE, SORT_TILE, ENC_TILE = 4096, 8192, 2048
+SCAN_TILE, SORT_TILE, ENC_TILE = 8192, 8192, 2048
+LARGE_SCAN, LARGE_SCAN_TILE = 1 << 23, 16384  # scans above LARGE_SCAN elements use the larger tile
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +33,7 @@ def _ka():
 
 # ---- exclusive scan ------------------------------------------------------------------
 SCAN_SIZES = [1, 2, 3, 4, 5, 63, 64, 65, SCAN_TILE - 1, SCAN_TILE, SCAN_TILE + 1, 3 * SCAN_TILE + 7,
-              70 * SCAN_TILE + 3, (1 << 20) + 1]
+              70 * SCAN_TILE + 3, (1 << 20) + 1, LARGE_SCAN, LARGE_SCAN + 1, LARGE_SCAN + 3 * LARGE_SCAN_TILE + 5]
 
 
 @pytest.mark.parametrize("n", SCAN_SIZES)
