@@ -14,6 +14,7 @@ import json
 import os
 import re
 import sys
+import threading
 import time
 
 import numpy as np
@@ -264,7 +265,21 @@ def bench_served(args) -> int:
         batched_kw = dict(streams=args.served_streams, max_batch=1024, max_batch_bytes=args.served_batch_mb << 20)
         for form, kw in (("batched", batched_kw), ("plain", dict(streams=1, max_batch=1))):
             srv = Server(sess, chain_a=a, chain_b=b, **kw)
-            handles = []
+            # a client thread takes each result as it completes and releases it
+            handles = [None] * count
+            submitted = threading.Semaphore(0)
+            failures = []
+
+            def consume():
+                for j in range(count):
+                    submitted.acquire()
+                    rc = srv.wait(handles[j])
+                    if rc != 0:
+                        failures.append(rc)
+                    srv.release(handles[j])
+
+            consumer = threading.Thread(target=consume)
+            consumer.start()
             t0 = Server.clock_us() + 20_000.0  # first arrival 20 ms from now
             w0 = time.perf_counter()
             for j in range(count):
@@ -276,12 +291,11 @@ def bench_served(args) -> int:
                     if due - now > 200:
                         time.sleep((due - now - 100) * 1e-6)
                 pool = pool_idx if kinds[j] == workloads.KIND_WAH else pool_u32
-                handles.append(srv.submit(int(kinds[j]), pool[starts[j]:starts[j] + sizes[j]], arrival_us=due))
-            for h in handles:
-                rc = srv.wait(h)
-                if rc != 0:
-                    raise RuntimeError(f"served request failed: {rc}")
-                srv.release(h)
+                handles[j] = srv.submit(int(kinds[j]), pool[starts[j]:starts[j] + sizes[j]], arrival_us=due)
+                submitted.release()
+            consumer.join()
+            if failures:
+                raise RuntimeError(f"served request failed: {failures[0]}")
             wall = time.perf_counter() - w0
             st = srv.stats()
             srv.close()

@@ -198,13 +198,15 @@ int Pool::alloc(uint64_t bytes, uint32_t stream, void** out, uint64_t* got) {
   const uint64_t c = size_class(bytes);
   std::lock_guard<std::mutex> g(mu_);
   if (!deferred_.empty()) poll_deferred_locked();
+  // a free block of the size class or up to twice it (batches of varying
+  // size then reuse blocks instead of calling hipMalloc each time)
   auto& fl = free_[stream];
-  auto it = fl.find(c);
-  if (it != fl.end()) {
+  auto it = fl.lower_bound(c);
+  if (it != fl.end() && it->first <= 2 * c) {
     *out = it->second;
-    *got = c;
+    *got = it->first;
+    in_use_ += it->first;
     fl.erase(it);
-    in_use_ += c;
     return KA_OK;
   }
   if (budget_ && in_use_ + c > budget_)
@@ -262,32 +264,39 @@ void Pool::destroy() {
 // ---------------------------------------------------------------------------------
 // pinned host staging
 // ---------------------------------------------------------------------------------
+// A free buffer of the size class, or of up to twice it, is reused; otherwise
+// a new one is allocated -- outside the lock, since pinning takes
+// milliseconds for large buffers and other threads (request submission, the
+// mailbox thread) take buffers meanwhile.
 void* HostStage::get(System* sys, uint64_t bytes) {
   const uint64_t c = Pool::size_class(bytes);
-  std::lock_guard<std::mutex> g(mu_);
-  for (size_t i = 0; i < busy_.size();) {
-    const hipError_t q = hipEventQuery(busy_[i].done);
-    if (q != hipSuccess) (void)hipGetLastError();  // "not ready" must not stay pending
-    if (q == hipSuccess) {
-      sys->put_event(busy_[i].done);
-      free_.emplace(busy_[i].bytes, busy_[i].p);
-      busy_[i] = busy_.back();
-      busy_.pop_back();
-    } else {
-      ++i;
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    for (size_t i = 0; i < busy_.size();) {
+      const hipError_t q = hipEventQuery(busy_[i].done);
+      if (q != hipSuccess) (void)hipGetLastError();  // "not ready" must not stay pending
+      if (q == hipSuccess) {
+        sys->put_event(busy_[i].done);
+        free_.emplace(busy_[i].bytes, busy_[i].p);
+        busy_[i] = busy_.back();
+        busy_.pop_back();
+      } else {
+        ++i;
+      }
     }
-  }
-  auto it = free_.find(c);
-  if (it != free_.end()) {
-    void* p = it->second;
-    free_.erase(it);
-    return p;
+    auto it = free_.lower_bound(c);
+    if (it != free_.end() && it->first <= 2 * c) {
+      void* p = it->second;
+      free_.erase(it);
+      return p;
+    }
   }
   void* p = nullptr;
   if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
   }
+  std::lock_guard<std::mutex> g(mu_);
   sizes_[p] = c;
   return p;
 }

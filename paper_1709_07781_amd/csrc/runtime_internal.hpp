@@ -32,7 +32,8 @@ struct System;
 class Pool {
  public:
   void init(System* sys, uint64_t budget);
-  // bytes are rounded up to a size class; *got receives the class size.
+  // bytes are rounded up to a size class; *got receives the size of the block
+  // handed out (the class, or a cached block of up to twice it).
   int alloc(uint64_t bytes, uint32_t stream, void** out, uint64_t* got);
   void release(void* p, uint64_t bytes, uint32_t home, uint64_t used_mask);
   void destroy();
