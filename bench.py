@@ -257,45 +257,57 @@ def bench_served(args) -> int:
     rows = []
     for rate in rates:
         count = int(min(args.served_max, max(50, rate * args.served_seconds)))
-        t, sizes, kinds, dseeds = workloads.served_requests(seed=5, count=count, rate_per_s=rate)
+        warm = max(50, count // 8)
+        t, sizes, kinds, dseeds = workloads.served_requests(seed=5, count=warm + count, rate_per_s=rate)
         sizes = np.minimum(sizes, pool_n)
         starts = (dseeds % np.uint64(pool_n)).astype(np.int64)
         starts = np.minimum(starts, pool_n - sizes)
-        res = {"rate_per_s": rate, "requests": count}
+        res = {"rate_per_s": rate, "requests": count, "warmup_requests": warm}
         batched_kw = dict(streams=args.served_streams, max_batch=1024, max_batch_bytes=args.served_batch_mb << 20)
         for form, kw in (("batched", batched_kw), ("plain", dict(streams=1, max_batch=1))):
             srv = Server(sess, chain_a=a, chain_b=b, **kw)
-            # a client thread takes each result as it completes and releases it
-            handles = [None] * count
-            submitted = threading.Semaphore(0)
-            failures = []
 
-            def consume():
-                for j in range(count):
-                    submitted.acquire()
-                    rc = srv.wait(handles[j])
-                    if rc != 0:
-                        failures.append(rc)
-                    srv.release(handles[j])
+            def run(lo, hi):
+                """Requests lo..hi-1 on their schedule; a client thread takes
+                each result as it completes and releases it."""
+                m = hi - lo
+                handles = [None] * m
+                submitted = threading.Semaphore(0)
+                failures = []
 
-            consumer = threading.Thread(target=consume)
-            consumer.start()
-            t0 = Server.clock_us() + 20_000.0  # first arrival 20 ms from now
+                def consume():
+                    for j in range(m):
+                        submitted.acquire()
+                        rc = srv.wait(handles[j])
+                        if rc != 0:
+                            failures.append(rc)
+                        srv.release(handles[j])
+
+                consumer = threading.Thread(target=consume)
+                consumer.start()
+                t0 = Server.clock_us() + 20_000.0 - t[lo] * 1e6  # first arrival 20 ms from now
+                for j in range(m):
+                    due = t0 + t[lo + j] * 1e6
+                    while True:
+                        now = Server.clock_us()
+                        if now >= due:
+                            break
+                        if due - now > 200:
+                            time.sleep((due - now - 100) * 1e-6)
+                    k = lo + j
+                    pool = pool_idx if kinds[k] == workloads.KIND_WAH else pool_u32
+                    handles[j] = srv.submit(int(kinds[k]), pool[starts[k]:starts[k] + sizes[k]], arrival_us=due)
+                    submitted.release()
+                consumer.join()
+                if failures:
+                    raise RuntimeError(f"served request failed: {failures[0]}")
+
+            # warm-up: the first requests of the same schedule fill the pinned
+            # and device caches; their statistics are dropped
+            run(0, warm)
+            srv.reset_stats()
             w0 = time.perf_counter()
-            for j in range(count):
-                due = t0 + t[j] * 1e6
-                while True:
-                    now = Server.clock_us()
-                    if now >= due:
-                        break
-                    if due - now > 200:
-                        time.sleep((due - now - 100) * 1e-6)
-                pool = pool_idx if kinds[j] == workloads.KIND_WAH else pool_u32
-                handles[j] = srv.submit(int(kinds[j]), pool[starts[j]:starts[j] + sizes[j]], arrival_us=due)
-                submitted.release()
-            consumer.join()
-            if failures:
-                raise RuntimeError(f"served request failed: {failures[0]}")
+            run(warm, warm + count)
             wall = time.perf_counter() - w0
             st = srv.stats()
             srv.close()
