@@ -255,6 +255,31 @@ __global__ __launch_bounds__(kPlanBlock) void k_radix_plan(const uint32_t* __res
 // ---------------------------------------------------------------------------------
 // scatter: one tile, ranked in LDS, written to its offsets
 // ---------------------------------------------------------------------------------
+// Bit B of d spread over the word: 0 or ~0 (one v_bfe_i32; the compiler
+// otherwise emits a shift pair).
+template <int B>
+__device__ __forceinline__ uint32_t spread_bit(uint32_t d) {
+  uint32_t s;
+  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(s) : "v"(d), "n"(B));
+  return s;
+}
+
+// Adds to (lo, hi) the lanes whose digit differs from this lane's in bit B or
+// B+1: for each bit, the ballot of the bit XOR this lane's bit spread over the
+// word.  One v_bitop3_b32 per bit and half computes lo | (m ^ s) (truth table
+// 0xF6 with operands in the order lo, m, s); together with the ballot's
+// compare and the extract that is 4 instructions per digit bit, which matters
+// because the scatter is bound by instruction issue, not by HBM.
+template <int B>
+__device__ __forceinline__ void differing_lanes(uint32_t d, uint32_t& lo, uint32_t& hi) {
+  const uint32_t s0 = spread_bit<B>(d), s1 = spread_bit<B + 1>(d);
+  const uint64_t m0 = __ballot(s0 != 0), m1 = __ballot(s1 != 0);
+  lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)m0, s0, 0xF6);
+  hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m0 >> 32), s0, 0xF6);
+  lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)m1, s1, 0xF6);
+  hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m1 >> 32), s1, 0xF6);
+}
+
 template <int kBlock, int kItems>
 struct ScatterLds {
   static constexpr int kWaves = kBlock / 64;
@@ -319,14 +344,15 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
     const bool valid = wbase + i * 64 + lane < tile_n;
     const uint32_t d = (key[i] >> shift) & (kRadix - 1);
     uint32_t r = 0;
-    // peers: the lanes whose digit equals this lane's, bit by bit from ballots
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int bb = 0; bb < kRadixBits; ++bb) {
-      const bool bit = (d >> bb) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
+    // peers: the valid lanes whose digit equals this lane's, i.e. that differ
+    // from it in no digit bit
+    uint32_t diff_lo = 0, diff_hi = 0;
+    static_assert(kRadixBits == 8, "four bit pairs");
+    differing_lanes<0>(d, diff_lo, diff_hi);
+    differing_lanes<2>(d, diff_lo, diff_hi);
+    differing_lanes<4>(d, diff_lo, diff_hi);
+    differing_lanes<6>(d, diff_lo, diff_hi);
+    const uint64_t peers = __ballot(valid) & ~(((uint64_t)diff_hi << 32) | diff_lo);
     if (valid) {
       const uint32_t below = (uint32_t)__popcll(peers & lt);
       const uint32_t old = L.wcnt[w][d];
