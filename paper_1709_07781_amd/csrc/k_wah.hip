@@ -278,38 +278,42 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
   __syncthreads();
   const uint32_t wpre = s_pre[0], dpre = s_pre[1];
 
-  // ---- this work-item's kEncItems consecutive elements, in registers ---------------
+  // ---- this work-item's kEncItems consecutive elements, in registers: key, the
+  // row's group (row / 31) and its bit inside the group; elements past the
+  // tile's end get bit 31, which no literal keeps --------------------------------
   const uint32_t e0 = tid * kEncItems;
-  uint32_t key[kEncItems], row[kEncItems];
+  const uint32_t nvalid = e0 < tile_n ? min(tile_n - e0, (uint32_t)kEncItems) : 0u;
+  const uint32_t valid = nvalid >= 32u ? ~0u : (1u << nvalid) - 1u;  // bit i: element i exists
+  uint32_t key[kEncItems], grp_of[kEncItems], bit_of[kEncItems];
 #pragma unroll
   for (int i = 0; i < kEncItems; ++i) {
     key[i] = s_k[pidx(e0 + i + 1)];
-    row[i] = s_r[pidx(e0 + i + 1)];
+    const uint32_t r = s_r[pidx(e0 + i + 1)];
+    grp_of[i] = r / kGroupRows;
+    bit_of[i] = (valid >> i) & 1u ? r - grp_of[i] * kGroupRows : 31u;
   }
   const uint32_t kprev = s_k[pidx(e0)];
   const uint32_t cprev = s_r[pidx(e0)] / kGroupRows;
 
   // ---- group and value heads, words and values emitted ------------------------------
   uint32_t heads = 0, segs = 0, gaps = 0;  // bit i: element i starts a group / a value / has a fill
-  uint32_t nw = 0, ns = 0;
 #pragma unroll
   for (int i = 0; i < kEncItems; ++i) {
-    if (e0 + i < tile_n) {
-      const uint32_t c = row[i] / kGroupRows;
-      const uint32_t kp = i ? key[i - 1] : kprev;
-      const uint32_t cp = i ? row[i - 1] / kGroupRows : cprev;
-      const bool seg = (base + e0 + i) == 0 || key[i] != kp;
-      const bool grp = seg || c != cp;
-      if (grp) {
-        const bool gap = seg ? c != 0u : c != cp + 1u;
-        heads |= 1u << i;
-        segs |= (seg ? 1u : 0u) << i;
-        gaps |= (gap ? 1u : 0u) << i;
-        nw += gap ? 2u : 1u;
-        ns += seg ? 1u : 0u;
-      }
-    }
+    const uint32_t c = grp_of[i];
+    const uint32_t kp = i ? key[i - 1] : kprev;
+    const uint32_t cp = i ? grp_of[i - 1] : cprev;
+    const bool seg = key[i] != kp || (base + e0 + i) == 0;
+    const bool grp = seg || c != cp;
+    const bool gap = grp && (seg ? c != 0u : c != cp + 1u);
+    heads |= (uint32_t)grp << i;
+    segs |= (uint32_t)seg << i;
+    gaps |= (uint32_t)gap << i;
   }
+  heads &= valid;
+  segs &= valid;
+  gaps &= valid;
+  const uint32_t nw = (uint32_t)__popc(heads) + (uint32_t)__popc(gaps);
+  const uint32_t ns = (uint32_t)__popc(segs);
   // Both counts in one scan: words in the low half, values in the high half
   // (a tile emits at most 2*kEncTile words and kEncTile values).
   uint32_t packed_total;
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
   // further elements, into the look-ahead): collect its bits now -------------------
   uint32_t tail = 0;
   if (e0 + kEncItems <= tile_n) {
-    const uint32_t kl = key[kEncItems - 1], cl = row[kEncItems - 1] / kGroupRows;
+    const uint32_t kl = key[kEncItems - 1], cl = grp_of[kEncItems - 1];
     for (uint32_t j = e0 + kEncItems; j < avail; ++j) {
       const uint32_t kj = s_k[pidx(j + 1)];
       const uint32_t rj = s_r[pidx(j + 1)];
@@ -339,22 +343,19 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
     uint32_t acc = tail;
 #pragma unroll
     for (int i = kEncItems - 1; i >= 0; --i) {
-      if (e0 + i < tile_n) {
-        const uint32_t c = row[i] / kGroupRows;
-        acc |= 1u << (row[i] - c * kGroupRows);
-        if ((heads >> i) & 1u) {
-          s_words[--w] = acc;
-          acc = 0;
-          const bool seg = (segs >> i) & 1u;
-          if ((gaps >> i) & 1u) {
-            const uint32_t cp = i ? row[i - 1] / kGroupRows : cprev;
-            s_words[--w] = kFill | (seg ? c : c - cp - 1u);
-          }
-          if (seg) {
-            const uint32_t d = dpre + ls + (uint32_t)__popc(segs & ((1u << i) - 1u));
-            out_keys[d] = key[i];
-            out_offsets[d] = wpre + w;
-          }
+      acc |= 1u << bit_of[i];
+      if ((heads >> i) & 1u) {
+        s_words[--w] = acc & ~kFill;  // drops the bit 31 of elements past the tile's end
+        acc = 0;
+        const bool seg = (segs >> i) & 1u;
+        if ((gaps >> i) & 1u) {
+          const uint32_t cp = i ? grp_of[i - 1] : cprev;
+          s_words[--w] = kFill | (seg ? grp_of[i] : grp_of[i] - cp - 1u);
+        }
+        if (seg) {
+          const uint32_t d = dpre + ls + (uint32_t)__popc(segs & ((1u << i) - 1u));
+          out_keys[d] = key[i];
+          out_offsets[d] = wpre + w;
         }
       }
     }
