@@ -41,14 +41,19 @@ constexpr int kEncItems = KA_ENC_ITEMS;
 constexpr int kEncTile = kEncBlock * kEncItems;  // 4096 pairs
 constexpr int kVecs = kEncTile / 4 / kEncBlock;  // 16-byte loads per work-item and array
 constexpr int kLook = 32;                        // >= 30 elements of look-ahead
-constexpr int kStage = kEncTile + 1 + kLook;     // one element of look-behind
+constexpr int kStage = kEncTile + kLook;         // staged elements (the look-behind is kept apart)
 constexpr uint32_t kGroupRows = 31;
 constexpr uint32_t kFill = 0x80000000u;
 
-// Padded LDS index: one spare word every 16 so that a work-item reading its
-// kEncItems consecutive elements does not collide on banks with its neighbours.
-__device__ __forceinline__ uint32_t pidx(uint32_t i) { return i + (i >> 4); }
-constexpr int kStagePadded = kStage + kStage / 16 + 1;
+// Padded LDS index: four spare words after every 64 elements.  Groups of 4
+// elements stay 16-byte aligned, so the tile is staged with conflict-free
+// 16-byte writes (work-item t writes elements 4t..4t+3); a work-item reads its
+// 16 consecutive elements with 16-byte reads, and the 16 work-items served
+// together (starting 64 bytes apart, plus 16 after every fourth) cover all 64
+// banks once.
+__device__ __forceinline__ uint32_t pidx(uint32_t i) { return i + 4 * (i >> 6); }
+constexpr int kStagePadded = kStage + 4 * (kStage / 64) + 4;
+static_assert(kEncItems == 16, "one padded run of 16 elements per work-item");
 static_assert(2 * kEncTile <= 2 * kStagePadded, "word staging fits over the input staging");
 
 // Words and values emitted by an element with key k and row r whose
@@ -206,7 +211,7 @@ __global__ void k_wah_empty(uint32_t* __restrict__ out_offsets, uint64_t* __rest
 // write: literals, fills and lookup-table entries of one tile
 // ---------------------------------------------------------------------------------
 template <bool kVec>
-__global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restrict__ skeys,
+__global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const uint32_t* __restrict__ skeys,
                                                          const uint32_t* __restrict__ srows, uint32_t n,
                                                          const uint32_t* __restrict__ tile_words,
                                                          const uint32_t* __restrict__ tile_values,
@@ -221,6 +226,7 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
   __shared__ __align__(16) uint32_t s_mem[2 * kStagePadded];
   __shared__ uint32_t s_scan[kEncBlock / 64];
   __shared__ uint32_t s_pre[2];
+  __shared__ uint32_t s_behind[2];  // key and row of element base - 1
   uint32_t* s_k = s_mem;
   uint32_t* s_r = s_mem + kStagePadded;
   uint32_t* s_words = s_mem;  // after the literals are built
@@ -230,17 +236,16 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
   const uint32_t tile_n = min((uint32_t)kEncTile, n - base);
   const uint32_t avail = min((uint32_t)(kEncTile + kLook), n - base);  // readable from base on
 
-  // ---- stage elements base-1 .. base+kEncTile+kLook-1 into slots 0.. --------------
-  // Work-items 64..96 also load the look-behind element (slot 0) and the
-  // look-ahead (slots kEncTile+1 ..).
+  // ---- stage elements base .. base+kEncTile+kLook-1 into slots 0.. ---------------
+  // Work-items 64..95 also load the look-ahead (slots kEncTile ..) and
+  // work-item 96 the look-behind element base - 1.
   {
     uint32_t vk[kVecs][4], vr[kVecs][4];
     load_pairs<kVec>(skeys, srows, base, tile_n, tid, vk, vr);
-    const bool extra = tid >= 64 && tid < 64 + 1 + kLook;
-    const uint32_t xslot = tid == 64 ? 0u : (uint32_t)(kEncTile + (tid - 64));
+    const bool extra = tid >= 64 && tid < 64 + kLook + 1;
+    const int64_t g = tid == 64 + kLook ? (int64_t)base - 1 : (int64_t)base + kEncTile + (tid - 64);
     uint32_t xk = 0, xr = 0;
     if (extra) {
-      const int64_t g = (int64_t)base - 1 + xslot;
       const bool ok = g >= 0 && g < (int64_t)n;
       xk = ok ? skeys[g] : 0u;
       xr = ok ? br.local(xk, srows[g]) : 0u;
@@ -263,16 +268,24 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
       }
     }
 #pragma unroll
-    for (int j = 0; j < kVecs; ++j)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const uint32_t sl = 1 + 4 * (j * kEncBlock + tid) + c;
-        s_k[pidx(sl)] = vk[j][c];
-        s_r[pidx(sl)] = br.local(vk[j][c], vr[j][c]);
-      }
+    for (int j = 0; j < kVecs; ++j) {
+      const uint32_t sl = pidx(4 * (j * kEncBlock + tid));
+      u32x4 k4, r4;
+      k4.x = vk[j][0], k4.y = vk[j][1], k4.z = vk[j][2], k4.w = vk[j][3];
+      r4.x = br.local(vk[j][0], vr[j][0]), r4.y = br.local(vk[j][1], vr[j][1]);
+      r4.z = br.local(vk[j][2], vr[j][2]), r4.w = br.local(vk[j][3], vr[j][3]);
+      *reinterpret_cast<u32x4*>(s_k + sl) = k4;
+      *reinterpret_cast<u32x4*>(s_r + sl) = r4;
+    }
     if (extra) {
-      s_k[pidx(xslot)] = xk;
-      s_r[pidx(xslot)] = xr;
+      if (tid == 64 + kLook) {
+        s_behind[0] = xk;
+        s_behind[1] = xr;
+      } else {
+        const uint32_t sl = pidx((uint32_t)(kEncTile + (tid - 64)));
+        s_k[sl] = xk;
+        s_r[sl] = xr;
+      }
     }
   }
   __syncthreads();
@@ -286,14 +299,20 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
   const uint32_t valid = nvalid >= 32u ? ~0u : (1u << nvalid) - 1u;  // bit i: element i exists
   uint32_t key[kEncItems], grp_of[kEncItems], bit_of[kEncItems];
 #pragma unroll
-  for (int i = 0; i < kEncItems; ++i) {
-    key[i] = s_k[pidx(e0 + i + 1)];
-    const uint32_t r = s_r[pidx(e0 + i + 1)];
-    grp_of[i] = r / kGroupRows;
-    bit_of[i] = (valid >> i) & 1u ? r - grp_of[i] * kGroupRows : 31u;
+  for (int q = 0; q < kEncItems / 4; ++q) {
+    const u32x4 k4 = *reinterpret_cast<const u32x4*>(s_k + pidx(e0) + 4 * q);
+    const u32x4 r4 = *reinterpret_cast<const u32x4*>(s_r + pidx(e0) + 4 * q);
+    const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w}, rr[4] = {r4.x, r4.y, r4.z, r4.w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = 4 * q + c;
+      key[i] = kk[c];
+      grp_of[i] = rr[c] / kGroupRows;
+      bit_of[i] = (valid >> i) & 1u ? rr[c] - grp_of[i] * kGroupRows : 31u;
+    }
   }
-  const uint32_t kprev = s_k[pidx(e0)];
-  const uint32_t cprev = s_r[pidx(e0)] / kGroupRows;
+  const uint32_t kprev = tid ? s_k[pidx(e0 - 1)] : s_behind[0];
+  const uint32_t cprev = (tid ? s_r[pidx(e0 - 1)] : s_behind[1]) / kGroupRows;
 
   // ---- group and value heads, words and values emitted ------------------------------
   uint32_t heads = 0, segs = 0, gaps = 0;  // bit i: element i starts a group / a value / has a fill
@@ -326,8 +345,8 @@ __global__ __launch_bounds__(kEncBlock) void k_wah_write(const uint32_t* __restr
   if (e0 + kEncItems <= tile_n) {
     const uint32_t kl = key[kEncItems - 1], cl = grp_of[kEncItems - 1];
     for (uint32_t j = e0 + kEncItems; j < avail; ++j) {
-      const uint32_t kj = s_k[pidx(j + 1)];
-      const uint32_t rj = s_r[pidx(j + 1)];
+      const uint32_t kj = s_k[pidx(j)];
+      const uint32_t rj = s_r[pidx(j)];
       const uint32_t cj = rj / kGroupRows;
       if (kj != kl || cj != cl) break;
       tail |= 1u << (rj - cj * kGroupRows);
