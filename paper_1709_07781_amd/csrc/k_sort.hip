@@ -98,15 +98,26 @@ __device__ __forceinline__ PassIo pass_io(const PassBuffers& buf, uint32_t activ
 }
 
 // LDS add of 1 to bin d by every active lane, aggregated over lanes that share
-// the first active lane's bin (the common case for skewed or high digits).
+// a bin: in each of kRounds rounds the first remaining lane's bin takes the
+// count of all remaining lanes with that bin in one add; the lanes left after
+// the rounds add 1 each.  One round suits keys in input order; after an LSD
+// pass a tile's keys are grouped by their lower digits, equal keys sit
+// together and the next digit is concentrated in few values, where a second
+// round removes most same-address adds (measured on Zipf keys: pass 1 -12 us,
+// while a second round in pass 0 costs +9 us).
+template <int kRounds>
 __device__ __forceinline__ void lds_add_aggregated(uint32_t* bins, uint32_t d, bool valid) {
-  const uint64_t active = __ballot(valid);
-  if (!active) return;
-  const uint32_t first_lane = (uint32_t)__builtin_ctzll(active);
-  const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, (int)first_lane);
-  const uint64_t same = __ballot(valid && d == d0);
-  if (lane_id() == first_lane) atomicAdd(&bins[d0], (uint32_t)__popcll(same));
-  if (valid && d != d0) atomicAdd(&bins[d], 1u);
+  uint64_t rest = __ballot(valid);
+#pragma unroll
+  for (int round = 0; round < kRounds; ++round) {
+    if (!rest) return;
+    const uint32_t first_lane = (uint32_t)__builtin_ctzll(rest);
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, (int)first_lane);
+    const uint64_t same = __ballot(d == d0) & rest;
+    if (lane_id() == first_lane) atomicAdd(&bins[d0], (uint32_t)__popcll(same));
+    rest &= ~same;
+  }
+  if ((rest >> lane_id()) & 1ull) atomicAdd(&bins[d], 1u);
 }
 
 // Tile of work-group b under an XCD-aware order.  Work-groups are dispatched
@@ -180,7 +191,7 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const bool valid = 4 * (j * kUpBlock + tid) + c < len;
-      lds_add_aggregated(s_hist[w], (k[j][c] >> shift) & (kRadix - 1), valid);
+      lds_add_aggregated<kFirst ? 1 : 2>(s_hist[w], (k[j][c] >> shift) & (kRadix - 1), valid);
       if (kFirst && valid) {
         kor |= k[j][c];
         kand &= k[j][c];
