@@ -295,8 +295,7 @@ template <int kBlock, int kItems>
 struct ScatterLds {
   static constexpr int kWaves = kBlock / 64;
   static constexpr int kTile = kBlock * kItems;
-  __align__(16) uint32_t keys[kTile];  // reorder buffers
-  uint32_t rows[kTile];
+  uint2 kr[kTile];  // reorder buffer: key and row of each element
   uint16_t wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave offsets
   uint32_t loff[kRadix];          // tile-local start of each digit
   uint32_t dbase[kRadix];         // global start minus tile-local start
@@ -398,8 +397,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
     if (wbase + i * 64 + lane < tile_n) {
       const uint32_t d = (key[i] >> shift) & (kRadix - 1);
       const uint32_t pos = L.loff[d] + L.wcnt[w][d] + rank[i];
-      L.keys[pos] = key[i];
-      L.rows[pos] = row[i];
+      L.kr[pos] = make_uint2(key[i], row[i]);
     }
   }
   __syncthreads();
@@ -409,10 +407,11 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
   for (int i = 0; i < kItems; ++i) {
     const uint32_t p = i * kBlock + tid;
     if (p < tile_n) {
-      const uint32_t k = L.keys[p];
+      const uint2 v = L.kr[p];
+      const uint32_t k = v.x;
       const uint32_t g = L.dbase[(k >> shift) & (kRadix - 1)] + p;
       io.dst_keys[g] = k;
-      io.dst_rows[g] = L.rows[p];
+      io.dst_rows[g] = v.y;
     }
   }
   __syncthreads();  // the LDS buffers are free again
