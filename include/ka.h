@@ -398,7 +398,12 @@ typedef struct ka_server_stats {
  * wait for the next slot), and a completion thread.  Index requests of a batch
  * run as one batched index build, scans as one scan rebased per request,
  * chains as one chain over their concatenation; batches on different streams
- * overlap.  Each result is the one the request gets alone. */
+ * overlap.  Each result is the one the request gets alone.  Creation warms the
+ * system's device pool and pinned staging for batches up to max_batch_bytes
+ * (per stream slot, two blocks of each power of two from 1 MiB up to a full
+ * batch's need; about 1 GiB of device memory per stream slot and 256 MiB of
+ * pinned memory at the default 16 MiB), which stay cached in the system
+ * after the server ends. */
 KA_API int ka_server_create(ka_system* sys, const ka_server_config* cfg, ka_server** out);
 /* Queues a request (the data are copied before return).  arrival_us is its
  * arrival time on the ka_server_clock_us clock (0 = now); latency is measured

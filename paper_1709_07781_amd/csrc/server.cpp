@@ -443,6 +443,31 @@ KA_API int ka_server_create(ka_system* sys, const ka_server_config* cfg, ka_serv
     s->chain_a.push_back(cfg->chain_a[i]);
     s->chain_b.push_back(cfg->chain_b[i]);
   }
+  // Warm the caches the batches draw from: per stream slot two device blocks,
+  // and two pinned buffers, of every power of two from 1 MiB up to what a
+  // full batch needs, taken and given back at once.  A cached block of up to
+  // twice a size class is reused, so the first batches of every size find
+  // memory cached instead of calling hipMalloc / hipHostMalloc, which take
+  // milliseconds and stall the mailbox or submitting thread meanwhile.  (A
+  // block the pool's budget refuses is skipped.)
+  {
+    const uint64_t dev_top = request_bytes(KA_REQ_WAH, s->max_batch_bytes / 4);
+    const uint64_t pin_top = 4 * s->max_batch_bytes;  // a full batch's outputs
+    for (uint32_t si = 0; si < s->streams; ++si)
+      for (uint64_t b = 1ull << 20; b < 2 * dev_top; b <<= 1) {
+        void* p[2] = {nullptr, nullptr};
+        uint64_t got[2] = {0, 0};
+        for (int k = 0; k < 2; ++k)
+          if (sys->pool.alloc(b, si, &p[k], &got[k]) != KA_OK) p[k] = nullptr;
+        for (int k = 0; k < 2; ++k)
+          if (p[k]) sys->pool.release(p[k], got[k], si, 1ull << si);
+      }
+    for (uint64_t b = 1ull << 20; b < 2 * pin_top; b <<= 1) {
+      void* p[2] = {sys->stage.get(sys, b), sys->stage.get(sys, b)};
+      for (int k = 0; k < 2; ++k)
+        if (p[k]) sys->stage.give_back(p[k]);
+    }
+  }
   sys->retain();
   s->loop = std::thread([s] { s->run_loop(); });
   s->completion = std::thread([s] { s->run_completion(); });
