@@ -9,6 +9,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -303,12 +304,19 @@ def bench_served(args) -> int:
                     raise RuntimeError(f"served request failed: {failures[0]}")
 
             # warm-up: the first requests of the same schedule fill the pinned
-            # and device caches; their statistics are dropped
+            # and device caches; their statistics are dropped.  The client's
+            # garbage collector is off while requests are submitted (its
+            # pauses would be charged to the server as late arrivals).
             run(0, warm)
             srv.reset_stats()
-            w0 = time.perf_counter()
-            run(warm, warm + count)
-            wall = time.perf_counter() - w0
+            gc.collect()
+            gc.disable()
+            try:
+                w0 = time.perf_counter()
+                run(warm, warm + count)
+                wall = time.perf_counter() - w0
+            finally:
+                gc.enable()
             st = srv.stats()
             srv.close()
             span_s = max(wall - 0.02, 1e-9)
