@@ -240,7 +240,7 @@ def bench_served(args) -> int:
     time (sizes log-uniform in [2^8, 2^22], 40% index of values below 2^12,
     30% scan, 30% 8-stage affine chain); latency runs from the scheduled
     arrival to completion seen on the host.  The batched server (continuous
-    batching, 3 streams, 64 GiB budget) against the plain server (one request
+    batching, 2 streams, 64 GiB budget) against the plain server (one request
     at a time, same kernels)."""
     import torch
     from paper_1709_07781_amd.session import Server, Session
@@ -473,7 +473,7 @@ def main() -> int:
     ap.add_argument("--served-seconds", type=float, default=2.0,
                     help="served: seconds of arrivals per rate (at most --served-max requests)")
     ap.add_argument("--served-max", type=int, default=4000)
-    ap.add_argument("--served-streams", type=int, default=3, help="served: streams of the batched server")
+    ap.add_argument("--served-streams", type=int, default=2, help="served: streams of the batched server")
     ap.add_argument("--served-batch-mb", type=int, default=16, help="served: MiB of input per batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run the in-place affine kernel over 2^n words 3 times "
