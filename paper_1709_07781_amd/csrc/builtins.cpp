@@ -93,8 +93,8 @@ int run_wah(LaunchCtx& c) {
                            const_cast<uint64_t*>(a[3].d_len), const_cast<uint64_t*>(a[4].d_len));
 }
 
-// wah_index_batch: (in values; in req_off; priv value_bits; out keys; out offsets;
-//                   out words; out key_start; out word_start)
+// wah_index_batch: (in values; in req_off; priv value_bits [, largest request + 1];
+//                   out keys; out offsets; out words; out key_start; out word_start)
 int run_batch(LaunchCtx& c) {
   auto& a = *c.args;
   if (a[1].d_len) return c.env->fail(KA_E_ARG, "wah_index_batch: the request table's length must be known on the host");
@@ -111,7 +111,8 @@ int run_batch(LaunchCtx& c) {
                           static_cast<uint32_t*>(a[6].ptr), static_cast<uint32_t*>(a[7].ptr),
                           const_cast<uint64_t*>(a[3].d_len), const_cast<uint64_t*>(a[4].d_len),
                           const_cast<uint64_t*>(a[5].d_len), const_cast<uint64_t*>(a[6].d_len),
-                          const_cast<uint64_t*>(a[7].d_len));
+                          const_cast<uint64_t*>(a[7].d_len), 0,
+                          a[2].priv[1] ? (uint32_t)(a[2].priv[1] - 1) : kMaxReqUnknown);
 }
 
 std::vector<BuiltinKernel> make_registry() {

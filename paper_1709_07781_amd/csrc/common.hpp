@@ -70,11 +70,15 @@ int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, ui
                       uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
                       uint64_t* d_len_words, const uint32_t* req_base = nullptr, uint32_t req_shift = 32);
 // Batched index build: nreq requests, values concatenated, req_off[j] the
-// first position of request j (req_off[nreq] = n).
+// first position of request j (req_off[nreq] = n).  max_req: the largest
+// request, when the caller knows it (kMaxReqUnknown otherwise); batches of
+// small requests take a one-work-group-per-request path.
+constexpr uint32_t kMaxReqUnknown = 0xFFFFFFFFu;
 int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
                      uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
                      uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
-                     uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape = 0);
+                     uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape = 0,
+                     uint32_t max_req = kMaxReqUnknown);
 // Exclusive scan of each of nreq requests concatenated in in[0..n) (req_off as
 // for the batched index).
 int launch_segmented_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* req_off,

@@ -185,12 +185,195 @@ __global__ __launch_bounds__(kSplitBlock) void k_batch_tables(
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Small requests: one work-group builds one request's whole index
+// ---------------------------------------------------------------------------------
+// When every request holds at most kSmallMax values and values fit in
+// 32 - kSmallRowBits bits, each request is sorted and encoded by one
+// work-group in LDS, so the batch takes three launches instead of the tagged
+// sort's and encoder's fifteen or so:
+//   k_small_index  sorts value << kSmallRowBits | row (a bitonic sort; the row
+//                  bits make equal values keep their order), marks value,
+//                  group and fill heads as the encoder does, and writes the
+//                  request's words, keys and offsets into slots bounded by its
+//                  size (words at 2 * req_off[j], keys at req_off[j], offsets
+//                  at req_off[j] + j), with its word and value counts and
+//                  whether a value was out of range;
+//   k_small_starts scans the counts into key_start and word_start and sets the
+//                  output lengths (all 0 if a value was out of range);
+//   k_small_place  copies each request's slots to their places.
+constexpr int kSmallMax = 1024;
+constexpr uint32_t kSmallRowBits = 10;
+constexpr int kSmallBlock = 256;
+constexpr int kSmallPer = kSmallMax / kSmallBlock;  // consecutive sorted elements per work-item
+constexpr uint32_t kSmallRows = 31, kSmallFill = 0x80000000u;
+static_assert((1 << kSmallRowBits) == kSmallMax, "row bits cover a request");
+
+__global__ __launch_bounds__(kSmallBlock) void k_small_index(const uint32_t* __restrict__ values,
+                                                             const uint32_t* __restrict__ req_off,
+                                                             uint32_t value_bits, uint32_t* __restrict__ wslot,
+                                                             uint32_t* __restrict__ kslot,
+                                                             uint32_t* __restrict__ oslot,
+                                                             uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s[kSmallMax];
+  __shared__ uint32_t s_scan[kSmallBlock / 64];
+  const uint32_t j = blockIdx.x, tid = threadIdx.x;
+  const uint32_t b = req_off[j];
+  const uint32_t n = min(req_off[j + 1] - b, (uint32_t)kSmallMax);  // the host checked n <= kSmallMax
+  uint32_t over = 0;
+#pragma unroll
+  for (int q = 0; q < kSmallPer; ++q) {
+    const uint32_t i = q * kSmallBlock + tid;
+    uint32_t c = 0xFFFFFFFFu;  // padding sorts last
+    if (i < n) {
+      const uint32_t v = values[b + i];
+      over |= v >> value_bits;  // value_bits <= 32 - kSmallRowBits here
+      c = (v << kSmallRowBits) | i;
+    }
+    s[i] = c;
+  }
+  const bool bad = __syncthreads_or(over != 0u);
+  // bitonic sort of the first m = 2^ceil(log2 n) entries, ascending
+  uint32_t m = 1;
+  while (m < n) m <<= 1;
+  for (uint32_t k = 2; k <= m; k <<= 1) {
+    for (uint32_t h = k >> 1; h > 0; h >>= 1) {
+      for (uint32_t i = tid; i < m; i += kSmallBlock) {
+        const uint32_t l = i ^ h;
+        if (l > i) {
+          const uint32_t x = s[i], y = s[l];
+          if ((x > y) == ((i & k) == 0u)) {
+            s[i] = y;
+            s[l] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // heads of values, groups and fills, as in the encoder (Sec. 4.1 parts 3-5)
+  const uint32_t e0 = tid * kSmallPer;
+  uint32_t heads = 0, segs = 0, gaps = 0;
+#pragma unroll
+  for (int q = 0; q < kSmallPer; ++q) {
+    const uint32_t i = e0 + q;
+    if (i < n) {
+      const uint32_t c = s[i], v = c >> kSmallRowBits, ch = (c & (kSmallMax - 1)) / kSmallRows;
+      bool seg = true, grp = true, gap = ch != 0u;
+      if (i > 0) {
+        const uint32_t p = s[i - 1], pv = p >> kSmallRowBits, pch = (p & (kSmallMax - 1)) / kSmallRows;
+        seg = v != pv;
+        grp = seg || ch != pch;
+        gap = grp && (seg ? ch != 0u : ch != pch + 1u);
+      }
+      heads |= (uint32_t)grp << q;
+      segs |= (uint32_t)seg << q;
+      gaps |= (uint32_t)gap << q;
+    }
+  }
+  const uint32_t nw = (uint32_t)__popc(heads) + (uint32_t)__popc(gaps), ns = (uint32_t)__popc(segs);
+  uint32_t total;
+  const uint32_t pre = block_excl_scan<kSmallBlock>((ns << 16) | nw, s_scan, &total);
+  const uint32_t W = total & 0xFFFFu, D = total >> 16;
+  uint32_t w = pre & 0xFFFFu, d = pre >> 16;
+  uint32_t* ws = wslot + 2ull * b;
+  uint32_t* ks = kslot + b;
+  uint32_t* os = oslot + b + j;
+#pragma unroll
+  for (int q = 0; q < kSmallPer; ++q) {
+    if (!((heads >> q) & 1u)) continue;
+    const uint32_t i = e0 + q;
+    const uint32_t c = s[i], v = c >> kSmallRowBits, ch = (c & (kSmallMax - 1)) / kSmallRows;
+    const bool seg = (segs >> q) & 1u;
+    if (seg) {
+      ks[d] = v;
+      os[d] = w;
+      ++d;
+    }
+    if ((gaps >> q) & 1u) {
+      const uint32_t pch = seg ? 0u : (s[i - 1] & (kSmallMax - 1)) / kSmallRows;
+      ws[w++] = kSmallFill | (seg ? ch : ch - pch - 1u);
+    }
+    // the literal: the bits of the group's rows (at most 31 elements)
+    uint32_t lit = 0;
+    for (uint32_t t = i; t < n; ++t) {
+      const uint32_t ct = s[t];
+      const uint32_t rt = ct & (kSmallMax - 1);
+      if ((ct >> kSmallRowBits) != v || rt / kSmallRows != ch) break;
+      lit |= 1u << (rt - ch * kSmallRows);
+    }
+    ws[w++] = lit;
+  }
+  if (tid == 0) {
+    os[D] = W;
+    counts[3 * j] = W;
+    counts[3 * j + 1] = D;
+    counts[3 * j + 2] = bad ? 1u : 0u;
+  }
+}
+
+constexpr int kStartsBlock = 1024;
+__global__ __launch_bounds__(kStartsBlock) void k_small_starts(const uint32_t* __restrict__ counts, uint32_t nreq,
+                                                               uint32_t* __restrict__ key_start,
+                                                               uint32_t* __restrict__ word_start,
+                                                               uint64_t* __restrict__ len_keys,
+                                                               uint64_t* __restrict__ len_offsets,
+                                                               uint64_t* __restrict__ len_words,
+                                                               uint64_t* __restrict__ len_key_start,
+                                                               uint64_t* __restrict__ len_word_start) {
+  __shared__ uint32_t s_a[kStartsBlock / 64], s_b[kStartsBlock / 64];
+  uint32_t wbase = 0, dbase = 0, any_bad = 0;
+  for (uint32_t c0 = 0; c0 < nreq; c0 += kStartsBlock) {
+    const uint32_t j = c0 + threadIdx.x;
+    const bool ok = j < nreq;
+    const uint32_t wj = ok ? counts[3 * j] : 0u, dj = ok ? counts[3 * j + 1] : 0u;
+    any_bad |= ok ? counts[3 * j + 2] : 0u;
+    uint32_t wt, dt;
+    const uint32_t wp = block_excl_scan<kStartsBlock>(wj, s_a, &wt);
+    const uint32_t dp = block_excl_scan<kStartsBlock>(dj, s_b, &dt);
+    if (ok) {
+      word_start[j] = wbase + wp;
+      key_start[j] = dbase + dp;
+    }
+    wbase += wt;
+    dbase += dt;
+    __syncthreads();  // s_a, s_b are reused by the next chunk
+  }
+  const bool bad = __syncthreads_or(any_bad != 0u);
+  if (threadIdx.x == 0) {
+    word_start[nreq] = wbase;
+    key_start[nreq] = dbase;
+    *len_keys = bad ? 0u : dbase;
+    *len_offsets = bad ? 0u : (uint64_t)dbase + nreq;
+    *len_words = bad ? 0u : wbase;
+    *len_key_start = bad ? 0u : (uint64_t)nreq + 1;
+    *len_word_start = bad ? 0u : (uint64_t)nreq + 1;
+  }
+}
+
+__global__ __launch_bounds__(kSmallBlock) void k_small_place(const uint32_t* __restrict__ counts,
+                                                             const uint32_t* __restrict__ req_off,
+                                                             const uint32_t* __restrict__ wslot,
+                                                             const uint32_t* __restrict__ kslot,
+                                                             const uint32_t* __restrict__ oslot,
+                                                             const uint32_t* __restrict__ key_start,
+                                                             const uint32_t* __restrict__ word_start,
+                                                             uint32_t* __restrict__ keys, uint32_t* __restrict__ offsets,
+                                                             uint32_t* __restrict__ words) {
+  const uint32_t j = blockIdx.x, tid = threadIdx.x;
+  const uint32_t b = req_off[j], W = counts[3 * j], D = counts[3 * j + 1];
+  const uint32_t wd = word_start[j], kd = key_start[j];
+  for (uint32_t i = tid; i < W; i += kSmallBlock) words[wd + i] = wslot[2ull * b + i];
+  for (uint32_t i = tid; i < D; i += kSmallBlock) keys[kd + i] = kslot[b + i];
+  for (uint32_t i = tid; i <= D; i += kSmallBlock) offsets[kd + j + i] = oslot[b + j + i];
+}
+
 }  // namespace
 
 int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
                      uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
                      uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
-                     uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape) {
+                     uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape, uint32_t max_req) {
   if (!req_off || !offsets || !key_start || !word_start || !len_keys || !len_offsets || !len_words || !len_key_start ||
       !len_word_start)
     return env.fail(kErrArg, "wah_index_batch: null buffer");
@@ -202,6 +385,30 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
   if (n >= (1ull << 30)) return env.fail(kErrArg, "wah_index_batch: n must be below 2^30");
   if (n && (!values || !keys || !words)) return env.fail(kErrArg, "wah_index_batch: null buffer");
   const uint32_t nn = (uint32_t)n;
+
+  if (max_req <= (uint32_t)kSmallMax && value_bits <= 32 - kSmallRowBits) {
+    // every request is small: one work-group per request
+    uint32_t* wslot = static_cast<uint32_t*>(env.scratch(8 * (n ? n : 1)));
+    uint32_t* kslot = static_cast<uint32_t*>(env.scratch(4 * (n ? n : 1)));
+    uint32_t* oslot = static_cast<uint32_t*>(env.scratch(4 * (n + nreq)));
+    uint32_t* counts = static_cast<uint32_t*>(env.scratch(12ull * nreq));
+    if (!wslot || !kslot || !oslot || !counts) return env.fail(kErrOom, "wah_index_batch: scratch");
+    env.prof_begin("batch_small_index");
+    k_small_index<<<dim3(nreq), dim3(kSmallBlock), 0, env.stream()>>>(values, req_off, value_bits, wslot, kslot,
+                                                                       oslot, counts);
+    env.prof_end("batch_small_index");
+    int rc = check_launch(env, "batch_small_index launch");
+    if (rc) return rc;
+    env.prof_begin("batch_small_place");
+    k_small_starts<<<dim3(1), dim3(kStartsBlock), 0, env.stream()>>>(counts, nreq, key_start, word_start, len_keys,
+                                                                      len_offsets, len_words, len_key_start,
+                                                                      len_word_start);
+    if ((rc = check_launch(env, "batch_small_starts launch"))) return rc;
+    k_small_place<<<dim3(nreq), dim3(kSmallBlock), 0, env.stream()>>>(counts, req_off, wslot, kslot, oslot,
+                                                                       key_start, word_start, keys, offsets, words);
+    env.prof_end("batch_small_place");
+    return check_launch(env, "batch_small_place launch");
+  }
 
   uint32_t* bad = static_cast<uint32_t*>(env.scratch(4));
   uint32_t* tkeys = static_cast<uint32_t*>(env.scratch(4 * (n ? n : 1)));

@@ -108,8 +108,11 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
   if (nreq == 0) return set_error(KA_E_ARG, "no requests");
   const uint64_t n = req_off[nreq];
   if (req_off[0] != 0) return set_error(KA_E_ARG, "req_off must start at 0");
-  for (uint32_t j = 0; j < nreq; ++j)
+  uint32_t biggest = 0;  // the largest request (selects the small-request path)
+  for (uint32_t j = 0; j < nreq; ++j) {
     if (req_off[j + 1] < req_off[j]) return set_error(KA_E_ARG, "req_off must be non-decreasing");
+    biggest = std::max(biggest, req_off[j + 1] - req_off[j]);
+  }
   if (n >= (1ull << 30)) return set_error(KA_E_ARG, "n must be below 2^30");
   if (value_bits == 0 || value_bits > 32) return set_error(KA_E_ARG, "value_bits must be 1..32");
   const uint32_t req_bits = nreq > 1 ? 32u - (uint32_t)__builtin_clz(nreq - 1) : 0u;
@@ -128,7 +131,7 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
   const uint64_t n1 = n ? n : 1;
   const uint64_t sort_tiles = (n + 8191) / 8192, enc_tiles = (n + 4095) / 4096;
   const uint64_t scan_tiles = 2 * ((256 * sort_tiles + 4095) / 4096) + 2;  // scan tiles hold >= 4096 entries
-  const uint64_t arena_bytes = 24 * n1 + 2 * sort_tiles * 2064 + 8 * enc_tiles + (64ull << 10);
+  const uint64_t arena_bytes = 24 * n1 + 16ull * nreq + 2 * sort_tiles * 2064 + 8 * enc_tiles + (64ull << 10);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     const uint64_t o = off;
@@ -191,7 +194,7 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
     }
     rc = launch_wah_batch(e, p->input, n, p->req_off, nreq, value_bits, p->keys, p->offsets, p->words,
                           p->key_start, p->word_start, p->lens, p->lens + 1, p->lens + 2, p->lens + 3, p->lens + 4,
-                          shape);
+                          shape, biggest);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(p->s, &g);
     p->graph[v] = g;

@@ -1520,7 +1520,12 @@ KA_API int ka_wah_batch(ka_system* sys, const uint32_t* values, uint64_t n, cons
   ka_arg sig[8] = {};
   sig[0] = {KA_IN, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
   sig[1] = {KA_IN, KA_U32, KA_VAL, KA_REF, 0, nullptr, nullptr, nullptr};
-  sig[2] = {KA_PRIV, KA_U32, KA_VAL, KA_VAL, 1, nullptr, nullptr, &value_bits};
+  // private values: value_bits, and the largest request plus one (a hint for
+  // the small-request path; 0 = unknown)
+  uint64_t biggest = 0;
+  for (uint32_t j = 0; j < nreq; ++j) biggest = std::max<uint64_t>(biggest, (uint64_t)req_off[j + 1] - req_off[j]);
+  const uint32_t priv_vals[2] = {value_bits, biggest < 0xFFFFFFFEull ? (uint32_t)biggest + 1u : 0u};
+  sig[2] = {KA_PRIV, KA_U32, KA_VAL, KA_VAL, 2, nullptr, nullptr, priv_vals};
   for (int i = 3; i < 8; ++i) sig[i] = {KA_OUT, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
   ka_nd_range r{};
   r.dims = 1;

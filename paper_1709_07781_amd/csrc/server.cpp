@@ -238,9 +238,11 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
       return b;
     }
     uint64_t* lens = reinterpret_cast<uint64_t*>(dev + d_lens);
+    uint32_t biggest = 0;
+    for (auto* r : b->reqs[KA_REQ_WAH]) biggest = std::max<uint32_t>(biggest, (uint32_t)r->n);
     if (rw)
       rc = launch_wah_batch(env, u32(d_vw), nw, u32(d_rw), rw, value_bits, u32(d_keys), u32(d_offs), u32(d_words),
-                            u32(d_ks), u32(d_ws), lens, lens + 1, lens + 2, lens + 3, lens + 4);
+                            u32(d_ks), u32(d_ws), lens, lens + 1, lens + 2, lens + 3, lens + 4, 0, biggest);
     if (!rc && rs) rc = launch_segmented_scan(env, u32(d_vs), u32(d_scan), ns, u32(d_rs), rs);
     for (size_t i = 0; !rc && nc && i < chain_a.size(); ++i)
       rc = launch_affine(env, u32(d_vc), nc, nullptr, 0, chain_a[i], chain_b[i]);

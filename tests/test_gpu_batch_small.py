@@ -1,0 +1,94 @@
+"""GPU parity of the batched index build on batches whose requests all hold at
+most 1024 values (one work-group per request: sort in LDS, encode, place).
+Every request must equal the oracle's index of that request alone, and the
+same batch through the tagged-sort path (value_bits above 22, where the
+small-request path does not apply) must give the same bytes."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+SMALL_SIZES = [0, 1, 2, 30, 31, 32, 61, 62, 63, 64, 93, 500, 1000, 1023, 1024, 0, 7]
+
+
+@pytest.fixture(scope="module")
+def sess():
+    from paper_1709_07781_amd.session import Session
+    s = Session()
+    yield s
+    s.close()
+
+
+def _offsets(sizes):
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    return off
+
+
+def _check(results, off, values):
+    ora = oracle.default()
+    assert len(results) == len(off) - 1
+    for j in range(len(off) - 1):
+        v = values[off[j]:off[j + 1]]
+        ek, eo, ew = ora.wah_index(v)
+        k, o, w = results[j]
+        np.testing.assert_array_equal(k, ek, err_msg=f"request {j} keys (n={v.size})")
+        np.testing.assert_array_equal(o, eo, err_msg=f"request {j} offsets (n={v.size})")
+        np.testing.assert_array_equal(w, ew, err_msg=f"request {j} words (n={v.size})")
+
+
+@pytest.mark.parametrize("kind", ["uniform", "all_equal", "alternating_chunks", "sparse_hot", "presorted", "reverse"])
+@pytest.mark.parametrize("value_bits", [12, 22])
+def test_small_requests_match_oracle(sess, kind, value_bits):
+    off = _offsets(SMALL_SIZES)
+    parts = []
+    for i, n in enumerate(SMALL_SIZES):
+        if kind == "uniform":
+            parts.append(workloads.uniform_values(500 + i, n, 1 << value_bits))
+        else:
+            parts.append(workloads.structured(kind, n, seed=600 + i) & np.uint32((1 << value_bits) - 1))
+    v = np.concatenate(parts).astype(np.uint32)
+    _check(sess.wah_batch(v, off, value_bits), off, v)
+
+
+def test_small_path_equals_tagged_sort_path(sess):
+    off, v = workloads.batched_requests(seed=71, count=400, lo_log2=0, hi_log2=10)
+    v = v & np.uint32((1 << 20) - 1)
+    small = sess.wah_batch(v, off, 22)  # every request <= 1024 values, value_bits <= 22
+    tagged = sess.wah_batch(v, off, 23)  # value_bits 23: the tagged radix sort path
+    assert len(small) == len(tagged)
+    for a, b in zip(small, tagged):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+    _check(small, off, v)
+
+
+def test_small_requests_reject_values_beyond_value_bits(sess):
+    import paper_1709_07781_amd as ka
+    off = np.array([0, 100, 300, 301], dtype=np.uint32)
+    v = workloads.uniform_values(81, 301, 1 << 10)
+    v[250] = 1 << 10
+    res = ka.ka_wah_batch_result()
+    rc = ka.lib.ka_wah_batch(sess.sys, v.ctypes.data, v.size, off.ctypes.data, 3, 10, 0, ctypes.byref(res))
+    assert rc == ka.KA_E_ARG
+    v[250] = 5
+    _check(sess.wah_batch(v, off, 10), off, v)
+
+
+def test_small_requests_plan_replays(sess):
+    from paper_1709_07781_amd.session import BatchPlan
+    off, v1 = workloads.batched_requests(seed=91, count=256, lo_log2=0, hi_log2=10)
+    n = int(off[-1])
+    v2 = workloads.uniform_values(92, n, 1 << 12)
+    plan = BatchPlan(sess, off, 12)
+    try:
+        for v in (v1, v2, v1):
+            plan.run(v)
+            _check(plan.result(), off, v)
+    finally:
+        plan.close()
