@@ -178,7 +178,11 @@ KA_API int ka_system_memory(ka_system* sys, uint64_t* in_use, uint64_t* reserved
  *   wah_index_batch       (in values; in req_off; priv value_bits; out keys; out offsets;
  *                          out words; out key_start; out word_start)
  *                                                                 the index of each of nreq requests
- *                                                                 (see ka_wah_batch), one pass for all
+ *                                                                 (see ka_wah_batch), one pass for all;
+ *                                                                 priv may hold a second value, the
+ *                                                                 largest request + 1: with requests of
+ *                                                                 at most 1024 values and value_bits
+ *                                                                 <= 22 each is built by one work-group
  * The names, their signatures and the data each one reads and writes are
  * documented at ka_spawn. */
 KA_API int ka_program_builtin(ka_system* sys, ka_program** out);
