@@ -183,6 +183,9 @@ KA_API int ka_system_memory(ka_system* sys, uint64_t* in_use, uint64_t* reserved
  *                                                                 largest request + 1: with requests of
  *                                                                 at most 1024 values and value_bits
  *                                                                 <= 22 each is built by one work-group
+ *                                                                 (under such a hint a request above
+ *                                                                 1024 values fails the batch: all
+ *                                                                 output lengths 0)
  * The names, their signatures and the data each one reads and writes are
  * documented at ka_spawn. */
 KA_API int ka_program_builtin(ka_system* sys, ka_program** out);

@@ -219,8 +219,11 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_index(const uint32_t* __r
   __shared__ uint32_t s_scan[kSmallBlock / 64];
   const uint32_t j = blockIdx.x, tid = threadIdx.x;
   const uint32_t b = req_off[j];
-  const uint32_t n = min(req_off[j + 1] - b, (uint32_t)kSmallMax);  // the host checked n <= kSmallMax
-  uint32_t over = 0;
+  // A request above kSmallMax (a wrong size hint) fails the batch like an
+  // out-of-range value; only its first kSmallMax values are touched.
+  const uint32_t n_req = req_off[j + 1] - b;
+  const uint32_t n = min(n_req, (uint32_t)kSmallMax);
+  uint32_t over = n_req > (uint32_t)kSmallMax ? 1u : 0u;
 #pragma unroll
   for (int q = 0; q < kSmallPer; ++q) {
     const uint32_t i = q * kSmallBlock + tid;

@@ -92,3 +92,57 @@ def test_small_requests_plan_replays(sess):
             _check(plan.result(), off, v)
     finally:
         plan.close()
+
+
+def test_actor_size_hint(sess):
+    """The builtin actor with its optional second private value (largest
+    request + 1): a hint of at most 1024 takes the small-request path, no hint
+    the tagged sort (same bytes); a request above 1024 values under such a
+    hint fails the batch (every output length 0) instead of being truncated."""
+    import paper_1709_07781_amd as ka
+    off = np.array([0, 10, 110, 110, 140], dtype=np.uint32)
+    v = workloads.uniform_values(61, 140, 1 << 8)
+
+    def run(hint):
+        priv = (ctypes.c_uint32 * 2)(8, hint)
+        act = sess.spawn("wah_index_batch", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_IN, in_mode=ka.KA_VAL),
+                                             ka.arg(ka.KA_PRIV, count=2, init=priv)] + [ka.arg(ka.KA_OUT)] * 5)
+        try:
+            refs = sess.request(act, ka.val(v.ctypes.data, v.size), ka.val(off.ctypes.data, off.size), n_out=5)
+        finally:
+            sess.release_actor(act)
+        try:
+            return [sess.length(r) for r in refs], [sess.read(r) for r in refs]
+        finally:
+            for r in refs:
+                sess.release_ref(r)
+
+    lens, outs = run(101)  # right: the largest request holds 100 values
+    lens0, outs0 = run(0)  # no hint
+    assert lens == lens0 and lens[0] > 0
+    for a, b in zip(outs, outs0):
+        np.testing.assert_array_equal(a, b)
+    words = outs[2]
+    ws = outs[4]
+    ora = oracle.default()
+    for j in range(len(off) - 1):
+        np.testing.assert_array_equal(words[ws[j]:ws[j + 1]], ora.wah_index(v[off[j]:off[j + 1]])[2])
+    lens_small, outs_small = run(11)  # below the largest request but within 1024: still exact
+    assert lens_small == lens
+    for a, b in zip(outs_small, outs):
+        np.testing.assert_array_equal(a, b)
+    big_off = np.array([0, 10, 2010], dtype=np.uint32)  # a 2000-value request
+    big_v = workloads.uniform_values(62, 2010, 1 << 8)
+    priv = (ctypes.c_uint32 * 2)(8, 11)
+    act = sess.spawn("wah_index_batch", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_IN, in_mode=ka.KA_VAL),
+                                         ka.arg(ka.KA_PRIV, count=2, init=priv)] + [ka.arg(ka.KA_OUT)] * 5)
+    try:
+        refs = sess.request(act, ka.val(big_v.ctypes.data, big_v.size), ka.val(big_off.ctypes.data, big_off.size),
+                            n_out=5)
+    finally:
+        sess.release_actor(act)
+    try:
+        assert [sess.length(r) for r in refs] == [0] * 5
+    finally:
+        for r in refs:
+            sess.release_ref(r)
