@@ -155,8 +155,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wave
 
 // ---- decoupled look-back -------------------------------------------------------
 
-constexpr uint32_t kNoTile = 0xFFFFFFFFu;
-
 __device__ __forceinline__ uint64_t lb_pack(uint32_t value, uint32_t epoch, uint32_t flag) {
   return ((uint64_t)value << 32) | ((uint64_t)epoch << 2) | flag;
 }
