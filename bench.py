@@ -480,8 +480,8 @@ def main() -> int:
                          "(a plain copy of known size, for scaling the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the pipeline is not sharded "
-              "across GPUs in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library runs the pipeline "
+              "on a single GPU and has no multi-GPU sharding", file=sys.stderr)
         return 2
     if args.workload == "batched":
         return bench_batched(args)
