@@ -9,10 +9,10 @@
 // the order in which work-groups are dispatched.  The fallback reads a
 // predecessor's input, which is why the input and output must not overlap.
 // (Tiles numbered by a ticket counter instead cost about 8 ns per work-group,
-// serialised on the counter.)  The
-// compaction is the primitive of the fuseFillsLiterals step (Sec. 4.1): it
-// removes the zero entries and keeps the order; its phases "count per group",
-// "scan of the group counts" and "move the valid elements" run in one kernel.
+// serialised on the counter.)  The compaction is the primitive of the
+// fuseFillsLiterals step (Sec. 4.1): it removes the zero entries and keeps the
+// order; its phases "count per group", "scan of the group counts" and "move
+// the valid elements" run in one kernel.
 //
 // Tile layout: round r of thread t holds the 4 consecutive elements starting at
 // tile_base + 4 (r * BLOCK + t), so every global access is a coalesced
