@@ -78,6 +78,115 @@ def measured_traffic(n_log2: int):
     return t["hbm_bytes_per_launch"]
 
 
+def host_info() -> dict:
+    """The host's CPU count and model (for the CPU baseline)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def timed_oracle(o, v, runs: int):
+    """The oracle's index of v, timed `runs` times with the calling thread
+    pinned to one core (restored afterwards).  Returns (seconds per run, the
+    last result)."""
+    old = None
+    try:
+        old = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(old)})
+    except (AttributeError, OSError):
+        old = None
+    times, res = [], None
+    try:
+        for _ in range(runs):
+            c0 = time.perf_counter()
+            res = o.wah_index(v)
+            times.append(time.perf_counter() - c0)
+    finally:
+        if old is not None:
+            os.sched_setaffinity(0, old)
+    return times, res
+
+
+def plain_request_leg(sess, args) -> dict:
+    """The plain configuration: one request of 2^16 values uniform below 1024
+    through ka_wah_index, host values in and host arrays out (the paper's
+    timer includes the transfers), median over repeated requests; also the
+    device-only time of the same request from HBM-resident input."""
+    import ctypes
+
+    import paper_1709_07781_amd as ka
+    import workloads
+
+    v = workloads.plain_request()
+    reps = 50
+    e2e = []
+    for k in range(reps + 3):
+        t0 = time.perf_counter()
+        res = ka.ka_wah_result()
+        ka.check(ka.lib.ka_wah_index(sess.sys, v.ctypes.data, v.size, 0, ctypes.byref(res)))
+        dt = time.perf_counter() - t0
+        D, W = res.D, res.W
+        ka.check(ka.lib.ka_wah_result_free(ctypes.byref(res)))
+        if k >= 3:
+            e2e.append(dt)
+    dv = sess.upload(v)
+    dev = []
+    import torch
+    for k in range(reps + 3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ka.ka_wah_result()
+        ka.check(ka.lib.ka_wah_index(sess.sys, ctypes.c_void_p(dv.data_ptr()), v.size,
+                                     ka.KA_WAH_INPUT_DEVICE | ka.KA_WAH_OUTPUT_REFS, ctypes.byref(res)))
+        dt = time.perf_counter() - t0
+        ka.check(ka.lib.ka_wah_result_free(ctypes.byref(res)))
+        if k >= 3:
+            dev.append(dt)
+    e2e_ms = float(np.median(e2e)) * 1e3
+    dev_ms = float(np.median(dev)) * 1e3
+    log(f"[bench] plain 2^16 request: {e2e_ms:.3f} ms end to end (host in/out), {dev_ms:.3f} ms from HBM")
+    return {"workload": "2^16 values uniform below 1024, one ka_wah_index call", "n": int(v.size), "D": int(D),
+            "W": int(W), "e2e_ms_median": e2e_ms, "e2e_elements_per_s": v.size / (e2e_ms * 1e-3),
+            "device_resident_ms_median": dev_ms, "device_resident_elements_per_s": v.size / (dev_ms * 1e-3),
+            "requests": reps, "how": "wall time per call on the host (waits for the result), median"}
+
+
+def pcie_inclusive_leg(sess, v, args) -> dict:
+    """The large request with host input and host outputs (ka_wah_index: copy
+    in, pipeline, copy the index back): the rate including the transfers over
+    PCIe.  Context only; `value` is measured from HBM-resident input."""
+    import ctypes
+
+    import paper_1709_07781_amd as ka
+
+    times = []
+    for k in range(4):
+        t0 = time.perf_counter()
+        res = ka.ka_wah_result()
+        ka.check(ka.lib.ka_wah_index(sess.sys, v.ctypes.data, v.size, 0, ctypes.byref(res)))
+        dt = time.perf_counter() - t0
+        D, W = res.D, res.W
+        ka.check(ka.lib.ka_wah_result_free(ctypes.byref(res)))
+        if k:
+            times.append(dt)
+    ms = float(np.median(times)) * 1e3
+    moved = 4 * v.size + 4 * (D + (D + 1) + W)
+    log(f"[bench] PCIe-inclusive large request: {ms:.2f} ms")
+    return {"ms_median": ms, "elements_per_s": v.size / (ms * 1e-3), "host_bytes_moved": int(moved),
+            "runs": len(times), "how": "ka_wah_index with host input and host outputs (pageable), wall time"}
+
+
 def bench_batched(args) -> int:
     """4096 index requests (sizes log-uniform in [2^10, 2^20], values below
     2^12): the batched actor wah_index_batch over all of them per step,
@@ -189,15 +298,39 @@ def bench_batched(args) -> int:
     log(f"[bench] small batch ({int(soff[-1])} elements): actor {s_ms:.3f} ms, graph {sg_ms:.3f} ms, "
         f"plain {sp_ms:.1f} ms")
 
+    outs = sess.request(batch, ka.ref(vin), ka.ref(oin), n_out=5)
+    keys, offs, words, ks, ws = (sess.read(r) for r in outs)
+    for r in outs:
+        sess.release_ref(r)
+    # Algorithmic bytes of the batch: the sum over its requests of one
+    # request's bytes, 16 P_j n_j + 8 n_j + 4 W_j + 8 D_j + 4, with P_j the
+    # 8-bit digit passes request j's own values need.
+    sizes = np.diff(off)
+    nonempty = sizes > 0
+    starts = off[:-1][nonempty]
+    P_j = np.zeros(nreq, dtype=np.int64)
+    for p in range(4):
+        d = ((v >> np.uint32(8 * p)) & np.uint32(0xFF)).astype(np.uint8)
+        moves = np.minimum.reduceat(d, starts) != np.maximum.reduceat(d, starts)
+        P_j[nonempty] += moves
+    P_j[nonempty] = np.maximum(P_j[nonempty], 1)
+    D_j = np.diff(ks.astype(np.int64))
+    W_j = np.diff(ws.astype(np.int64))
+    batch_bytes = int(np.sum(16 * P_j * sizes + 8 * sizes + 4 * W_j + 8 * D_j + 4 * nonempty))
+    b_gbs = batch_bytes / (b_ms * 1e-3) / 1e9
+    g_gbs = batch_bytes / (g_ms * 1e-3) / 1e9
+    sc_launches, sc_ms = prof["radix_scatter"]
+    P_tag, _ = active_passes(((np.repeat(np.arange(nreq, dtype=np.uint32), sizes) << np.uint32(12)) | v)
+                            if N else v)
+    sc_bytes = (12 * N + 16 * N * (P_tag - 1)) * args.steps
+    sc_gbs = sc_bytes / max(sc_launches, 1) / (sc_ms / max(sc_launches, 1) * 1e-3) / 1e9
+    log(f"[bench] batched: sum of per-request bytes {batch_bytes / 1e9:.2f} GB: actor {b_gbs:.0f} GB/s, "
+        f"graph {g_gbs:.0f} GB/s")
+
     parity = None
     if not args.no_parity:
-        outs = sess.request(batch, ka.ref(vin), ka.ref(oin), n_out=5)
-        keys, offs, words, ks, ws = (sess.read(r) for r in outs)
-        for r in outs:
-            sess.release_ref(r)
         import oracle
         o = oracle.default()
-        sizes = np.diff(off)
         ok = True
         for j in sorted({0, nreq - 1, int(np.argmax(sizes)), int(np.argmin(sizes))}):
             ek, eo, ew = o.wah_index(v[off[j]:off[j + 1]])
@@ -227,6 +360,14 @@ def bench_batched(args) -> int:
         "small_batch": {"workload": "4096 requests, sizes log-uniform in [2^4, 2^10], values below 2^12",
                         "n": int(soff[-1]), "actor_ms": s_ms, "graph_ms": sg_ms, "plain_ms": sp_ms,
                         "shape": tuned[1][0], "first_run_ms_per_shape": tuned[1][1][:3]},
+        "roofline": {"bound": "hbm", "kernel": "k_radix_scatter", "achieved": sc_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": sc_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "launches": sc_launches, "avg_launch_ms": sc_ms / max(sc_launches, 1),
+                     "algorithmic_bytes_per_launch": sc_bytes / max(sc_launches, 1), "tag_passes": P_tag},
+        "pipeline": {"algorithmic_bytes": batch_bytes,
+                     "bytes_formula": "sum over requests of 16*P_j*n_j + 8*n_j + 4*W_j + 8*D_j + 4",
+                     "actor_GBs": b_gbs, "actor_frac": b_gbs / HBM_PEAK_GBS, "graph_GBs": g_gbs,
+                     "graph_frac": g_gbs / HBM_PEAK_GBS},
         "batched_wall_s_per_step": b_wall,
         "kernel_ms_per_step": {k: prof[k][1] / args.steps for k in prof if prof[k][0]},
         "parity": parity,
@@ -256,6 +397,11 @@ def bench_served(args) -> int:
     pool_u32 = workloads.u32(workloads.derive(5, 11), pool_n)
     rates = [float(r) for r in args.rates.split(",") if r]
     rows = []
+    check_every = 64  # every 64th timed request is checked against the oracle after its run
+    parity_ok = True
+    if not args.no_parity:
+        import oracle
+        ora = oracle.default()
     for rate in rates:
         count = int(min(args.served_max, max(50, rate * args.served_seconds)))
         warm = max(50, count // 8)
@@ -268,9 +414,11 @@ def bench_served(args) -> int:
         for form, kw in (("batched", batched_kw), ("plain", dict(streams=1, max_batch=1))):
             srv = Server(sess, chain_a=a, chain_b=b, **kw)
 
-            def run(lo, hi):
+            def run(lo, hi, keep=None):
                 """Requests lo..hi-1 on their schedule; a client thread takes
-                each result as it completes and releases it."""
+                each result as it completes and releases it.  keep: a dict
+                that receives a copy of the outputs of every
+                check_every-th request, for the parity check after the run."""
                 m = hi - lo
                 handles = [None] * m
                 submitted = threading.Semaphore(0)
@@ -282,6 +430,9 @@ def bench_served(args) -> int:
                         rc = srv.wait(handles[j])
                         if rc != 0:
                             failures.append(rc)
+                        elif keep is not None and (lo + j) % check_every == 0:
+                            nout = 3 if kinds[lo + j] == workloads.KIND_WAH else 1
+                            keep[lo + j] = [srv.result(handles[j], i) for i in range(nout)]
                         srv.release(handles[j])
 
                 consumer = threading.Thread(target=consume)
@@ -311,18 +462,34 @@ def bench_served(args) -> int:
             srv.reset_stats()
             gc.collect()
             gc.disable()
+            kept = {}
             try:
                 w0 = time.perf_counter()
-                run(warm, warm + count)
+                run(warm, warm + count, kept)
                 wall = time.perf_counter() - w0
             finally:
                 gc.enable()
             st = srv.stats()
             srv.close()
+            bad = 0
+            if not args.no_parity:
+                for k, outs in kept.items():
+                    pool = pool_idx if kinds[k] == workloads.KIND_WAH else pool_u32
+                    x = pool[starts[k]:starts[k] + sizes[k]]
+                    if kinds[k] == workloads.KIND_WAH:
+                        exp = ora.wah_index(x)
+                    elif kinds[k] == workloads.KIND_SCAN:
+                        exp = (ora.exclusive_scan(x),)
+                    else:
+                        exp = (ora.affine_chain(x, a, b),)
+                    bad += not all(np.array_equal(g, e) for g, e in zip(outs, exp))
             span_s = max(wall - 0.02, 1e-9)
             res[form] = {"p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3, "max_ms": st["max_us"] / 1e3,
                          "elements_per_s": st["elements"] / span_s, "requests_per_s": st["completed"] / span_s,
-                         "mean_batch": st["mean_batch"], "batches": st["batches"]}
+                         "mean_batch": st["mean_batch"], "batches": st["batches"],
+                         "parity": None if args.no_parity else
+                         (f"bit-exact ({len(kept)} requests checked)" if not bad else f"MISMATCH in {bad}")}
+            parity_ok &= bad == 0
             log(f"[bench] served rate={rate:.0f}/s {form}: p50={res[form]['p50_ms']:.2f} ms "
                 f"p99={res[form]['p99_ms']:.2f} ms, {res[form]['requests_per_s']:.0f} req/s, "
                 f"batch={st['mean_batch']:.1f}")
@@ -341,7 +508,7 @@ def bench_served(args) -> int:
         "served": rows,
     }
     print(json.dumps(out), flush=True)
-    return 0
+    return 0 if parity_ok else 1
 
 
 def bench_chain(args) -> int:
@@ -463,6 +630,8 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="skip the plain 2^16 request leg and the PCIe-inclusive leg of the default workload")
     ap.add_argument("--workload", choices=("large", "batched", "served", "chain"), default="large",
                     help="large: the 2^26 Zipf request (default); batched: 4096 requests of 2^10..2^20 values, "
                          "one batched pass against 4096 plain per-request pipelines; served: Poisson arrivals of "
@@ -470,9 +639,9 @@ def main() -> int:
                          "one-request-at-a-time server")
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000",
                     help="served: arrival rates in requests/s")
-    ap.add_argument("--served-seconds", type=float, default=2.0,
+    ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="served: seconds of arrivals per rate (at most --served-max requests)")
-    ap.add_argument("--served-max", type=int, default=4000)
+    ap.add_argument("--served-max", type=int, default=20000)
     ap.add_argument("--served-streams", type=int, default=2, help="served: streams of the batched server")
     ap.add_argument("--served-batch-mb", type=int, default=16, help="served: MiB of input per batch")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -557,12 +726,20 @@ def main() -> int:
     W = sess.length(last[2])
 
     # ---- algorithmic bytes (what the method has to move) -----------------------------
-    # scatter: the first active pass reads keys (rows are made from positions)
-    # and writes keys and rows; every later one reads and writes both.
+    # The pipeline: P stable pair passes of 16 B per element each (the first
+    # reads no rows but one 4 B histogram read of the keys is added), one read
+    # of the sorted pairs by the encoder (8n), and the index it writes
+    # (4W + 8D + 4).
+    pipe_bytes = 16 * P * n + 8 * n + 4 * W + 8 * D + 4
+    # What this implementation moves on top: the upsweep of every pass after
+    # the first re-reads the keys (4n per pass) and the encoder reads the
+    # sorted pairs twice (its count kernel, 8n); the first scatter pass reads
+    # no rows (-4n).
+    overhead_bytes = 4 * n * (P - 1) + 8 * n - 4 * n
+    # The dominant kernel, k_radix_scatter: the first active pass reads keys
+    # (rows are made from positions) and writes keys and rows; every later one
+    # reads and writes both.
     scatter_bytes = 12 * n + 16 * n * (P - 1)
-    upsweep_bytes = 4 * n * P
-    enc_bytes = 8 * n + 4 * W + 8 * D + 4
-    pipe_bytes = scatter_bytes + upsweep_bytes + enc_bytes  # = 20 P n + 4 n + 4 W + 8 D + 4 (+ the small tables)
     launches, scatter_ms = prof["radix_scatter"]
     per_launch_bytes = scatter_bytes * args.steps / max(launches, 1)
     avg_launch_ms = scatter_ms / max(launches, 1)
@@ -583,30 +760,25 @@ def main() -> int:
         del buf
         log("[bench] copy calibration: 3 in-place affine launches over 2^%d words" % args.n_log2)
 
+    plain = None if args.no_extra_legs else plain_request_leg(sess, args)
+    pcie = None if args.no_extra_legs else pcie_inclusive_leg(sess, v, args)
+
     parity = None
-    ora_s = None
     cpu = None
     if not args.no_cpu_baseline or not args.no_parity:
         import oracle
         o = oracle.default()
-        c0 = time.perf_counter()
-        ek, eo, ew = o.wah_index(v)
-        ora_s = time.perf_counter() - c0
-        reps = 1
-        if ora_s < 10.0 and not args.no_cpu_baseline:
-            c0 = time.perf_counter()
-            o.wah_index(v)
-            ora_s = (ora_s + time.perf_counter() - c0) / 2
-            reps = 2
-        log(f"[bench] oracle: {ora_s:.2f}s per request ({reps} runs, 1 thread)")
+        times, (ek, eo, ew) = timed_oracle(o, v, 1 if args.no_cpu_baseline else 3)
+        log(f"[bench] oracle: {np.median(times):.2f}s per request (median of {len(times)}, one pinned core)")
         if not args.no_parity:
             ok = (np.array_equal(sess.read(last[0]), ek) and np.array_equal(sess.read(last[1]), eo)
                   and np.array_equal(sess.read(last[2]), ew))
             parity = "bit-exact" if ok else "MISMATCH"
         if not args.no_cpu_baseline:
-            cpu = {"value": n / ora_s, "unit": "elements/s", "cores": 1, "kind": "oracle",
-                   "sample": f"the full 2^{args.n_log2}-element request, {reps} run(s), single thread "
-                             "(std::stable_sort + sequential six-part WAH encoder)"}
+            cpu = {"value": n / float(np.median(times)), "unit": "elements/s", "cores": 1, "kind": "oracle",
+                   "sample": f"the full 2^{args.n_log2}-element request, median of {len(times)} runs on one core "
+                             "(std::stable_sort + sequential six-part WAH encoder)",
+                   "runs_s": times, "host": host_info()}
     for r in last:
         sess.release_ref(r)
 
@@ -631,12 +803,15 @@ def main() -> int:
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launches": launches, "avg_launch_ms": avg_launch_ms,
                      "algorithmic_bytes_per_launch": per_launch_bytes},
-        "pipeline": {"algorithmic_bytes": pipe_bytes, "ms": ms_per_step, "achieved_GBs": pipe_gbs,
+        "pipeline": {"algorithmic_bytes": pipe_bytes, "overhead_bytes": overhead_bytes,
+                     "bytes_formula": "16*P*n + 8*n + 4*W + 8*D + 4", "ms": ms_per_step, "achieved_GBs": pipe_gbs,
                      "frac": pipe_gbs / HBM_PEAK_GBS, "profiled_ms_per_step": prof_ms / args.steps,
                      "kernel_ms_per_step": {k: prof[k][1] / args.steps for k in prof},
                      "launches_per_step": {k: prof[k][0] / args.steps for k in prof},
                      "wall_s": wall},
         "cpu_baseline": cpu,
+        "plain_request": plain,
+        "pcie_inclusive": pcie,
         "parity": parity,
     }
     for a in (pipe, sort, enc):

@@ -368,8 +368,8 @@ KA_API int ka_batch_plan_result(ka_batch_plan* plan, ka_wah_batch_result* out);
 KA_API int ka_batch_plan_shape(ka_batch_plan* plan, int* shape, float* ms, uint32_t nms);
 KA_API int ka_batch_plan_destroy(ka_batch_plan* plan);
 
-/* ---- the served form (Sec. 3.3: the mailbox buffers messages in order of
- * arrival; Sec. 3.4: an OpenCL actor feeds its device's command queue) ------------ */
+/* ---- the served form (Sec. 2.1: an actor's messages wait in its mailbox in
+ * order of arrival; Sec. 3.6: an OpenCL actor's mailbox maps to a command queue) - */
 /* Request kinds: the WAH index of the values (outputs keys, offsets, words, as
  * ka_wah_index), their exclusive scan mod 2^32 (one output), or the server's
  * affine chain x <- a_i x + b_i, i = 0..chain_len-1 (one output). */
@@ -435,6 +435,26 @@ KA_API int ka_server_reset_stats(ka_server* srv);
 KA_API int ka_server_clock_us(double* now);
 /* Cancels waiting requests, waits for batches in flight, stops the threads. */
 KA_API int ka_server_destroy(ka_server* srv);
+
+/* ---- allocation-free index build ---------------------------------------------------- */
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc.  The same
+ * composed build as ka_wah_index (same kernels, same words), with every
+ * scratch buffer carved from one static device array of the library (about
+ * 66 MiB per device, held by each device the library runs on until the process
+ * ends).  The array's device address is looked up on the first call on each
+ * device; no call allocates or frees device memory.
+ *
+ * All pointers are device memory of the current HIP device: values[n]; keys
+ * (capacity n), offsets (n + 1) and words (2n) as in ka_wah_index; lengths[3]
+ * receives D, D + 1 and W (uint64, written on the device).  The work is queued
+ * on `stream` (a hipStream_t; NULL = the default stream) and the call does not
+ * wait.  KA_E_ARG if n > KA_NOALLOC_MAX_N or a pointer is missing.  Every call
+ * on one device shares the static array: calls that may overlap on a device
+ * (other streams, other threads) race and must be ordered by the caller. */
+#define KA_NOALLOC_MAX_N (1u << 22)
+KA_API int ka_wah_index_noalloc(const uint32_t* values, uint64_t n, uint32_t* keys, uint32_t* offsets,
+                                uint32_t* words, uint64_t* lengths, void* stream);
 
 /* ---- the actor-overhead baseline (Sec. 3.6) ---------------------------------------- */
 /* Queues `stages` launches of the affine kernel (x <- a[i] x + b[i] mod 2^32)

@@ -137,6 +137,7 @@ SIGNATURES = {
     "ka_wah_batch": [_P, _P, _U64, _P, _U32, _U32, _U32, ctypes.POINTER(ka_wah_batch_result)],
     "ka_wah_batch_result_free": [ctypes.POINTER(ka_wah_batch_result)],
     "ka_affine_chain_raw": [_P, _P, _U64, _P, _P, _U32],
+    "ka_wah_index_noalloc": [_P, _U64, _P, _P, _P, _P, _P],
     "ka_batch_plan_create": [_P, _P, _U32, _U32, _U32, _PP],
     "ka_batch_plan_shape": [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float), _U32],
     "ka_batch_plan_input": [_P, _PP],

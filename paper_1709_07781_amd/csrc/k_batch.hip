@@ -48,12 +48,15 @@ __device__ __forceinline__ uint32_t request_of(const T* off, uint32_t lo, uint32
 }
 
 // Per-value maps that need the request of each value.
-struct TagOp {  // key = request << value_bits | value; flags values with bits at or above value_bits
+// key = request << value_bits | value; a value with bits at or above
+// value_bits is flagged, and only its low value_bits bits enter the key, so the
+// request field of every key stays below nreq even in a rejected batch.
+struct TagOp {
   uint32_t value_bits;
   __device__ __forceinline__ uint32_t operator()(uint32_t v, uint32_t j, uint32_t& over) const {
     if (!tag_shift_ok(value_bits)) return v;
     over |= v >> value_bits;
-    return j << value_bits | v;
+    return j << value_bits | (v & ((1u << value_bits) - 1u));
   }
 };
 struct RebaseOp {  // a batch-wide exclusive scan minus its value at the request's first position

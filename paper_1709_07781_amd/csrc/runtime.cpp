@@ -390,16 +390,25 @@ int ref_length(Ref* r, uint64_t* len) {
   return KA_OK;
 }
 
-int ref_use_on(Ref* r, uint32_t si) {
+int ref_use_on(Ref* r, uint32_t si, bool write) {
   System* sys = r->sys;
-  if (r->home != si) {
+  // A read waits for the last writer; a write also waits for every stream that
+  // may still be reading the buffer (no write-after-read across streams).
+  uint64_t wait = write ? (r->used_mask.load() | (1ull << r->home)) : (1ull << r->home);
+  wait &= ~(1ull << si);
+  for (uint32_t s = 0; wait && s < sys->streams.size(); ++s) {
+    if (!((wait >> s) & 1ull)) continue;
     hipEvent_t e = sys->get_event();
     if (!e) return set_error(KA_E_DEVICE, "event creation failed");
-    KA_HIP(hipEventRecord(e, sys->streams[r->home]->s), "hipEventRecord");
+    KA_HIP(hipEventRecord(e, sys->streams[s]->s), "hipEventRecord");
     KA_HIP(hipStreamWaitEvent(sys->streams[si]->s, e, 0), "hipStreamWaitEvent");
     sys->put_event(e);  // reusable: the wait is already queued
   }
-  r->used_mask.fetch_or(1ull << si);
+  // After a write on si every earlier use is ordered before si's later work.
+  if (write)
+    r->used_mask.store(1ull << si);
+  else
+    r->used_mask.fetch_or(1ull << si);
   return KA_OK;
 }
 
@@ -672,7 +681,7 @@ static int run_kernel_actor(Actor* a, Msg& msg, Msg& out, uint32_t si) {
     } else {
       r = v.ref;
       ref_retain(r);
-      if ((rc = ref_use_on(r, si))) {
+      if ((rc = ref_use_on(r, si, a->sig[i].a.dir == KA_IN_OUT))) {
         ref_release(r);
         cleanup();
         return rc;

@@ -223,8 +223,9 @@ void ref_release(Ref* r);
 int ref_sync(Ref* r);
 // The true length (reads the device slot if needed; waits).
 int ref_length(Ref* r, uint64_t* len);
-// Orders stream si after the last writer of r and records the use.
-int ref_use_on(Ref* r, uint32_t si);
+// Orders stream si after the last writer of r (and, for a write, after every
+// stream that used r) and records the use.
+int ref_use_on(Ref* r, uint32_t si, bool write);
 
 // ---- programs and built-in kernels -------------------------------------------
 struct Bound {  // one signature argument bound for a launch

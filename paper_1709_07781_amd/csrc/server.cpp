@@ -1,6 +1,7 @@
-// The served form: an actor's mailbox (Sec. 3.3: messages are buffered and
-// processed in order of arrival; Sec. 3.4: an OpenCL actor maps its mailbox
-// onto the device's command queue) turned into continuous batching.
+// The served form: an actor's mailbox (Sec. 2.1: messages wait at the receiver
+// in order of arrival until they are processed; Sec. 3.6: an OpenCL actor's
+// mailbox maps to a command queue of the device) turned into continuous
+// batching.
 //
 //  * ka_server_submit copies the request's data into pinned host memory
 //    (recycled by size class) and appends it to the mailbox with its arrival

@@ -192,3 +192,38 @@ def test_budget_exceeded():
         s.release_actor(act)
     finally:
         s.close()
+
+
+def test_in_place_write_waits_for_reads_on_other_streams():
+    """A ref read by an actor on stream 1 and then written in place by an actor
+    on stream 0: the write must not start before the read has finished
+    (Sec. 3.5: refs are shared between stages).  The scan on stream 1 must see
+    the original values."""
+    import torch
+    from paper_1709_07781_amd.session import Session
+    ka = _ka()
+    s = Session(n_streams=2)
+    try:
+        n = 1 << 24
+        x = workloads.u32(61, n)
+        dx = s.upload(x)
+        rx = s.wrap(dx)
+        scan = s.spawn("exclusive_scan_u32", [ka.arg(ka.KA_IN), ka.arg(ka.KA_OUT)])
+        ka.check(ka.lib.ka_actor_set_stream(scan, 1))
+        aff = s.affine_actor(3, 5)
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = s.send(scan, ka.ref(rx))
+            (r,) = s.request(aff, ka.ref(rx), n_out=1)
+            (y,) = s.receive(t, 1)
+            s.release_ticket(t)
+            np.testing.assert_array_equal(s.read(y), oracle.default().exclusive_scan(x))
+            s.release_ref(y)
+            s.release_ref(r)
+            x = (x * np.uint32(3) + np.uint32(5)).astype(np.uint32)
+            np.testing.assert_array_equal(s.read(rx), x)
+        s.release_actor(scan)
+        s.release_actor(aff)
+        s.release_ref(rx)
+    finally:
+        s.close()

@@ -115,23 +115,42 @@ def test_batch_argument_errors(sess):
             assert rc == ka.KA_E_ARG, (i, rc)
 
 
-def test_batch_full_config_sampled(sess):
+def test_batch_full_config_every_request(sess):
     """The batched configuration at full size (4096 requests, sizes 2^10..2^20,
-    values below 2^12, about 6.2e8 elements) in the launch bench.py times;
-    parity on a sample of requests (first, last, largest, smallest and 12
-    drawn ones) and the totals against the per-request sums of the sample."""
+    values below 2^12, about 6.2e8 elements) in the launch bench.py times:
+    every request's keys, offsets and words against the oracle's index of that
+    request alone.  This is the case that reaches the encoder's multi-group
+    tile offsets (more than 1024 encoder tiles) together with request-relative
+    rows.  The oracle runs on a pool of host threads."""
     import torch
+    from parallel_oracle import map_requests
     off, v = workloads.batched_requests()
     dv = torch.from_numpy(v.view(np.int32)).to("cuda")
     res = sess.wah_batch(dv, off, 12)
     del dv
-    sizes = np.diff(off)
-    rng = np.random.default_rng(7)
-    sample = sorted({0, len(sizes) - 1, int(np.argmax(sizes)), int(np.argmin(sizes))}
-                    | set(rng.choice(len(sizes), 12, replace=False).tolist()))
-    _check(res, off, v, oracle.default(), sample=sample)
-    # every request's index is well formed: offsets start at 0 and end at its word count
-    for j in range(len(sizes)):
-        k, o, w = res[j]
-        assert o[0] == 0 and o[-1] == w.size and o.size == k.size + 1
-        assert (k.size == 0) == (sizes[j] == 0)
+    torch.cuda.empty_cache()
+    nreq = len(off) - 1
+    assert len(res) == nreq
+    exp = map_requests("wah_index", [v[off[j]:off[j + 1]] for j in range(nreq)])
+    for j in range(nreq):
+        for got, e, what in zip(res[j], exp[j], ("keys", "offsets", "words")):
+            if not np.array_equal(got, e):
+                raise AssertionError(f"request {j} (n={off[j + 1] - off[j]}): {what} differ from the oracle")
+
+
+def test_batch_tagged_path_rejects_wide_values(sess):
+    """A batch on the tagged-sort path (a request above 1024 values) holding
+    values far above 2^value_bits (0xFFFFFFFF, 2^15 with value_bits 12) is
+    rejected with KA_E_ARG, every request tag stays in range while it is
+    rejected, and the system stays usable afterwards."""
+    import paper_1709_07781_amd as ka
+    v = workloads.uniform_values(52, 6000, 1 << 12)
+    v[17] = 0xFFFFFFFF
+    v[4321] = 1 << 15
+    off = np.array([0, 1500, 1500, 6000], dtype=np.uint32)
+    res = ka.ka_wah_batch_result()
+    rc = ka.lib.ka_wah_batch(sess.sys, v.ctypes.data, v.size, off.ctypes.data, 3, 12, 0, ctypes.byref(res))
+    assert rc == ka.KA_E_ARG
+    good = v & np.uint32(0xFFF)
+    got = sess.wah_batch(good, off, 12)
+    _check(got, off, good, oracle.default())

@@ -99,3 +99,24 @@ def test_sort_2p28_properties(sess):
     seen = np.zeros(n, dtype=bool)
     seen[sr] = True
     assert seen.all()                          # rows are a permutation
+
+
+@pytest.mark.parametrize("lg", [10, 14, 18, 22, 24])
+def test_affine_chain_raw_launches(sess, lg):
+    """The raw launch sequence of the actor-overhead comparison
+    (ka_affine_chain_raw: 8 launches of the affine kernel, no actors) at the
+    chain workload's sizes, against the oracle's chain."""
+    import ctypes
+    import torch
+    import paper_1709_07781_amd as ka
+    a, b = workloads.chain_params()
+    ca = np.ascontiguousarray(a, dtype=np.uint32)
+    cb = np.ascontiguousarray(b, dtype=np.uint32)
+    x = workloads.chain_input(m=1 << lg)
+    dv = sess.upload(x)
+    torch.cuda.synchronize()
+    ka.check(ka.lib.ka_affine_chain_raw(sess.sys, ctypes.c_void_p(dv.data_ptr()), x.size, ca.ctypes.data,
+                                        cb.ctypes.data, 8))
+    sess.synchronize()
+    got = dv.cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(got, oracle.default().affine_chain(x, a, b))

@@ -135,3 +135,45 @@ def test_destroy_cancels_or_finishes_everything(sess):
             done += 1
         lib.ka_server_request_release(h)
     assert done >= 1
+
+
+def test_served_mix_at_full_sizes(sess):
+    """The served configuration's sizes (log-uniform in [2^8, 2^22]) under its
+    16 MiB batch limit: 40 requests of the mix, one index request of 2^22
+    values (16 MiB: a batch of its own), and three index requests whose inputs
+    add up to 4 bytes under 16 MiB (one batch filled to the limit), all queued
+    at once.  Every result equals the oracle's and the one the same request
+    gets from a server that runs one request at a time."""
+    import concurrent.futures as cf
+    from parallel_oracle import host_threads
+    from paper_1709_07781_amd.session import Server
+    a, b = _chain()
+    ora = oracle.default()
+    reqs = _mix(40, seed=62, lo=8, hi=22)
+    reqs.append((workloads.KIND_WAH, workloads.uniform_values(63, 1 << 22, 4096)))
+    third = (16 << 20) // 4 // 3
+    reqs += [(workloads.KIND_WAH, workloads.uniform_values(64 + i, third, 4096)) for i in range(3)]
+    assert sum(x.size for _, x in reqs[-3:]) * 4 == (16 << 20) - 4
+    with cf.ThreadPoolExecutor(max_workers=host_threads()) as ex:
+        exp = list(ex.map(lambda kx: _expected(ora, kx[0], kx[1], a, b), reqs))
+    mixed = Server(sess, streams=2, max_batch=1024, max_batch_bytes=16 << 20, chain_a=a, chain_b=b)
+    alone = Server(sess, streams=1, max_batch=1, chain_a=a, chain_b=b)
+    try:
+        hm = [mixed.submit(k, x) for k, x in reqs]
+        for (k, x), e in zip(reqs, exp):
+            h = alone.submit(k, x)
+            assert alone.wait(h) == 0
+            for g, ee in zip(_results(alone, h, k), e):
+                np.testing.assert_array_equal(g, ee, err_msg=f"alone: kind {k}, n={x.size}")
+            alone.release(h)
+        for (k, x), h, e in zip(reqs, hm, exp):
+            assert mixed.wait(h) == 0
+            for g, ee in zip(_results(mixed, h, k), e):
+                np.testing.assert_array_equal(g, ee, err_msg=f"mixed: kind {k}, n={x.size}")
+            mixed.release(h)
+        st = mixed.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+        assert st["mean_batch"] > 1.0
+    finally:
+        mixed.close()
+        alone.close()
