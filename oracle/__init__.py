@@ -39,6 +39,13 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "ora_wah_table": [_U32P, _U32P, ctypes.c_uint64, _U32P, _U32P, _U64P],
         "ora_wah_index": [_U32P, ctypes.c_uint64, _U32P, _U32P, _U32P, _U64P, _U64P],
         "ora_wah_encode_sorted": [_U32P, _U32P, ctypes.c_uint64, _U32P, _U32P, _U32P, _U64P, _U64P],
+        "ora_wah_encode_groups": [_U32P, _U32P, _U32P, ctypes.c_uint64, ctypes.c_uint32, _U32P, _U32P, _U32P,
+                                  _U64P, _U64P],
+        "ora_wah_index_format": [_U32P, ctypes.c_uint64, ctypes.c_uint32, _U32P, _U32P, _U32P, _U64P, _U64P],
+        "ora_wah_lookup": [_U32P, ctypes.c_uint64, _U32P, ctypes.c_uint64, _U32P],
+        "ora_wah_decode": [_U32P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, _U32P],
+        "ora_wah_combine": [_U32P, ctypes.c_uint64, _U32P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                            ctypes.c_uint32, ctypes.c_uint32, _U32P, _U64P],
         "ora_exclusive_scan": [_U32P, ctypes.c_uint64, _U32P],
         "ora_affine_chain": [_U32P, ctypes.c_uint64, _U32P, _U32P, ctypes.c_uint32],
     }.items():
@@ -140,6 +147,51 @@ class Oracle:
         _check(self.lib.ora_wah_encode_sorted(_p(skeys), _p(srows), n, _p(keys), _p(offs), _p(words),
                                               ctypes.byref(D), ctypes.byref(W)), "wah_encode_sorted")
         return keys[: D.value].copy(), offs[: D.value + 1].copy(), words[: W.value].copy()
+
+    def wah_index_format(self, values, fmt: int):
+        """Index build in an encoder format (0 paper form, 1 canonical WAH,
+        2 PLWAH).  Returns (keys[D], offsets[D+1], words[W])."""
+        values = _u32(values)
+        n = values.size
+        keys = np.empty(max(n, 1), np.uint32)
+        offs = np.empty(n + 1, np.uint32)
+        words = np.empty(max(2 * n, 1), np.uint32)
+        D, W = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.ora_wah_index_format(_p(values), n, fmt, _p(keys), _p(offs), _p(words), ctypes.byref(D),
+                                             ctypes.byref(W)), "wah_index_format")
+        return keys[: D.value].copy(), offs[: D.value + 1].copy(), words[: W.value].copy()
+
+    def wah_encode_groups(self, gkey, gchunk, glit, fmt: int):
+        gkey, gchunk, glit = _u32(gkey), _u32(gchunk), _u32(glit)
+        k = gkey.size
+        keys = np.empty(max(k, 1), np.uint32)
+        offs = np.empty(k + 1, np.uint32)
+        words = np.empty(max(2 * k, 1), np.uint32)
+        D, W = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.ora_wah_encode_groups(_p(gkey), _p(gchunk), _p(glit), k, fmt, _p(keys), _p(offs), _p(words),
+                                              ctypes.byref(D), ctypes.byref(W)), "wah_encode_groups")
+        return keys[: D.value].copy(), offs[: D.value + 1].copy(), words[: W.value].copy()
+
+    def wah_lookup(self, keys, queries):
+        keys, queries = _u32(keys), _u32(queries)
+        out = np.empty(queries.size, np.uint32)
+        _check(self.lib.ora_wah_lookup(_p(keys), keys.size, _p(queries), queries.size, _p(out)), "wah_lookup")
+        return out
+
+    def wah_decode(self, words, fmt: int, ngroups: int):
+        words = _u32(words)
+        out = np.empty(ngroups, np.uint32)
+        _check(self.lib.ora_wah_decode(_p(words), words.size, fmt, ngroups, _p(out)), "wah_decode")
+        return out
+
+    def wah_combine(self, a, b, in_fmt: int, ngroups: int, op: int, out_fmt: int):
+        """AND (op 0) / OR (op 1) of two bitmaps, re-encoded in out_fmt."""
+        a, b = _u32(a), _u32(b)
+        out = np.empty(max(2 * ngroups, 1), np.uint32)
+        m = ctypes.c_uint64()
+        _check(self.lib.ora_wah_combine(_p(a), a.size, _p(b), b.size, in_fmt, ngroups, op, out_fmt, _p(out),
+                                        ctypes.byref(m)), "wah_combine")
+        return out[: m.value].copy()
 
     def exclusive_scan(self, x):
         x = _u32(x)

@@ -82,6 +82,96 @@ def brute_force_index(v: np.ndarray):
             np.array(words, dtype=np.uint32))
 
 
+FMT_PAPER, FMT_CANONICAL, FMT_PLWAH = 0, 1, 2
+FULL = 0x7FFFFFFF
+
+
+def decode_groups_format(words, fmt: int) -> list[int]:
+    """The 31-bit group words one bitmap's words stand for, from the word
+    layout of each format: a literal is one group; a fill is `length` groups
+    of 0 or all 31 bits (bit 30); in PLWAH the length has 25 bits and a
+    non-zero position p in bits 29..25 adds one group that differs from the
+    fill's groups in bit p - 1."""
+    out = []
+    for w in (int(x) for x in words):
+        if not w & FILL:
+            out.append(w)
+            continue
+        one = bool(w & 0x40000000)
+        length = w & (0x1FFFFFF if fmt == FMT_PLWAH else 0x3FFFFFFF)
+        pos = (w >> 25) & 31 if fmt == FMT_PLWAH else 0
+        assert length >= 1, "fill of length 0"
+        out += [FULL if one else 0] * length
+        if pos:
+            out.append(FULL ^ (1 << (pos - 1)) if one else 1 << (pos - 1))
+    return out
+
+
+def dense_groups(bits: np.ndarray) -> list[int]:
+    """31-bit group words of a boolean row vector (rows beyond it are 0)."""
+    n = bits.size
+    ng = (n + 30) // 31
+    padded = np.zeros(ng * 31, dtype=np.uint64)
+    padded[:n] = bits
+    grp = padded.reshape(ng, 31) if ng else padded.reshape(0, 31)
+    return [int(t) for t in (grp << np.arange(31, dtype=np.uint64)).sum(axis=1)]
+
+
+def definition_bitmap_words(groups: list[int], fmt: int) -> list[int]:
+    """One bitmap from the definition of each format, in two steps: first
+    run-length encode the group sequence (trailing empty groups dropped):
+    a run of empty groups is a 0-fill, a run of full groups a 1-fill (canonical
+    and PLWAH; the paper form keeps full groups as literals), every other
+    group a literal; then, for PLWAH, fold a literal that differs from the
+    fill just before it in one bit into that fill."""
+    while groups and groups[-1] == 0:
+        groups = groups[:-1]
+    words, i = [], 0
+    while i < len(groups):
+        g = groups[i]
+        homog = g == 0 or (g == FULL and fmt != FMT_PAPER)
+        if homog:
+            j = i
+            while j < len(groups) and groups[j] == g:
+                j += 1
+            words.append(("fill", g == FULL, j - i))
+            i = j
+        else:
+            words.append(("lit", g))
+            i += 1
+    out, k = [], 0
+    while k < len(words):
+        w = words[k]
+        if w[0] == "lit":
+            out.append(w[1])
+            k += 1
+            continue
+        _, one, length = w
+        pos = 0
+        if fmt == FMT_PLWAH and k + 1 < len(words) and words[k + 1][0] == "lit":
+            diff = words[k + 1][1] ^ (FULL if one else 0)
+            if bin(diff).count("1") == 1:
+                pos = diff.bit_length()
+                k += 1
+        limit = 0x1FFFFFF if fmt == FMT_PLWAH else 0x3FFFFFFF
+        assert length <= limit
+        out.append(FILL | (0x40000000 if one else 0) | (pos << 25) | length)
+        k += 1
+    return out
+
+
+def definition_index_format(v: np.ndarray, fmt: int):
+    """The index of v in format fmt from the definition (dense bitmap per value)."""
+    v = np.asarray(v, dtype=np.uint32)
+    keys, offsets, words = [], [0], []
+    for x in sorted(set(int(t) for t in v)):
+        words += definition_bitmap_words(dense_groups(v == x), fmt)
+        keys.append(x)
+        offsets.append(len(words))
+    return (np.array(keys, dtype=np.uint32), np.array(offsets, dtype=np.uint32),
+            np.array(words, dtype=np.uint32))
+
+
 def check_invariants(v: np.ndarray, keys, offsets, words):
     """Properties any correct index of v has, whatever the encoder."""
     v = np.asarray(v, dtype=np.uint32)
@@ -324,6 +414,164 @@ def pin_stage_composition(o):
         assert words.size <= idx.size  # compaction never grows the index
 
 
+def pin_golden_formats(o):
+    g, v = _load_golden("wah_formats_fills_and_tail.json")
+    for fmt, name in ((FMT_CANONICAL, "canonical"), (FMT_PLWAH, "plwah")):
+        keys, offs, words = o.wah_index_format(v, fmt)
+        np.testing.assert_array_equal(keys, np.array(g["keys"], dtype=np.uint32))
+        np.testing.assert_array_equal(offs, np.array(g[name]["offsets"], dtype=np.uint32), err_msg=name)
+        np.testing.assert_array_equal(words, _hex(g[name]["words"]), err_msg=name)
+
+
+def pin_formats_brute_force(o):
+    """Canonical WAH and PLWAH (and the paper form through the same entry)
+    against the definition encoder, over structured layouts and sizes that
+    cross group edges; full runs come from all-equal, alternating and sorted
+    inputs."""
+    kinds = ("all_equal", "alternating_chunks", "presorted", "uniform1024", "distinct", "sparse_hot", "zipf")
+    sizes = list(range(0, 70)) + [92, 93, 94, 124, 155, 186, 500, 1000, 1023, 1025]
+    for fmt in (FMT_PAPER, FMT_CANONICAL, FMT_PLWAH):
+        for kind in kinds:
+            for n in sizes:
+                v = workloads.structured(kind, n, seed=n + 29)
+                if kind == "uniform1024":
+                    v = v % np.uint32(max(1, n // 40 + 1))
+                got = o.wah_index_format(v, fmt)
+                exp = definition_index_format(v, fmt)
+                for a, b, what in zip(got, exp, ("keys", "offsets", "words")):
+                    np.testing.assert_array_equal(a, b, err_msg=f"{what} fmt={fmt} {kind} n={n}")
+
+
+def pin_formats_decode(o):
+    """decode(encode(v)) gives every value's rows back in each format, and each
+    encoding is in its normal form: no full literal in canonical WAH and PLWAH,
+    no two adjacent fills of one kind (unless the first holds a folded
+    literal), and in PLWAH no fill followed by a literal that differs from it
+    in one bit."""
+    for kind in workloads.STRUCTURED_KINDS:
+        for n in (0, 1, 30, 31, 32, 62, 63, 93, 124, 500, 4097):
+            v = workloads.structured(kind, n, seed=5 * n + 2)
+            for fmt in (FMT_CANONICAL, FMT_PLWAH):
+                keys, offs, words = o.wah_index_format(v, fmt)
+                np.testing.assert_array_equal(keys, np.unique(v))
+                assert offs[0] == 0 and offs[-1] == words.size
+                for d in range(keys.size):
+                    wd = [int(x) for x in words[offs[d]:offs[d + 1]]]
+                    groups = decode_groups_format(wd, fmt)
+                    ref = dense_groups(v == keys[d])
+                    assert groups == ref[:len(groups)] and not any(ref[len(groups):]), (kind, n, fmt, d)
+                    assert FULL not in wd, "a full group left as a literal"
+                    for a, b in zip(wd, wd[1:]):
+                        if a & FILL and b & FILL:  # (a PLWAH fill with a folded literal ends its run)
+                            assert (a ^ b) & 0x40000000 or (fmt == FMT_PLWAH and (a >> 25) & 31), \
+                                "two adjacent fills of one kind"
+                        if fmt == FMT_PLWAH and a & FILL and not b & FILL:
+                            diff = b ^ (FULL if a & 0x40000000 else 0)
+                            assert bin(diff).count("1") != 1 or (a >> 25) & 31, "literal not folded"
+
+
+def pin_formats_closed_forms(o):
+    # constant input of n = 31 m + t rows: one 1-fill of m groups, then the
+    # tail literal; PLWAH folds a 30-row tail (its clear bit is bit 30, p = 31)
+    for m, t in ((0, 5), (1, 0), (1, 30), (3, 7), (40, 30), (40, 0)):
+        n = 31 * m + t
+        v = np.full(n, 4, dtype=np.uint32)
+        tail = [(1 << t) - 1] if t else []
+        can = ([0xC0000000 | m] if m else []) + tail
+        np.testing.assert_array_equal(o.wah_index_format(v, FMT_CANONICAL)[2], np.array(can, dtype=np.uint32))
+        pl = ([0xC0000000 | (31 << 25) | m] if m and t == 30 else can)
+        np.testing.assert_array_equal(o.wah_index_format(v, FMT_PLWAH)[2], np.array(pl, dtype=np.uint32))
+    # a single row r: PLWAH writes one word, a fill with p = r % 31 + 1, when r >= 31
+    for r in (0, 30, 31, 100, 31 * 1000 + 17):
+        v = np.zeros(r + 1, dtype=np.uint32)
+        v[r] = 8
+        _, offs, words = o.wah_index_format(v, FMT_PLWAH)
+        exp = [FILL | ((r % 31 + 1) << 25) | (r // 31)] if r >= 31 else [1 << r]
+        np.testing.assert_array_equal(words[offs[-2]:offs[-1]], np.array(exp, dtype=np.uint32))
+    # all distinct values: one word per value in PLWAH
+    for n in (1, 31, 32, 500):
+        _, _, words = o.wah_index_format(np.arange(n, dtype=np.uint32), FMT_PLWAH)
+        assert words.size == n
+    # alternating groups of two values: 1-fills of length 1 between 0-fills of length 1
+    n = 31 * 6
+    v = ((np.arange(n) // 31) % 2).astype(np.uint32)
+    _, _, words = o.wah_index_format(v, FMT_CANONICAL)
+    exp = [0xC0000001, FILL | 1, 0xC0000001, FILL | 1, 0xC0000001] + [FILL | 1, 0xC0000001] * 3
+    np.testing.assert_array_equal(words, np.array(exp, dtype=np.uint32))
+
+
+def pin_plwah_length_field(o):
+    """PLWAH fill lengths have 25 bits: a gap of 2^25 - 1 groups fits, 2^25 is
+    refused; canonical WAH takes it (30 bits)."""
+    ok = o.wah_encode_groups([1], [(1 << 25) - 1], [1], FMT_PLWAH)[2]
+    np.testing.assert_array_equal(ok, np.array([FILL | (1 << 25) | ((1 << 25) - 1)], dtype=np.uint32))
+    try:
+        o.wah_encode_groups([1], [1 << 25], [1], FMT_PLWAH)
+    except RuntimeError:
+        pass
+    else:
+        raise AssertionError("a 2^25-group PLWAH fill was accepted")
+    can = o.wah_encode_groups([1], [1 << 25], [1], FMT_CANONICAL)[2]
+    np.testing.assert_array_equal(can, np.array([FILL | (1 << 25), 1], dtype=np.uint32))
+
+
+def pin_lookup(o):
+    keys = np.unique(workloads.uniform_values(3, 500, 3000))
+    q = np.concatenate([keys[::7], np.array([0, 1, 2999, 3000, 0xFFFFFFFF], dtype=np.uint32),
+                        workloads.uniform_values(4, 300, 3100)]).astype(np.uint32)
+    got = o.wah_lookup(keys, q)
+    pos = {int(k): i for i, k in enumerate(keys)}
+    exp = [pos.get(int(x), 0xFFFFFFFF) for x in q]
+    np.testing.assert_array_equal(got, np.array(exp, dtype=np.uint32))
+    np.testing.assert_array_equal(o.wah_lookup(np.zeros(0, np.uint32), q[:3]), [0xFFFFFFFF] * 3)
+
+
+def pin_decode_groups(o):
+    for fmt in (FMT_PAPER, FMT_CANONICAL, FMT_PLWAH):
+        for kind in ("zipf", "all_equal", "alternating_chunks", "sparse_hot", "presorted"):
+            n = 2000
+            v = workloads.structured(kind, n, seed=11)
+            keys, offs, words = o.wah_index_format(v, fmt)
+            ng = (n + 30) // 31
+            for d in range(0, keys.size, max(1, keys.size // 9)):
+                got = o.wah_decode(words[offs[d]:offs[d + 1]], fmt, ng)
+                np.testing.assert_array_equal(got, np.array(dense_groups(v == keys[d]), dtype=np.uint32))
+    try:
+        o.wah_decode(np.array([FILL | 5, 1], np.uint32), FMT_PAPER, 5)
+    except RuntimeError:
+        pass
+    else:
+        raise AssertionError("a bitmap longer than ngroups was decoded")
+
+
+def pin_combine(o):
+    """AND / OR of two bitmaps: the decoded result is the bitwise AND / OR of
+    the rows, its words are the definition encoding of that row set, and the
+    usual identities hold (x AND x = x, x OR x = x, commutativity)."""
+    n = 31 * 300 + 11
+    ng = (n + 30) // 31
+    for kind in ("zipf", "alternating_chunks", "presorted", "sparse_hot"):
+        v = workloads.structured(kind, n, seed=21)
+        for fmt in (FMT_PAPER, FMT_CANONICAL, FMT_PLWAH):
+            keys, offs, words = o.wah_index_format(v, fmt)
+            pick = [0, keys.size // 2, keys.size - 1]
+            bms = [words[offs[d]:offs[d + 1]] for d in pick]
+            rows = [v == keys[d] for d in pick]
+            # an OR of several values is a range-like set: many full groups
+            for i, j in ((0, 1), (1, 2), (0, 2), (1, 1)):
+                for op, f in ((0, np.logical_and), (1, np.logical_or)):
+                    for out_fmt in (FMT_PAPER, FMT_CANONICAL, FMT_PLWAH):
+                        got = o.wah_combine(bms[i], bms[j], fmt, ng, op, out_fmt)
+                        exp = definition_bitmap_words(dense_groups(f(rows[i], rows[j])), out_fmt)
+                        np.testing.assert_array_equal(got, np.array(exp, dtype=np.uint32),
+                                                      err_msg=f"{kind} fmt={fmt} op={op} out={out_fmt}")
+                        sym = o.wah_combine(bms[j], bms[i], fmt, ng, op, out_fmt)
+                        np.testing.assert_array_equal(got, sym)
+            same = o.wah_combine(bms[0], bms[0], fmt, ng, 0, fmt)
+            np.testing.assert_array_equal(same, bms[0])
+
+
 ALL_PINS = [pin_golden_indexes, pin_golden_fuse_stages, pin_brute_force_small, pin_decode_and_invariants,
             pin_closed_forms, pin_empty, pin_sort_pairs, pin_exclusive_scan, pin_compact, pin_affine,
-            pin_stage_composition]
+            pin_stage_composition, pin_golden_formats, pin_formats_brute_force, pin_formats_decode, pin_formats_closed_forms,
+            pin_plwah_length_field, pin_lookup, pin_decode_groups, pin_combine]

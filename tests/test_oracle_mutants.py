@@ -31,6 +31,23 @@ MUTANTS = [
     ("rows_are_ranks", ": static_cast<uint32_t>(perm[j]);", ": static_cast<uint32_t>(j);"),
     ("table_counts_zeros", "kept += (index[2 * g] != 0) + (index[2 * g + 1] != 0);", "kept += 2;"),
     ("groups_by_key_only_in_literal", "glit[g - 1] |= bit;", "glit[g - 1] = bit;"),
+    # encoder formats and the query path
+    ("one_fill_without_fill_bit", "kFillFlag | (one ? kOneFill : 0u)", "kFillFlag | (one ? 0u : 0u)"),
+    ("full_run_ignores_adjacency", "c[i + run] == c[i] + run && lit[i + run] == kFull",
+     "lit[i + run] == kFull"),
+    ("one_fold_position_no_plus_one", "p = 1 + odd_bit(lit[nx], true);", "p = odd_bit(lit[nx], true);"),
+    ("zero_fold_any_small_literal", "gap > 0 && popcount31(lit[i]) == 1", "gap > 0 && popcount31(lit[i]) <= 2"),
+    ("fold_keeps_literal_group", "prev = static_cast<int64_t>(c[i] + run - 1) + (p ? 1 : 0);",
+     "prev = static_cast<int64_t>(c[i] + run - 1);"),
+    ("plwah_30_bit_lengths", "format == kFormatPlwah ? kPlwahMaxLen : kMaxFillLen;\n  if (len > lim)",
+     "kMaxFillLen;\n  if (len > lim)"),
+    ("fold_after_one_fill_of_29", "popcount31(lit[nx]) == 30", "popcount31(lit[nx]) >= 29"),
+    ("decode_position_off_by_one", "one ? (kFull & ~(1u << (p - 1))) : (1u << (p - 1))",
+     "one ? (kFull & ~(1u << p)) : (1u << p)"),
+    ("lookup_insertion_point", "(p != keys + D && *p == queries[i]) ?", "(p != keys + D) ?"),
+    ("combine_or_as_and", "op == 0 ? (ga[g] & gb[g]) : (ga[g] | gb[g])", "(ga[g] & gb[g])"),
+    ("canonical_keeps_full_literals", "if (format != kFormatPaper && lit[i] == kFull) {",
+     "if (format == kFormatPlwah && lit[i] == kFull) {"),
 ]
 
 
