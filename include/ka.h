@@ -175,6 +175,13 @@ KA_API int ka_system_memory(ka_system* sys, uint64_t* in_use, uint64_t* reserved
  *   radix_sort_rows_u32   (in keys; out skeys; out srows)         same with rows 0..n-1 (Sec. 4.1 part 1-2)
  *   wah_encode_sorted     (in skeys; in srows; out keys; out offsets; out words)
  *                                                                 Sec. 4.1 parts 3-6 on sorted pairs
+ *   wah_index             (in values; priv value_bits; out keys; out offsets; out words)
+ *                                                                 Sec. 4.1 parts 1-6 in one actor: the
+ *                                                                 sort, then the encoder (same words as
+ *                                                                 the composition of the two actors above);
+ *                                                                 value_bits as KA_WAH_VALUE_BITS (0 = no
+ *                                                                 hint); a value at or above the hint
+ *                                                                 gives every output length 0
  *   wah_index_batch       (in values; in req_off; priv value_bits; out keys; out offsets;
  *                          out words; out key_start; out word_start)
  *                                                                 the index of each of nreq requests
@@ -277,6 +284,10 @@ KA_API int ka_ref_serialize(const ka_ref* ref, void* buf, uint64_t cap, uint64_t
 /* ---- the composed WAH index (Sec. 4) --------------------------------------------- */
 #define KA_WAH_INPUT_DEVICE 1u /* `values` is a device pointer (else host memory) */
 #define KA_WAH_OUTPUT_REFS 2u  /* return device refs (else host arrays from malloc) */
+/* Every value is below 2^b (b = 1..32; 0 = no hint).  With b <= 16 the sort
+ * runs ceil(b / 8) passes over 16-bit sort keys (Sec. 4.2 sorts with a fixed
+ * cardinality of 16 bits).  A value at or above 2^b fails with KA_E_ARG. */
+#define KA_WAH_VALUE_BITS(b) (((uint32_t)(b) & 0x3Fu) << 8)
 
 typedef struct ka_wah_result {
   uint64_t n;        /* input elements */
@@ -290,8 +301,10 @@ typedef struct ka_wah_result {
   ka_ref* words_ref;
 } ka_wah_result;
 
-/* Builds the WAH bitmap index of values[0..n) (rows 0..n-1) with the composed
- * actor wah_encode_sorted (.) radix_sort_rows_u32 and waits for it.  Word
+/* Builds the WAH bitmap index of values[0..n) (rows 0..n-1) with the built-in
+ * wah_index actor (the sort and encoder stages of the composed actor
+ * wah_encode_sorted (.) radix_sort_rows_u32, queued by one actor; same words)
+ * and waits for it.  flags: KA_WAH_* above.  Word
  * format: a literal has bit 31 clear and bit b standing for row 31*g + b of
  * its 31-row group g; a fill has bit 31 set, bit 30 clear and the number of
  * empty groups it covers in bits 29..0.  Each non-empty group of a value is
@@ -418,6 +431,21 @@ KA_API int ka_server_create(ka_system* sys, const ka_server_config* cfg, ka_serv
  * an index value at or above 2^value_bits.  n < 2^30. */
 KA_API int ka_server_submit(ka_server* srv, uint32_t kind, const uint32_t* data, uint64_t n, double arrival_us,
                             ka_srv_req** out);
+/* Queues a request given as a message (Sec. 3.4: request ... receive) and
+ * answers it with a ticket.  in[0] holds the request's uint32 data: a host
+ * value (KA_VAL, copied before return) or a device reference (KA_REF,
+ * borrowed: the server keeps its own reference until the request's batch has
+ * copied the data on the device, ordered after the ref's last writer).  The
+ * response, taken with ka_receive, is the request's outputs (KA_REQ_WAH: keys,
+ * offsets, words; otherwise one array) as host values, or with
+ * KA_SRV_OUTPUT_REFS as device references of their own (Sec. 3.5: a result
+ * handed on without leaving the device).  Each result is the one the request
+ * gets alone.  An index value at or above 2^value_bits fails only this
+ * request with KA_E_ARG (at the call for host data, at ka_receive for a
+ * reference).  Other arguments and errors as ka_server_submit. */
+#define KA_SRV_OUTPUT_REFS 1u
+KA_API int ka_server_send(ka_server* srv, uint32_t kind, const ka_value* in, uint32_t nin, uint32_t flags,
+                          double arrival_us, ka_ticket** out);
 /* Waits for a request (timeout_us < 0: no limit); KA_E_TIMEOUT leaves it
  * pending; a failed request returns its error (KA_E_CANCELLED if the server
  * was destroyed before it ran). */

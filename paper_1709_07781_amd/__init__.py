@@ -31,6 +31,10 @@ KA_SYS_PROFILE = 1
 KA_WAH_INPUT_DEVICE, KA_WAH_OUTPUT_REFS = 1, 2
 
 
+def KA_WAH_VALUE_BITS(b: int) -> int:
+    return (b & 0x3F) << 8
+
+
 # ---- structs (ka.h) -----------------------------------------------------------------
 class ka_system_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_uint32),
@@ -101,6 +105,7 @@ class ka_server_stats(ctypes.Structure):
 
 
 KA_REQ_WAH, KA_REQ_SCAN, KA_REQ_CHAIN = 0, 1, 2
+KA_SRV_OUTPUT_REFS = 1
 KA_PLAN_AUTOTUNE = 1
 
 
@@ -147,6 +152,7 @@ SIGNATURES = {
     "ka_batch_plan_destroy": [_P],
     "ka_server_create": [_P, ctypes.POINTER(ka_server_config), _PP],
     "ka_server_submit": [_P, _U32, _P, _U64, ctypes.c_double, _PP],
+    "ka_server_send": [_P, _U32, ctypes.POINTER(ka_value), _U32, _U32, ctypes.c_double, _PP],
     "ka_server_wait": [_P, _I64],
     "ka_server_result": [_P, _U32, _P, _U64, _U64P],
     "ka_server_request_release": [_P],

@@ -25,6 +25,12 @@ uint64_t cap_batch(uint32_t i, uint64_t n, const std::vector<Bound>& args) {
     default: return std::max<uint64_t>(slots, 1);
   }
 }
+// (in values; priv value_bits; out keys[D <= n]; out offsets[D+1]; out words[W <= 2n])
+uint64_t cap_wah_index(uint32_t i, uint64_t n, const std::vector<Bound>&) {
+  if (i == 2) return n ? n : 1;
+  if (i == 3) return n + 1;
+  return n ? 2 * n : 1;
+}
 bool len_host(uint32_t) { return false; }
 bool len_batch(uint32_t i) { return i >= 3; }
 bool len_compact(uint32_t i) { return i == 1; }
@@ -93,6 +99,48 @@ int run_wah(LaunchCtx& c) {
                            const_cast<uint64_t*>(a[3].d_len), const_cast<uint64_t*>(a[4].d_len));
 }
 
+// wah_index: (in values; priv value_bits; out keys; out offsets; out words) --
+// parts 1-6 of Sec. 4.1 in one actor: the stable sort of (value, row) pairs,
+// then the encoder.  value_bits 1..16: every value is below 2^value_bits, the
+// sort runs ceil(value_bits / 8) passes over uint16 sort keys; 17..31: values
+// below 2^value_bits, the sort of uint32 keys; 0 or 32: any uint32 value.  A
+// value at or above 2^value_bits voids the result (every output length 0).
+int run_wah_index(LaunchCtx& c) {
+  auto& a = *c.args;
+  Env& env = *c.env;
+  const uint64_t n = c.n;
+  const uint32_t bits = (uint32_t)a[1].priv[0];
+  if (bits > 32) return env.fail(KA_E_ARG, "wah_index: value_bits must be 0..32");
+  if (n > a[0].cap) return env.fail(KA_E_ARG, "wah_index: range exceeds the values");
+  if (a[2].cap < n || a[3].cap < n + 1 || a[4].cap < 2 * n)
+    return env.fail(KA_E_ARG, "wah_index: outputs need capacities n, n+1 and 2n");
+  if (n >= (1ull << 30)) return env.fail(KA_E_ARG, "wah_index: n must be below 2^30");
+  const uint32_t* values = static_cast<const uint32_t*>(a[0].ptr);
+  uint32_t* keys = static_cast<uint32_t*>(a[2].ptr);
+  uint32_t* offsets = static_cast<uint32_t*>(a[3].ptr);
+  uint32_t* words = static_cast<uint32_t*>(a[4].ptr);
+  uint64_t* lk = const_cast<uint64_t*>(a[2].d_len);
+  uint64_t* lo = const_cast<uint64_t*>(a[3].d_len);
+  uint64_t* lw = const_cast<uint64_t*>(a[4].d_len);
+  if (n == 0) return launch_wah_encode(env, nullptr, nullptr, 0, keys, offsets, words, lk, lo, lw);
+  int rc;
+  if (bits >= 1 && bits <= 16) {
+    uint32_t* reject = static_cast<uint32_t*>(env.scratch(4));
+    uint16_t* sk = static_cast<uint16_t*>(env.scratch(2 * n));
+    uint32_t* sr = static_cast<uint32_t*>(env.scratch(4 * n));
+    if (!reject || !sk || !sr) return env.fail(KA_E_OOM, "wah_index: scratch");
+    if ((rc = launch_radix_sort_rows16(env, values, sk, sr, n, bits, reject))) return rc;
+    return launch_wah_encode16(env, sk, sr, n, keys, offsets, words, lk, lo, lw, reject, 0);
+  }
+  uint32_t* sk = static_cast<uint32_t*>(env.scratch(4 * n));
+  uint32_t* sr = static_cast<uint32_t*>(env.scratch(4 * n));
+  if (!sk || !sr) return env.fail(KA_E_OOM, "wah_index: scratch");
+  if ((rc = launch_radix_sort_pairs(env, values, nullptr, sk, sr, n))) return rc;
+  const bool check = bits >= 17 && bits <= 31;
+  return launch_wah_encode(env, sk, sr, n, keys, offsets, words, lk, lo, lw, nullptr, 32,
+                           check ? sort_plan_keys_or(env) : nullptr, check ? bits : 32u);
+}
+
 // wah_index_batch: (in values; in req_off; priv value_bits [, largest request + 1];
 //                   out keys; out offsets; out words; out key_start; out word_start)
 int run_batch(LaunchCtx& c) {
@@ -136,6 +184,12 @@ std::vector<BuiltinKernel> make_registry() {
                len_wah,
                true,
                run_wah});
+  r.push_back({"wah_index",
+               {{KA_IN, KA_U32}, {KA_PRIV, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}},
+               cap_wah_index,
+               len_wah,
+               true,
+               run_wah_index});
   r.push_back({"wah_index_batch",
                {{KA_IN, KA_U32},
                 {KA_IN, KA_U32},

@@ -47,6 +47,8 @@ class Env {
   // Reserves `words` status words and one epoch.
   virtual bool lookback(uint64_t words, LbArgs* out) = 0;
   virtual LookbackArena* arena() = 0;
+  // Polls of a silent predecessor before a look-back takes the fallback.
+  virtual uint32_t spin_limit() { return kLbSpinLimit; }
   // Optional timing of one launch (no-ops unless profiling is on).
   virtual void prof_begin(const char* kernel) = 0;
   virtual void prof_end(const char* kernel) = 0;
@@ -66,19 +68,38 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
                             uint32_t* srows, uint64_t n, int shape = 0);
 // Number of tile shapes launch_radix_sort_pairs offers (shape 0 is the default).
 int sort_shape_count();
+// Device address of the OR of all keys of the last launch_radix_sort_pairs on
+// this stream (valid once that sort has run, for n > 0).
+const uint32_t* sort_plan_keys_or(Env& env);
+// Stable sort of (key, row = position) for keys below 2^value_bits, value_bits
+// 1..16, with uint16 sorted keys; a key at or above 2^value_bits sets
+// *reject to 1 (0 otherwise; *reject is device memory).
+int launch_radix_sort_rows16(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t* srows, uint64_t n,
+                             uint32_t value_bits, uint32_t* reject, int shape = 0);
+// WAH encoder over sorted pairs.  reject_flag, when given, voids the result
+// (every output length 0) if (*reject_flag >> reject_shift) != 0 once the
+// earlier kernels of the stream have run.
 int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                       uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
-                      uint64_t* d_len_words, const uint32_t* req_base = nullptr, uint32_t req_shift = 32);
+                      uint64_t* d_len_words, const uint32_t* req_base = nullptr, uint32_t req_shift = 32,
+                      const uint32_t* reject_flag = nullptr, uint32_t reject_shift = 32);
+// The same over uint16 sorted keys (values below 2^16).
+int launch_wah_encode16(Env& env, const uint16_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
+                        uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
+                        uint64_t* d_len_words, const uint32_t* reject_flag = nullptr, uint32_t reject_shift = 32);
 // Batched index build: nreq requests, values concatenated, req_off[j] the
 // first position of request j (req_off[nreq] = n).  max_req: the largest
 // request, when the caller knows it (kMaxReqUnknown otherwise); batches of
-// small requests take a one-work-group-per-request path.
+// small requests take a one-work-group-per-request path.  A value at or above
+// 2^value_bits rejects the whole batch (every output length 0), or, with
+// req_bad (nreq device words), only its own request: req_bad[j] = 1 and that
+// request's slices are unspecified while every other request's are exact.
 constexpr uint32_t kMaxReqUnknown = 0xFFFFFFFFu;
 int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
                      uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
                      uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
                      uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape = 0,
-                     uint32_t max_req = kMaxReqUnknown);
+                     uint32_t max_req = kMaxReqUnknown, uint32_t* req_bad = nullptr);
 // Exclusive scan of each of nreq requests concatenated in in[0..n) (req_off as
 // for the batched index).
 int launch_segmented_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* req_off,
@@ -109,6 +130,18 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // Native 4 x uint32 vector: one 16-byte global access.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Four consecutive keys p[4q .. 4q+3] from one 16-byte (uint32 keys) or 8-byte
+// (uint16 keys) non-temporal load; p must be aligned to that size.
+__device__ __forceinline__ void load_key4(const uint32_t* __restrict__ p, uint64_t q, uint32_t (&k)[4]) {
+  const u32x4 a = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p) + q);
+  k[0] = a.x, k[1] = a.y, k[2] = a.z, k[3] = a.w;
+}
+__device__ __forceinline__ void load_key4(const uint16_t* __restrict__ p, uint64_t q, uint32_t (&k)[4]) {
+  const u32x2 a = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p) + q);
+  k[0] = a.x & 0xFFFFu, k[1] = a.x >> 16, k[2] = a.y & 0xFFFFu, k[3] = a.y >> 16;
+}
 
 // Inclusive wave64 prefix sum: row_shr 1,2,4,8 inside each row of 16 lanes,
 // then row_bcast:15 and row_bcast:31 carry row totals across rows.
@@ -159,6 +192,10 @@ __device__ __forceinline__ uint64_t lb_pack(uint32_t value, uint32_t epoch, uint
   return ((uint64_t)value << 32) | ((uint64_t)epoch << 2) | flag;
 }
 
+__device__ __forceinline__ void lb_publish_raw(uint64_t* p, uint64_t w) {
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void lb_publish(uint64_t* p, uint32_t value, uint32_t epoch, uint32_t flag) {
   __hip_atomic_store(p, lb_pack(value, epoch, flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -172,79 +209,139 @@ __device__ __forceinline__ uint32_t lb_flag(uint64_t w, uint32_t epoch) {
   return (((uint32_t)w >> 2) == epoch) ? ((uint32_t)w & 3u) : 0u;
 }
 
+// Status words of a look-back chain.  LbEpoch: [value:32 | epoch:30 | flag:2],
+// stale words of earlier launches read as unpublished, nothing is cleared.
+// LbPair: two counts [a:32 | b:30 | flag:2] with no epoch, in a region cleared
+// before the launch (b sums below 2^30, so adding whole words never carries
+// into a).
+struct LbEpoch {
+  typedef uint32_t sum_t;
+  uint32_t epoch;
+  __device__ __forceinline__ uint32_t flag(uint64_t w) const { return lb_flag(w, epoch); }
+  __device__ __forceinline__ sum_t payload(uint64_t w) const { return (uint32_t)(w >> 32); }
+  __device__ __forceinline__ static sum_t zero() { return 0u; }
+  __device__ __forceinline__ static sum_t add(sum_t x, sum_t y) { return x + y; }
+  __device__ __forceinline__ static sum_t wave_total(sum_t x) { return wave_sum(x); }
+};
+
+struct LbPairSum {
+  uint32_t a, b;
+};
+
+__device__ __forceinline__ uint64_t lb_pack_pair(uint32_t a, uint32_t b, uint32_t flag) {
+  return ((uint64_t)a << 32) | ((uint64_t)b << 2) | flag;
+}
+
+struct LbPair {
+  typedef LbPairSum sum_t;
+  __device__ __forceinline__ uint32_t flag(uint64_t w) const { return (uint32_t)w & 3u; }
+  __device__ __forceinline__ sum_t payload(uint64_t w) const { return {(uint32_t)(w >> 32), (uint32_t)w >> 2}; }
+  __device__ __forceinline__ static sum_t zero() { return {0u, 0u}; }
+  __device__ __forceinline__ static sum_t add(sum_t x, sum_t y) { return {x.a + y.a, x.b + y.b}; }
+  __device__ __forceinline__ static sum_t wave_total(sum_t x) { return {wave_sum(x.a), wave_sum(x.b)}; }
+};
+
 // Decoupled look-back with fallback by one whole wave; status[t] is tile t's
-// status word.  In a round, lane l inspects the kDepth predecessors
-// j - kDepth*l .. j - kDepth*l - kDepth + 1, so one round trip to memory covers
-// 64*kDepth tiles; the window slides back until an inclusive prefix is found.
-// A predecessor that has published nothing after spin_limit polls is no
-// longer waited for: the wave computes its total itself with reduce(t) --
-// every lane calls it, and it returns the tile's total in every lane -- adds
-// it and goes on from the tile before it.  Every wait is therefore bounded
-// whatever order the work-groups run in, so tiles can be numbered by
+// status word, read through the policy St (LbEpoch or LbPair).  The wave waits
+// on the nearest tile it has not yet accounted for, j, with one status read per
+// poll (every lane reads the same word, one request): polling a wide window
+// instead makes every waiting wave re-read kilobytes per poll, which competes
+// with the streaming traffic of the whole chip.  Once tile j has published, a
+// window of the 64 tiles j, j-1, ..., j-63 (lane l reads tile j - l) is summed
+// up to the nearest inclusive prefix; an unpublished tile inside the window
+// becomes the next tile waited on.  A tile that has published nothing after
+// spin_limit polls is no longer waited for: the wave computes its total itself
+// with reduce(t) -- every lane calls it, and it returns the tile's total in
+// every lane -- and goes on from the tile before it.  Every wait is therefore
+// bounded whatever order the work-groups run in, so tiles can be numbered by
 // work-group id.  reduce(t) may only read data that no work-group of the
 // launch writes.  Returns the exclusive prefix of `tile` in every lane.
-template <int kDepth, class Reduce>
-__device__ __forceinline__ uint32_t lb_lookback(const uint64_t* status, uint32_t tile, uint32_t epoch,
-                                                uint32_t spin_limit, Reduce&& reduce) {
+// One step over a window of status words: lane l holds w, the word of tile
+// j - l.  Adds the aggregates up to the nearest inclusive prefix (returns true,
+// done) or up to the nearest unpublished tile, which becomes the new j; with
+// all 64 aggregates, j moves 64 tiles back.
+template <class St>
+__device__ __forceinline__ bool lb_window_step(uint64_t w, const St& st, int64_t& j, typename St::sum_t& excl) {
+  typedef typename St::sum_t S;
   const uint32_t lane = lane_id();
-  uint32_t excl = 0;
+  const int64_t idx = j - (int64_t)lane;
+  const uint32_t f = idx >= 0 ? st.flag(w) : kLbInclusive;  // before tile 0: a zero prefix
+  const S v = idx >= 0 && f ? st.payload(w) : St::zero();
+  const uint64_t stop = __ballot(f == kLbInclusive);
+  const uint64_t gap = __ballot(f == 0);
+  const uint32_t first_stop = stop ? (uint32_t)__builtin_ctzll(stop) : 64u;
+  const uint32_t first_gap = gap ? (uint32_t)__builtin_ctzll(gap) : 64u;
+  if (first_gap < first_stop) {  // lanes below the gap hold aggregates
+    excl = St::add(excl, St::wave_total(lane < first_gap ? v : St::zero()));
+    j -= first_gap;
+    return false;
+  }
+  if (first_stop < 64u) {
+    excl = St::add(excl, St::wave_total(lane <= first_stop ? v : St::zero()));
+    return true;
+  }
+  excl = St::add(excl, St::wave_total(v));
+  j -= 64;
+  return false;
+}
+
+// Decoupled look-back with fallback by one whole wave; status[t] is tile t's
+// status word, read through the policy St (LbEpoch or LbPair).  The wave waits
+// on the nearest tile it has not yet accounted for, j, with one status read per
+// poll (every lane reads the same word, one request): polling a wide window
+// instead makes every waiting wave re-read kilobytes per poll, which competes
+// with the streaming traffic of the whole chip.  Once tile j has published, a
+// window of the 64 tiles j, j-1, ..., j-63 (lane l reads tile j - l) is summed
+// up to the nearest inclusive prefix; an unpublished tile inside the window
+// becomes the next tile waited on.  A tile that has published nothing after
+// spin_limit polls is no longer waited for: the wave computes its total itself
+// with reduce(t) -- every lane calls it, and it returns the tile's total in
+// every lane -- and goes on from the tile before it.  Every wait is therefore
+// bounded whatever order the work-groups run in, so tiles can be numbered by
+// work-group id.  reduce(t) may only read data that no work-group of the
+// launch writes.  With `window` the first window (tiles tile-1-lane) was read
+// earlier by the caller, so its latency overlapped other work.  Returns the
+// exclusive prefix of `tile` in every lane.
+template <class St, class Reduce>
+__device__ __forceinline__ typename St::sum_t lb_lookback_st(const uint64_t* status, uint32_t tile, const St& st,
+                                                             uint32_t spin_limit, Reduce&& reduce,
+                                                             const uint64_t* window = nullptr) {
+  typedef typename St::sum_t S;
+  const uint32_t lane = lane_id();
+  S excl = St::zero();
   int64_t j = (int64_t)tile - 1;
+  if (window && j >= 0 && lb_window_step(*window, st, j, excl)) return excl;
   uint32_t spins = 0;
   while (j >= 0) {
-    uint64_t w[kDepth];
-#pragma unroll
-    for (int k = 0; k < kDepth; ++k) {
-      const int64_t idx = j - (int64_t)(kDepth * lane + k);
-      w[k] = idx >= 0 ? lb_load(status + idx) : 0ull;
-    }
-    // This lane's run of predecessors, nearest first: state 2 = reaches an
-    // inclusive prefix (or the start), 1 = all aggregates, 0 = meets an
-    // unpublished tile, at position `gap`; sum = the values before it.
-    uint32_t state = 1, sum = 0, gap = 0;
-#pragma unroll
-    for (int k = 0; k < kDepth; ++k) {
-      if (state != 1) break;
-      const int64_t idx = j - (int64_t)(kDepth * lane + k);
-      if (idx < 0) {
-        state = 2;
-        break;
-      }
-      const uint32_t f = lb_flag(w[k], epoch);
-      if (f == 0) {
-        state = 0;
-        gap = (uint32_t)k;
-        break;
-      }
-      sum += (uint32_t)(w[k] >> 32);
-      if (f == kLbInclusive) state = 2;
-    }
-    const uint64_t inc = __ballot(state == 2);
-    const uint64_t stall = __ballot(state == 0);
-    const uint32_t stop = inc ? (uint32_t)__builtin_ctzll(inc) : 63u;
-    const uint64_t need = (stop == 63u) ? ~0ull : ((2ull << stop) - 1ull);
-    const uint64_t blocked = stall & need;
-    if (blocked) {
+    const uint64_t w0 = lb_load(status + j);
+    const uint32_t f0 = st.flag(w0);
+    if (f0 == 0) {
       if (++spins < spin_limit) {
-        __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_s_sleep(2);
         continue;
       }
-      // The nearest unpublished tile u: lanes below s saw aggregates only,
-      // lane s those before u.  Take u's total from its input.
-      const uint32_t s = (uint32_t)__builtin_ctzll(blocked);
-      const uint32_t gs = (uint32_t)__builtin_amdgcn_readlane((int)gap, (int)s);
-      excl += wave_sum(lane <= s ? sum : 0u);
-      const int64_t u = j - (int64_t)(kDepth * s + gs);
-      excl += reduce((uint32_t)u);
-      j = u - 1;
+      excl = St::add(excl, reduce((uint32_t)j));
+      j -= 1;
       spins = 0;
       continue;
     }
-    excl += wave_sum(lane <= stop ? sum : 0u);
-    if (inc) break;
-    j -= 64 * kDepth;
     spins = 0;
+    if (f0 == kLbInclusive) {
+      excl = St::add(excl, st.payload(w0));
+      break;
+    }
+    // Tile j holds an aggregate: sum the window below it.
+    const int64_t idx = j - (int64_t)lane;
+    const uint64_t w = (lane && idx >= 0) ? lb_load(status + idx) : w0;
+    if (lb_window_step(w, st, j, excl)) break;
   }
   return excl;
+}
+
+template <class Reduce>
+__device__ __forceinline__ uint32_t lb_lookback(const uint64_t* status, uint32_t tile, uint32_t epoch,
+                                                uint32_t spin_limit, Reduce&& reduce) {
+  return lb_lookback_st(status, tile, LbEpoch{epoch}, spin_limit, reduce);
 }
 
 // Reads the element count: the device-resident one when given.

@@ -51,11 +51,20 @@ __device__ __forceinline__ uint32_t request_of(const T* off, uint32_t lo, uint32
 // key = request << value_bits | value; a value with bits at or above
 // value_bits is flagged, and only its low value_bits bits enter the key, so the
 // request field of every key stays below nreq even in a rejected batch.
+// With req_bad, a value at or above 2^value_bits flags its own request
+// (req_bad[j] = 1) instead of the whole batch; either way the tag keeps only
+// the value bits, so the other requests' keys and results are untouched.
 struct TagOp {
   uint32_t value_bits;
+  uint32_t* req_bad;
   __device__ __forceinline__ uint32_t operator()(uint32_t v, uint32_t j, uint32_t& over) const {
     if (!tag_shift_ok(value_bits)) return v;
-    over |= v >> value_bits;
+    const uint32_t hi = v >> value_bits;
+    if (req_bad) {
+      if (hi) req_bad[j] = 1u;
+    } else {
+      over |= hi;
+    }
     return j << value_bits | (v & ((1u << value_bits) - 1u));
   }
 };
@@ -326,14 +335,19 @@ __global__ __launch_bounds__(kStartsBlock) void k_small_starts(const uint32_t* _
                                                                uint64_t* __restrict__ len_offsets,
                                                                uint64_t* __restrict__ len_words,
                                                                uint64_t* __restrict__ len_key_start,
-                                                               uint64_t* __restrict__ len_word_start) {
+                                                               uint64_t* __restrict__ len_word_start,
+                                                               uint32_t* __restrict__ req_bad) {
   __shared__ uint32_t s_a[kStartsBlock / 64], s_b[kStartsBlock / 64];
   uint32_t wbase = 0, dbase = 0, any_bad = 0;
   for (uint32_t c0 = 0; c0 < nreq; c0 += kStartsBlock) {
     const uint32_t j = c0 + threadIdx.x;
     const bool ok = j < nreq;
     const uint32_t wj = ok ? counts[3 * j] : 0u, dj = ok ? counts[3 * j + 1] : 0u;
-    any_bad |= ok ? counts[3 * j + 2] : 0u;
+    if (req_bad) {  // per-request rejection: the batch's lengths stand
+      if (ok) req_bad[j] = counts[3 * j + 2];
+    } else {
+      any_bad |= ok ? counts[3 * j + 2] : 0u;
+    }
     uint32_t wt, dt;
     const uint32_t wp = block_excl_scan<kStartsBlock>(wj, s_a, &wt);
     const uint32_t dp = block_excl_scan<kStartsBlock>(dj, s_b, &dt);
@@ -379,7 +393,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_place(const uint32_t* __r
 int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
                      uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
                      uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
-                     uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape, uint32_t max_req) {
+                     uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape, uint32_t max_req,
+                     uint32_t* req_bad) {
   if (!req_off || !offsets || !key_start || !word_start || !len_keys || !len_offsets || !len_words || !len_key_start ||
       !len_word_start)
     return env.fail(kErrArg, "wah_index_batch: null buffer");
@@ -408,7 +423,7 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
     env.prof_begin("batch_small_place");
     k_small_starts<<<dim3(1), dim3(kStartsBlock), 0, env.stream()>>>(counts, nreq, key_start, word_start, len_keys,
                                                                       len_offsets, len_words, len_key_start,
-                                                                      len_word_start);
+                                                                      len_word_start, req_bad);
     if ((rc = check_launch(env, "batch_small_starts launch"))) return rc;
     k_small_place<<<dim3(nreq), dim3(kSmallBlock), 0, env.stream()>>>(counts, req_off, wslot, kslot, oslot,
                                                                        key_start, word_start, keys, offsets, words);
@@ -425,11 +440,12 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
   if (!bad || !tkeys || !skeys || !srows || !g_off || !g_len) return env.fail(kErrOom, "wah_index_batch: scratch");
   int rc = launch_fill_u32(env, bad, 1, 0);
   if (rc) return rc;
+  if (req_bad && (rc = launch_fill_u32(env, req_bad, nreq, 0))) return rc;
   if (n) {
     const uint64_t blocks = (n + kKeyTile - 1) / kKeyTile;
     env.prof_begin("batch_keys");
     k_batch_map<TagOp><<<dim3((uint32_t)blocks), dim3(kKeyBlock), 0, env.stream()>>>(values, tkeys, nn, req_off, nreq,
-                                                                                    TagOp{value_bits}, bad);
+                                                                                    TagOp{value_bits, req_bad}, bad);
     env.prof_end("batch_keys");
     if ((rc = check_launch(env, "batch_keys launch"))) return rc;
     if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n, sort_shape))) return rc;

@@ -106,7 +106,7 @@ __device__ __forceinline__ void tile_lookback(const LbArgs& lb, uint32_t tile, u
       if (threadIdx.x == 0) lb_publish(lb.status, tile_total, lb.epoch, kLbInclusive);
     } else {
       if (threadIdx.x == 0) lb_publish(lb.status + tile, tile_total, lb.epoch, kLbAggregate);
-      prefix = lb_lookback<4>(lb.status, tile, lb.epoch, lb.spin_limit, reduce);
+      prefix = lb_lookback(lb.status, tile, lb.epoch, lb.spin_limit, reduce);
       if (threadIdx.x == 0) lb_publish(lb.status + tile, prefix + tile_total, lb.epoch, kLbInclusive);
     }
     if (threadIdx.x == 0) *s_prefix = prefix;

@@ -24,6 +24,8 @@
 // are given), later ones read the previous active pass's output, and the last
 // active pass writes the caller's buffers.
 #include <algorithm>
+#include <cstddef>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -59,7 +61,7 @@ constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 // The sort plan, written by the pass-0 count kernel.
 struct SortPlan {
   uint32_t active;               // bit p: pass p moves data
-  uint32_t pad;
+  uint32_t keys_or;              // OR of all keys
   uint64_t scan_len[kPasses];    // entries of pass p's table scan (0 when skipped)
 };
 static_assert(sizeof(SortPlan) <= kSortPlanBytes, "plan storage");
@@ -75,13 +77,17 @@ struct PassBuffers {
   uint32_t* rows_b;
 };
 
-struct PassIo {
-  const uint32_t* src_keys;
+// Source and destination of one pass; keys are uint32, or uint16 in the
+// narrow-key sort.
+template <class SK, class DK>
+struct PassIoT {
+  const SK* src_keys;
   const uint32_t* src_rows;
-  uint32_t* dst_keys;
+  DK* dst_keys;
   uint32_t* dst_rows;
   bool implicit_rows;
 };
+using PassIo = PassIoT<uint32_t, uint32_t>;
 
 // Source and destination of pass `pass` under the plan's active mask: the
 // last active pass writes buffer a, the one before it b, and so on.
@@ -145,42 +151,32 @@ constexpr int kUpWaves = kUpBlock / 64;
 // table[d * ntiles + tile] = number of keys of the tile with digit d.  The
 // exclusive scan of the table in this digit-major order is, entry by entry,
 // the position in the pass's output of the tile's first key with digit d.
-// All of a work-item's loads are issued before the first key is counted; the
-// pass-0 instance also writes the OR and the AND of the tile's keys.
-template <bool kFirst, int kTile>
-__global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, const SortPlan* __restrict__ plan,
-                                                            uint32_t* __restrict__ table, uint32_t* __restrict__ orand,
-                                                            uint32_t pass, uint32_t n, uint32_t ntiles) {
-  constexpr int kUpVecs = kTile / 4 / kUpBlock;  // 16-byte loads per work-item
+// All of a work-item's loads are issued before the first key is counted; with
+// kOrAnd the OR and the AND of the tile's keys are written too.
+template <int kTile, int kRounds, bool kOrAnd, class SK>
+__device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32_t shift, uint32_t tile, uint32_t n,
+                                             uint32_t ntiles, uint32_t* __restrict__ table,
+                                             uint32_t* __restrict__ orand) {
+  constexpr int kUpVecs = kTile / 4 / kUpBlock;  // 4-key loads per work-item
+  constexpr uintptr_t kAlign = 4 * sizeof(SK) - 1;
   __shared__ uint32_t s_hist[kUpWaves][kRadix];
   __shared__ uint32_t s_or[kUpWaves], s_and[kUpWaves];
   const uint32_t tid = threadIdx.x, w = tid / 64;
-  const uint32_t* keys = buf.keys_in;
-  if (!kFirst) {
-    const uint32_t active = plan->active;
-    if (!((active >> pass) & 1u)) return;  // uniform over the grid
-    keys = pass_io(buf, active, pass).src_keys;
-  }
-  const uint32_t shift = pass * kRadixBits;
-  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
   const uint32_t base = tile * kTile;
   const uint32_t len = min((uint32_t)kTile, n - base);
 
   // Key 4 (j * kUpBlock + tid) + c of the tile in k[j][c].
   uint32_t k[kUpVecs][4];
-  if (len == (uint32_t)kTile && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
+  if (len == (uint32_t)kTile && (reinterpret_cast<uintptr_t>(keys) & kAlign) == 0) {
 #pragma unroll
-    for (int j = 0; j < kUpVecs; ++j) {
-      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + base) + j * kUpBlock + tid);
-      k[j][0] = v.x, k[j][1] = v.y, k[j][2] = v.z, k[j][3] = v.w;
-    }
+    for (int j = 0; j < kUpVecs; ++j) load_key4(keys + base, (uint64_t)j * kUpBlock + tid, k[j]);
   } else {
 #pragma unroll
     for (int j = 0; j < kUpVecs; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const uint32_t e = 4 * (j * kUpBlock + tid) + c;
-        k[j][c] = e < len ? keys[base + e] : 0u;
+        k[j][c] = e < len ? (uint32_t)keys[base + e] : 0u;
       }
   }
   for (int i = tid; i < kUpWaves * kRadix; i += kUpBlock) (&s_hist[0][0])[i] = 0;
@@ -191,13 +187,13 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const bool valid = 4 * (j * kUpBlock + tid) + c < len;
-      lds_add_aggregated<kFirst ? 1 : 2>(s_hist[w], (k[j][c] >> shift) & (kRadix - 1), valid);
-      if (kFirst && valid) {
+      lds_add_aggregated<kRounds>(s_hist[w], (k[j][c] >> shift) & (kRadix - 1), valid);
+      if (kOrAnd && valid) {
         kor |= k[j][c];
         kand &= k[j][c];
       }
     }
-  if (kFirst) {
+  if (kOrAnd) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       kor |= (uint32_t)__shfl_xor((int)kor, off);
@@ -213,7 +209,7 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
 #pragma unroll
   for (int ww = 0; ww < kUpWaves; ++ww) c += s_hist[ww][tid];
   table[(uint64_t)tid * ntiles + tile] = c;
-  if (kFirst && tid == 0) {
+  if (kOrAnd && tid == 0) {
     uint32_t o = 0, a = ~0u;
 #pragma unroll
     for (int ww = 0; ww < kUpWaves; ++ww) {
@@ -223,6 +219,32 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
     orand[2 * tile] = o;
     orand[2 * tile + 1] = a;
   }
+}
+
+// Plan-driven upsweep of pass `pass`; the pass-0 instance also writes the OR
+// and the AND of the tile's keys for the plan.
+template <bool kFirst, int kTile>
+__global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, const SortPlan* __restrict__ plan,
+                                                            uint32_t* __restrict__ table, uint32_t* __restrict__ orand,
+                                                            uint32_t pass, uint32_t n, uint32_t ntiles) {
+  const uint32_t* keys = buf.keys_in;
+  if (!kFirst) {
+    const uint32_t active = plan->active;
+    if (!((active >> pass) & 1u)) return;  // uniform over the grid
+    keys = pass_io(buf, active, pass).src_keys;
+  }
+  upsweep_tile<kTile, kFirst ? 1 : 2, kFirst>(keys, pass * kRadixBits, xcd_tile(blockIdx.x, ntiles), n, ntiles,
+                                              table, orand);
+}
+
+// Upsweep of a fixed pass (no plan) over uint32 or uint16 keys.  Work-group 0
+// of the first pass clears *reject.
+template <int kTile, int kRounds, class SK>
+__global__ __launch_bounds__(kUpBlock) void k_radix_count(const SK* __restrict__ keys, uint32_t* __restrict__ table,
+                                                          uint32_t shift, uint32_t n, uint32_t ntiles,
+                                                          uint32_t* __restrict__ reject) {
+  if (reject && blockIdx.x == 0 && threadIdx.x == 0) *reject = 0u;
+  upsweep_tile<kTile, kRounds, false>(keys, shift, xcd_tile(blockIdx.x, ntiles), n, ntiles, table, nullptr);
 }
 
 // The sort plan from the OR and the AND of every tile's keys: a pass moves
@@ -259,6 +281,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_radix_plan(const uint32_t* __res
       if ((diff >> (p * kRadixBits)) & (kRadix - 1)) act |= 1u << p;
     if (act == 0) act = 1u << (kPasses - 1);  // all keys equal: one pass still moves them
     plan->active = act;
+    plan->keys_or = o;
     for (int p = 0; p < kPasses; ++p) plan->scan_len[p] = ((act >> p) & 1u) ? (uint64_t)ntiles * kRadix : 0u;
   }
 }
@@ -304,8 +327,8 @@ struct ScatterLds {
 
 // The tile's keys and rows: wave w owns 64*kItems consecutive elements, lane
 // l the elements w*64*kItems + i*64 + l.
-template <int kBlock, int kItems>
-__device__ __forceinline__ void scatter_load(const PassIo& io, uint32_t base, uint32_t tile_n,
+template <int kBlock, int kItems, class IO>
+__device__ __forceinline__ void scatter_load(const IO& io, uint32_t base, uint32_t tile_n,
                                              uint32_t (&key)[kItems], uint32_t (&row)[kItems]) {
   constexpr int kTile = kBlock * kItems;
   const uint32_t w = threadIdx.x / 64, lane = lane_id();
@@ -327,7 +350,7 @@ __device__ __forceinline__ void scatter_load(const PassIo& io, uint32_t base, ui
       const uint32_t local = wbase + i * 64 + lane;
       const uint32_t g = base + local;
       const bool valid = local < tile_n;
-      key[i] = valid ? io.src_keys[g] : 0u;
+      key[i] = valid ? (uint32_t)io.src_keys[g] : 0u;
       row[i] = valid ? (io.implicit_rows ? g : io.src_rows[g]) : 0u;
     }
   }
@@ -335,11 +358,13 @@ __device__ __forceinline__ void scatter_load(const PassIo& io, uint32_t base, ui
 
 // Ranks, reorders and writes one tile whose keys and rows are in registers
 // (their loads may still be in flight); dstart = the table entry of digit
-// threadIdx.x for this tile.  Starts and ends with a barrier.
-template <int kBlock, int kItems>
-__device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, const PassIo& io, uint32_t shift,
+// threadIdx.x for this tile.  Starts and ends with a barrier.  With kCheck a
+// key at or above 2^check_shift sets *reject to 1.
+template <int kBlock, int kItems, bool kCheck = false, class IO>
+__device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, const IO& io, uint32_t shift,
                                              uint32_t tile_n, uint32_t dstart, const uint32_t (&key)[kItems],
-                                             const uint32_t (&row)[kItems]) {
+                                             const uint32_t (&row)[kItems], uint32_t check_shift = 32,
+                                             uint32_t* reject = nullptr) {
   constexpr int kWaves = kBlock / 64;
   const uint32_t tid = threadIdx.x, w = tid / 64, lane = lane_id();
   const uint32_t wbase = w * 64 * kItems;
@@ -370,6 +395,13 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
       r = old + below;
     }
     rank[i] = r;
+  }
+  if (kCheck) {
+    uint32_t over = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i)
+      over |= (wbase + i * 64 + lane < tile_n) ? key[i] >> check_shift : 0u;
+    if (__ballot(over != 0u) && lane == 0) *reject = 1u;
   }
   __syncthreads();
 
@@ -410,7 +442,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
       const uint2 v = L.kr[p];
       const uint32_t k = v.x;
       const uint32_t g = L.dbase[(k >> shift) & (kRadix - 1)] + p;
-      io.dst_keys[g] = k;
+      io.dst_keys[g] = (std::remove_pointer_t<decltype(io.dst_keys)>)k;
       io.dst_rows[g] = v.y;
     }
   }
@@ -435,6 +467,24 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   uint32_t key[kItems], row[kItems];
   scatter_load<kBlock, kItems>(io, base, tile_n, key, row);
   scatter_tile<kBlock, kItems>(L, io, pass * kRadixBits, tile_n, dstart, key, row);
+}
+
+// Scatter of a fixed pass (no plan): keys uint32 or uint16 on either side.
+// With kCheck (the first pass of the narrow-key sort) a key at or above
+// 2^check_shift sets *reject.
+template <int kBlock, int kItems, bool kCheck, class SK, class DK>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter_fixed(PassIoT<SK, DK> io, const uint32_t* __restrict__ table,
+                                                                uint32_t shift, uint32_t n, uint32_t ntiles,
+                                                                uint32_t check_shift, uint32_t* __restrict__ reject) {
+  constexpr int kTile = kBlock * kItems;
+  __shared__ ScatterLds<kBlock, kItems> L;
+  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+  const uint32_t base = tile * kTile;
+  const uint32_t tile_n = min((uint32_t)kTile, n - base);
+  const uint32_t dstart = threadIdx.x < kRadix ? table[(uint64_t)threadIdx.x * ntiles + tile] : 0u;
+  uint32_t key[kItems], row[kItems];
+  scatter_load<kBlock, kItems>(io, base, tile_n, key, row);
+  scatter_tile<kBlock, kItems, kCheck>(L, io, shift, tile_n, dstart, key, row, check_shift, reject);
 }
 
 }  // namespace
@@ -501,9 +551,85 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
   return kOk;
 }
 
+// The narrow-key sort: keys below 2^value_bits, value_bits <= 16, rows
+// 0..n-1.  ceil(value_bits / 8) fixed passes (no plan, no skipped launches);
+// from the first pass on the keys are stored as uint16 (6 bytes per pair
+// instead of 8).  The first pass flags a key at or above 2^value_bits in
+// *reject (cleared by its upsweep); the sort's output is then unspecified.
+template <int kBlock, int kItems>
+int sort16_with_shape(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t* srows, uint64_t n,
+                      uint32_t value_bits, uint32_t* reject) {
+  constexpr int kTile = kBlock * kItems;
+  const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
+  const uint32_t nn = (uint32_t)n;
+  const uint32_t passes = (value_bits + kRadixBits - 1) / kRadixBits;
+  uint16_t* kb = nullptr;
+  uint32_t* rb = nullptr;
+  if (passes > 1) {
+    kb = static_cast<uint16_t*>(env.scratch(n * 2));
+    rb = static_cast<uint32_t*>(env.scratch(n * 4));
+    if (!kb || !rb) return env.fail(kErrOom, "radix_sort16: scratch buffers");
+  }
+  uint32_t* table = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * kRadix * 4));
+  uint32_t* offs = static_cast<uint32_t*>(env.scratch((uint64_t)ntiles * kRadix * 4));
+  if (!table || !offs) return env.fail(kErrOom, "radix_sort16: digit tables");
+  const uint64_t tlen = (uint64_t)ntiles * kRadix;
+  int rc;
+  // pass 0: uint32 values in, uint16 keys out
+  env.prof_begin("radix_upsweep0");
+  k_radix_count<kTile, 1, uint32_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(keys, table, 0, nn, ntiles,
+                                                                                       reject);
+  env.prof_end("radix_upsweep0");
+  if ((rc = check_launch(env, "radix_count launch"))) return rc;
+  if ((rc = launch_exclusive_scan(env, table, offs, tlen, nullptr))) return rc;
+  PassIoT<uint32_t, uint16_t> io0{keys, nullptr, passes > 1 ? kb : skeys, passes > 1 ? rb : srows, true};
+  env.prof_begin("radix_scatter");
+  k_radix_scatter_fixed<kBlock, kItems, true><<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(
+      io0, offs, 0u, nn, ntiles, value_bits, reject);
+  env.prof_end("radix_scatter");
+  if ((rc = check_launch(env, "radix_scatter launch"))) return rc;
+  if (passes == 1) return kOk;
+  // pass 1: uint16 keys in and out
+  env.prof_begin("radix_upsweep");
+  k_radix_count<kTile, 2, uint16_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(kb, table, kRadixBits, nn,
+                                                                                       ntiles, nullptr);
+  env.prof_end("radix_upsweep");
+  if ((rc = check_launch(env, "radix_count launch"))) return rc;
+  if ((rc = launch_exclusive_scan(env, table, offs, tlen, nullptr))) return rc;
+  PassIoT<uint16_t, uint16_t> io1{kb, rb, skeys, srows, false};
+  env.prof_begin("radix_scatter");
+  k_radix_scatter_fixed<kBlock, kItems, false><<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(
+      io1, offs, kRadixBits, nn, ntiles, 32u, nullptr);
+  env.prof_end("radix_scatter");
+  return check_launch(env, "radix_scatter launch");
+}
+
 }  // namespace
 
 int sort_shape_count() { return kNumShapes; }
+
+const uint32_t* sort_plan_keys_or(Env& env) {
+  return reinterpret_cast<const uint32_t*>(static_cast<const char*>(env.arena()->plan) + offsetof(SortPlan, keys_or));
+}
+
+int launch_radix_sort_rows16(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t* srows, uint64_t n,
+                             uint32_t value_bits, uint32_t* reject, int shape) {
+  if (!reject) return env.fail(kErrArg, "radix_sort16: null reject flag");
+  if (value_bits == 0 || value_bits > 16) return env.fail(kErrArg, "radix_sort16: value_bits must be 1..16");
+  if (n == 0) return launch_fill_u32(env, reject, 1, 0);
+  if (!keys || !skeys || !srows) return env.fail(kErrArg, "radix_sort16: null buffer");
+  if (n >= (1ull << 31)) return env.fail(kErrArg, "radix_sort16: n must be below 2^31");
+  switch (shape) {
+    case 0:
+      return sort16_with_shape<kShapes[0].block, kShapes[0].items>(env, keys, skeys, srows, n, value_bits, reject);
+    case 1:
+      return sort16_with_shape<kShapes[1].block, kShapes[1].items>(env, keys, skeys, srows, n, value_bits, reject);
+    case 2:
+      return sort16_with_shape<kShapes[2].block, kShapes[2].items>(env, keys, skeys, srows, n, value_bits, reject);
+    default:
+      return env.fail(kErrArg, "radix_sort16: unknown tile shape");
+  }
+}
 
 int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows, uint32_t* skeys,
                             uint32_t* srows, uint64_t n, int shape) {

@@ -15,19 +15,19 @@
 //   grp(e) = seg(e) or chunk(e) != chunk(e - 1)   (e starts a group),
 //   gap(e) = grp(e) and the fill before e is non-zero (chunk(e) != 0 for a
 //            value's first group, chunk(e) != chunk(e - 1) + 1 otherwise),
-// and e emits grp(e) + gap(e) words and seg(e) values.  So the encoding is a
-// reduce-then-scan over tiles of kEncTile pairs, with no wait between tiles:
-//   k_wah_count    counts each tile's words and values,
-//   k_wah_groups   scans the tile counts inside groups of 1024 tiles and
-//                  writes the group totals,
-//   k_wah_write    adds the totals of the earlier groups to its tile's offset,
-//                  re-derives the tile's groups and writes its words and
-//                  lookup-table entries; the last tile writes W, D, offsets[D]
-//                  and the three output lengths.
-// A group spans at most 31 sorted elements (rows are distinct), so the write
-// kernel finishes a group that runs past its tile by reading at most 30
-// elements ahead (kLook).  Words are staged in LDS (over the staged input,
-// which is dead by then) and written out by consecutive work-items.
+// and e emits grp(e) + gap(e) words and seg(e) values.  So the encoding is one
+// single-pass kernel over tiles of kEncTile pairs, k_wah_write: each tile
+// counts its words and values, publishes both counts, finds the counts of all
+// earlier tiles by decoupled look-back (one status chain for words, one for
+// values; a silent predecessor is counted from its input by the waiting wave)
+// and writes its words and lookup-table entries; the last tile writes W, D,
+// offsets[D] and the three output lengths.  The sorted pairs are read once.
+// A group spans at most 31 sorted elements (rows are distinct), so a tile
+// finishes a group that runs past its end by reading at most 30 elements
+// ahead (kLook).  Words are staged in LDS (over the staged input, which is
+// dead by then) and written out by consecutive work-items.  Sorted keys are
+// uint32, or uint16 when every value is below 2^16 (the index build's
+// narrow-key sort).
 #include "common.hpp"
 
 namespace ka {
@@ -70,17 +70,16 @@ __device__ __forceinline__ void element_counts(uint32_t k, uint32_t r, uint32_t 
 
 // Tile elements in registers: slot (j, c) of work-item tid holds element
 // b + 4 (j * kEncBlock + tid) + c (0 beyond len).
-template <bool kVec>
-__device__ __forceinline__ void load_pairs(const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ srows,
+template <bool kVec, class KeyT>
+__device__ __forceinline__ void load_pairs(const KeyT* __restrict__ skeys, const uint32_t* __restrict__ srows,
                                            uint32_t b, uint32_t len, uint32_t tid, uint32_t (&vk)[kVecs][4],
                                            uint32_t (&vr)[kVecs][4]) {
   if (kVec && len == (uint32_t)kEncTile) {
 #pragma unroll
     for (int j = 0; j < kVecs; ++j) {
       const uint32_t q = j * kEncBlock + tid;
-      const u32x4 a = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(skeys + b) + q);
+      load_key4(skeys + b, q, vk[j]);
       const u32x4 c = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(srows + b) + q);
-      vk[j][0] = a.x, vk[j][1] = a.y, vk[j][2] = a.z, vk[j][3] = a.w;
       vr[j][0] = c.x, vr[j][1] = c.y, vr[j][2] = c.z, vr[j][3] = c.w;
     }
   } else {
@@ -89,15 +88,12 @@ __device__ __forceinline__ void load_pairs(const uint32_t* __restrict__ skeys, c
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const uint32_t i = 4 * (j * kEncBlock + tid) + c;
-        vk[j][c] = i < len ? skeys[b + i] : 0u;
+        vk[j][c] = i < len ? (uint32_t)skeys[b + i] : 0u;
         vr[j][c] = i < len ? srows[b + i] : 0u;
       }
   }
 }
 
-// ---------------------------------------------------------------------------------
-// count: words and values emitted by each tile
-// ---------------------------------------------------------------------------------
 // Rows of a batch of requests sorted together are batch positions; the row
 // inside the request is the position minus the request's first position,
 // found from the request id in the key's high bits (key >> req_shift).
@@ -109,91 +105,32 @@ struct BatchRows {
   }
 };
 
-template <bool kVec>
-__global__ __launch_bounds__(kEncBlock) void k_wah_count(const uint32_t* __restrict__ skeys,
-                                                         const uint32_t* __restrict__ srows, uint32_t n,
-                                                         uint32_t* __restrict__ tile_words,
-                                                         uint32_t* __restrict__ tile_values, BatchRows br) {
-  __shared__ uint32_t s_w[kEncBlock / 64], s_s[kEncBlock / 64];
-  const uint32_t tid = threadIdx.x, tile = blockIdx.x;
-  const uint32_t b = tile * kEncTile;
-  const uint32_t len = min((uint32_t)kEncTile, n - b);
-  uint32_t vk[kVecs][4], vr[kVecs][4], pk[kVecs], pr[kVecs];
-  load_pairs<kVec>(skeys, srows, b, len, tid, vk, vr);
-  if (br.req_base) {
-#pragma unroll
-    for (int j = 0; j < kVecs; ++j)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) vr[j][c] = br.local(vk[j][c], vr[j][c]);
-  }
-  // The predecessor of each vector's first element is the last element of the
-  // lane before (a wave shuffle); lane 0 reads it from memory (it belongs to
-  // another wave's vector or to the previous tile, and is served from cache).
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (int j = 0; j < kVecs; ++j) {
-    const uint32_t i = 4 * (j * kEncBlock + tid);
-    pk[j] = (uint32_t)__shfl_up((int)vk[j][3], 1);
-    pr[j] = (uint32_t)__shfl_up((int)vr[j][3], 1);
-    if (lane == 0 && b + i > 0 && i < len) {
-      pk[j] = skeys[b + i - 1];
-      pr[j] = br.local(pk[j], srows[b + i - 1]);
-    }
-  }
+// Words and values that tile u emits, counted from its input by one wave --
+// the look-back's fallback for a predecessor that has not published yet.  Lane
+// l takes 64 consecutive elements.
+template <class KeyT>
+__device__ LbPairSum wave_tile_count(const KeyT* __restrict__ skeys, const uint32_t* __restrict__ srows, uint32_t n,
+                                     uint32_t u, BatchRows br) {
+  constexpr uint32_t kPer = kEncTile / 64;
+  const uint32_t b = u * kEncTile;
+  const uint32_t end = min(b + (uint32_t)kEncTile, n);
+  const uint32_t e0 = b + lane_id() * kPer;
   uint32_t nw = 0, ns = 0;
-#pragma unroll
-  for (int j = 0; j < kVecs; ++j)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const uint32_t i = 4 * (j * kEncBlock + tid) + c;
-      if (i < len)
-        element_counts(vk[j][c], vr[j][c], c ? vk[j][c - 1] : pk[j], c ? vr[j][c - 1] : pr[j], b + i == 0, nw,
-                       ns);
+  if (e0 < end) {
+    uint32_t kp = 0, rp = 0;
+    if (e0 > 0) {
+      kp = skeys[e0 - 1];
+      rp = br.local(kp, srows[e0 - 1]);
     }
-  nw = wave_sum(nw);
-  ns = wave_sum(ns);
-  if (lane_id() == 0) {
-    s_w[tid / 64] = nw;
-    s_s[tid / 64] = ns;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t w = 0, s = 0;
-#pragma unroll
-    for (int i = 0; i < kEncBlock / 64; ++i) {
-      w += s_w[i];
-      s += s_s[i];
+    const uint32_t e1 = min(e0 + kPer, end);
+    for (uint32_t e = e0; e < e1; ++e) {
+      const uint32_t k = skeys[e], r = br.local(k, srows[e]);
+      element_counts(k, r, kp, rp, e == 0, nw, ns);
+      kp = k;
+      rp = r;
     }
-    tile_words[tile] = w;
-    tile_values[tile] = s;
   }
-}
-
-// ---------------------------------------------------------------------------------
-// groups: tile counts -> offsets inside groups of kGroupTiles tiles, group totals
-// ---------------------------------------------------------------------------------
-constexpr int kGroupTiles = 1024;  // one work-item per tile of the group
-
-// The write kernel adds the totals of the groups before its own (at most
-// ntiles / kGroupTiles values), so no single work-group scans every tile.
-__global__ __launch_bounds__(kGroupTiles) void k_wah_groups(uint32_t* __restrict__ tile_words,
-                                                            uint32_t* __restrict__ tile_values, uint32_t ntiles,
-                                                            uint32_t* __restrict__ group_words,
-                                                            uint32_t* __restrict__ group_values) {
-  __shared__ uint32_t s_a[kGroupTiles / 64], s_b[kGroupTiles / 64];
-  const uint32_t t = blockIdx.x * kGroupTiles + threadIdx.x;
-  const uint32_t w = t < ntiles ? tile_words[t] : 0u, v = t < ntiles ? tile_values[t] : 0u;
-  uint32_t tw, tv;
-  const uint32_t pw = block_excl_scan<kGroupTiles>(w, s_a, &tw);
-  const uint32_t pv = block_excl_scan<kGroupTiles>(v, s_b, &tv);
-  if (t < ntiles) {
-    tile_words[t] = pw;
-    tile_values[t] = pv;
-  }
-  if (threadIdx.x == 0) {
-    group_words[blockIdx.x] = tw;
-    group_values[blockIdx.x] = tv;
-  }
+  return {wave_sum(nw), wave_sum(ns)};
 }
 
 // An empty input: D = 0, W = 0, offsets = [0].
@@ -207,19 +144,27 @@ __global__ void k_wah_empty(uint32_t* __restrict__ out_offsets, uint64_t* __rest
   }
 }
 
+// Rejection of the whole input, decided by earlier kernels: the encoding is
+// void when (*flag >> shift) != 0 (a value at or above 2^shift), and every
+// output length is then 0.
+struct Reject {
+  const uint32_t* flag;  // null: never
+  uint32_t shift;
+  __device__ __forceinline__ bool operator()() const { return flag && shift < 32 && (*flag >> shift) != 0u; }
+};
+
 // ---------------------------------------------------------------------------------
 // write: literals, fills and lookup-table entries of one tile
 // ---------------------------------------------------------------------------------
-template <bool kVec>
-__global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const uint32_t* __restrict__ skeys,
+// status[tile]: the tile's (words, values) look-back word, zeroed before the
+// launch.
+template <bool kVec, class KeyT>
+__global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const KeyT* __restrict__ skeys,
                                                          const uint32_t* __restrict__ srows, uint32_t n,
-                                                         const uint32_t* __restrict__ tile_words,
-                                                         const uint32_t* __restrict__ tile_values,
-                                                         const uint32_t* __restrict__ group_words,
-                                                         const uint32_t* __restrict__ group_values,
+                                                         uint64_t* __restrict__ status, uint32_t spin_limit,
                                                          uint32_t* __restrict__ out_keys,
                                                          uint32_t* __restrict__ out_offsets,
-                                                         uint32_t* __restrict__ out_words, BatchRows br,
+                                                         uint32_t* __restrict__ out_words, BatchRows br, Reject rej,
                                                          uint64_t* __restrict__ len_keys,
                                                          uint64_t* __restrict__ len_offsets,
                                                          uint64_t* __restrict__ len_words) {
@@ -247,25 +192,8 @@ __global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const uint32_t* __re
     uint32_t xk = 0, xr = 0;
     if (extra) {
       const bool ok = g >= 0 && g < (int64_t)n;
-      xk = ok ? skeys[g] : 0u;
+      xk = ok ? (uint32_t)skeys[g] : 0u;
       xr = ok ? br.local(xk, srows[g]) : 0u;
-    }
-    // This tile's first word and value: its offset inside its group plus the
-    // totals of the groups before (wave 0, once the tile's loads are issued;
-    // read after the next barrier).
-    if (tid < 64) {
-      const uint32_t grp = tile / kGroupTiles;
-      uint32_t gw = 0, gv = 0;
-      for (uint32_t j = tid; j < grp; j += 64) {
-        gw += group_words[j];
-        gv += group_values[j];
-      }
-      gw = wave_sum(gw);
-      gv = wave_sum(gv);
-      if (tid == 0) {
-        s_pre[0] = gw + tile_words[tile];
-        s_pre[1] = gv + tile_values[tile];
-      }
     }
 #pragma unroll
     for (int j = 0; j < kVecs; ++j) {
@@ -289,7 +217,6 @@ __global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const uint32_t* __re
     }
   }
   __syncthreads();
-  const uint32_t wpre = s_pre[0], dpre = s_pre[1];
 
   // ---- this work-item's kEncItems consecutive elements, in registers: key, the
   // row's group (row / 31) and its bit inside the group; elements past the
@@ -337,7 +264,12 @@ __global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const uint32_t* __re
   // (a tile emits at most 2*kEncTile words and kEncTile values).
   uint32_t packed_total;
   const uint32_t packed_pre = block_excl_scan<kEncBlock>((ns << 16) | nw, s_scan, &packed_total);
-  const uint32_t tile_nw = packed_total & 0xFFFFu;
+  const uint32_t tile_nw = packed_total & 0xFFFFu, tile_ns = packed_total >> 16;
+
+  // ---- publish the tile's counts at once: successors find them while this
+  // tile builds its words --------------------------------------------------------------
+  if (tid == 0)
+    lb_publish_raw(status + tile, lb_pack_pair(tile_nw, tile_ns, tile == 0 ? kLbInclusive : kLbAggregate));
 
   // ---- the last group may run past this work-item's elements (at most 30
   // further elements, into the look-ahead): collect its bits now -------------------
@@ -354,11 +286,11 @@ __global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const uint32_t* __re
   }
   __syncthreads();  // the staged input is dead from here on
 
-  // ---- one backward sweep: literals (OR of the group's bits), fills and lookup-table
-  // entries, placed from the end of this work-item's words --------------------------
+  // ---- one backward sweep: literals (OR of the group's bits) and fills, placed in
+  // LDS from the end of this work-item's words --------------------------------------
+  const uint32_t wbeg = packed_pre & 0xFFFFu;  // this work-item's first word in the tile
   {
-    uint32_t w = (packed_pre & 0xFFFFu) + nw;  // one past this work-item's last word
-    const uint32_t ls = packed_pre >> 16;      // tile-local index of its first value
+    uint32_t w = wbeg + nw;  // one past this work-item's last word
     uint32_t acc = tail;
 #pragma unroll
     for (int i = kEncItems - 1; i >= 0; --i) {
@@ -366,78 +298,112 @@ __global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const uint32_t* __re
       if ((heads >> i) & 1u) {
         s_words[--w] = acc & ~kFill;  // drops the bit 31 of elements past the tile's end
         acc = 0;
-        const bool seg = (segs >> i) & 1u;
         if ((gaps >> i) & 1u) {
           const uint32_t cp = i ? grp_of[i - 1] : cprev;
-          s_words[--w] = kFill | (seg ? grp_of[i] : grp_of[i] - cp - 1u);
-        }
-        if (seg) {
-          const uint32_t d = dpre + ls + (uint32_t)__popc(segs & ((1u << i) - 1u));
-          out_keys[d] = key[i];
-          out_offsets[d] = wpre + w;
+          s_words[--w] = kFill | (((segs >> i) & 1u) ? grp_of[i] : grp_of[i] - cp - 1u);
         }
       }
     }
   }
-  __syncthreads();
-  for (uint32_t i = tid; i < tile_nw; i += kEncBlock) out_words[wpre + i] = s_words[i];
-  if (base + tile_n == n && tid == 0) {  // the last tile: totals and lengths
-    const uint32_t D = dpre + (packed_total >> 16), W = wpre + tile_nw;
-    out_offsets[D] = W;
-    *len_keys = D;
-    *len_offsets = (uint64_t)D + 1;
-    *len_words = W;
+
+  // ---- the tile's first word and value: look back over the earlier tiles (wave 0)
+  if (tid < 64) {
+    LbPairSum pre{0u, 0u};
+    if (tile > 0) {
+      pre = lb_lookback_st(status, tile, LbPair{}, spin_limit,
+                           [&](uint32_t u) { return wave_tile_count(skeys, srows, n, u, br); });
+      if (tid == 0) lb_publish_raw(status + tile, lb_pack_pair(pre.a + tile_nw, pre.b + tile_ns, kLbInclusive));
+    }
+    if (tid == 0) {
+      s_pre[0] = pre.a;
+      s_pre[1] = pre.b;
+    }
   }
+  __syncthreads();
+  const uint32_t wpre = s_pre[0], dpre = s_pre[1];
+
+  // ---- words, then the lookup-table entries of the values starting here ----------------
+  for (uint32_t i = tid; i < tile_nw; i += kEncBlock) out_words[wpre + i] = s_words[i];
+  if (segs) {
+    const uint32_t ls = packed_pre >> 16;  // tile-local index of this work-item's first value
+#pragma unroll
+    for (int i = 0; i < kEncItems; ++i) {
+      if ((segs >> i) & 1u) {
+        const uint32_t below = (1u << i) - 1u;
+        const uint32_t d = dpre + ls + (uint32_t)__popc(segs & below);
+        out_keys[d] = key[i];
+        out_offsets[d] = wpre + wbeg + (uint32_t)__popc(heads & below) + (uint32_t)__popc(gaps & below);
+      }
+    }
+  }
+  if (base + tile_n == n && tid == 0) {  // the last tile: totals and lengths
+    const uint32_t D = dpre + tile_ns, W = wpre + tile_nw;
+    out_offsets[D] = W;
+    const bool void_ = rej();
+    *len_keys = void_ ? 0u : D;
+    *len_offsets = void_ ? 0u : (uint64_t)D + 1;
+    *len_words = void_ ? 0u : W;
+  }
+}
+
+// Zeroes the encoder's status words (ntiles of them) before the write kernel.
+__global__ void k_wah_clear(uint64_t* __restrict__ status, uint32_t ntiles) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ntiles) status[i] = 0ull;
+}
+
+template <class KeyT>
+int encode_impl(Env& env, const KeyT* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys, uint32_t* offsets,
+                uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets, uint64_t* d_len_words,
+                const uint32_t* req_base, uint32_t req_shift, const uint32_t* reject_flag, uint32_t reject_shift) {
+  if (!offsets || !d_len_keys || !d_len_offsets || !d_len_words)
+    return env.fail(kErrArg, "wah_encode_sorted: null output");
+  if (n >= (1ull << 30)) return env.fail(kErrArg, "wah_encode_sorted: n must be below 2^30");
+  if (n && (!skeys || !srows || !keys || !words)) return env.fail(kErrArg, "wah_encode_sorted: null buffer");
+  const uint32_t ntiles = (uint32_t)((n + kEncTile - 1) / kEncTile);
+  if (!ntiles) {
+    k_wah_empty<<<dim3(1), dim3(64), 0, env.stream()>>>(offsets, d_len_keys, d_len_offsets, d_len_words);
+    return check_launch(env, "wah_empty launch");
+  }
+  // The (words, values) chain has no epoch: its own status words, zeroed here.
+  uint64_t* status = static_cast<uint64_t*>(env.scratch(8ull * ntiles));
+  if (!status) return env.fail(kErrOom, "wah_encode_sorted: look-back status words");
+  int rc;
+  k_wah_clear<<<dim3((ntiles + 255) / 256), dim3(256), 0, env.stream()>>>(status, ntiles);
+  if ((rc = check_launch(env, "wah_clear launch"))) return rc;
+  constexpr uintptr_t kKeyAlign = sizeof(KeyT) == 4 ? 15u : 7u;
+  const bool vec = ((reinterpret_cast<uintptr_t>(skeys) & kKeyAlign) | (reinterpret_cast<uintptr_t>(srows) & 15u)) == 0;
+  const BatchRows br{req_base, req_shift};
+  const Reject rej{reject_flag, reject_shift};
+  const uint32_t nn = (uint32_t)n;
+  env.prof_begin("wah_write");
+  if (vec)
+    k_wah_write<true, KeyT><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(
+        skeys, srows, nn, status, env.spin_limit(), keys, offsets, words, br, rej, d_len_keys, d_len_offsets,
+        d_len_words);
+  else
+    k_wah_write<false, KeyT><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(
+        skeys, srows, nn, status, env.spin_limit(), keys, offsets, words, br, rej, d_len_keys, d_len_offsets,
+        d_len_words);
+  env.prof_end("wah_write");
+  return check_launch(env, "wah_write launch");
 }
 
 }  // namespace
 
 int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                       uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
-                      uint64_t* d_len_words, const uint32_t* req_base, uint32_t req_shift) {
-  if (!offsets || !d_len_keys || !d_len_offsets || !d_len_words)
-    return env.fail(kErrArg, "wah_encode_sorted: null output");
-  if (n >= (1ull << 30)) return env.fail(kErrArg, "wah_encode_sorted: n must be below 2^30");
-  if (n && (!skeys || !srows || !keys || !words)) return env.fail(kErrArg, "wah_encode_sorted: null buffer");
-  const uint32_t ntiles = (uint32_t)((n + kEncTile - 1) / kEncTile);
-  const uint32_t nn = (uint32_t)n;
-  uint32_t* tw = static_cast<uint32_t*>(env.scratch(4ull * (ntiles ? ntiles : 1)));
-  uint32_t* tv = static_cast<uint32_t*>(env.scratch(4ull * (ntiles ? ntiles : 1)));
-  const uint64_t ng = (ntiles + kGroupTiles - 1) / kGroupTiles;
-  uint32_t* gw = static_cast<uint32_t*>(env.scratch(4ull * (ng ? ng : 1)));
-  uint32_t* gv = static_cast<uint32_t*>(env.scratch(4ull * (ng ? ng : 1)));
-  if (!tw || !tv || !gw || !gv) return env.fail(kErrOom, "wah_encode_sorted: tile counts");
-  const bool vec = ((reinterpret_cast<uintptr_t>(skeys) | reinterpret_cast<uintptr_t>(srows)) & 15u) == 0;
-  const BatchRows br{req_base, req_shift};
-  int rc;
-  if (ntiles) {
-    env.prof_begin("wah_count");
-    if (vec)
-      k_wah_count<true><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv, br);
-    else
-      k_wah_count<false><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(skeys, srows, nn, tw, tv, br);
-    env.prof_end("wah_count");
-    if ((rc = check_launch(env, "wah_count launch"))) return rc;
-  }
-  if (!ntiles) {
-    k_wah_empty<<<dim3(1), dim3(64), 0, env.stream()>>>(offsets, d_len_keys, d_len_offsets, d_len_words);
-    return check_launch(env, "wah_empty launch");
-  }
-  const uint32_t ngroups = (ntiles + kGroupTiles - 1) / kGroupTiles;
-  env.prof_begin("wah_offsets");
-  k_wah_groups<<<dim3(ngroups), dim3(kGroupTiles), 0, env.stream()>>>(tw, tv, ntiles, gw, gv);
-  env.prof_end("wah_offsets");
-  if ((rc = check_launch(env, "wah_groups launch"))) return rc;
-  env.prof_begin("wah_write");
-  if (vec)
-    k_wah_write<true><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(
-        skeys, srows, nn, tw, tv, gw, gv, keys, offsets, words, br, d_len_keys, d_len_offsets, d_len_words);
-  else
-    k_wah_write<false><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(
-        skeys, srows, nn, tw, tv, gw, gv, keys, offsets, words, br, d_len_keys, d_len_offsets, d_len_words);
-  env.prof_end("wah_write");
-  if ((rc = check_launch(env, "wah_write launch"))) return rc;
-  return kOk;
+                      uint64_t* d_len_words, const uint32_t* req_base, uint32_t req_shift,
+                      const uint32_t* reject_flag, uint32_t reject_shift) {
+  return encode_impl(env, skeys, srows, n, keys, offsets, words, d_len_keys, d_len_offsets, d_len_words, req_base,
+                     req_shift, reject_flag, reject_shift);
+}
+
+int launch_wah_encode16(Env& env, const uint16_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
+                        uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
+                        uint64_t* d_len_words, const uint32_t* reject_flag, uint32_t reject_shift) {
+  return encode_impl(env, skeys, srows, n, keys, offsets, words, d_len_keys, d_len_offsets, d_len_words, nullptr, 32u,
+                     reject_flag, reject_shift);
 }
 
 }  // namespace ka

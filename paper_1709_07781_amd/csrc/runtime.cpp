@@ -902,10 +902,11 @@ KA_API int ka_system_destroy(ka_system* sys) {
   if (sys->destroyed.exchange(true)) return set_error(KA_E_STATE, "system already destroyed");
   {
     std::lock_guard<std::mutex> g(sys->wah_mu);
-    if (sys->wah_actor) {
-      ka_actor_release(static_cast<ka_actor*>(sys->wah_actor));
-      sys->wah_actor = nullptr;
-    }
+    for (auto& a : sys->wah_actor)
+      if (a) {
+        ka_actor_release(static_cast<ka_actor*>(a));
+        a = nullptr;
+      }
     if (sys->builtin) {
       ka_program_release(static_cast<ka_program*>(sys->builtin));
       sys->builtin = nullptr;
@@ -1201,6 +1202,7 @@ KA_API int ka_send(ka_actor* actor, const ka_value* args, uint32_t nargs, ka_tic
 }
 
 static int ticket_wait(ka_ticket* t, int64_t timeout_us) {
+  if (t->hc) return t->hc->wait(t, timeout_us);
   if (t->complete.load() || !t->done) return KA_OK;
   if (timeout_us < 0) {
     KA_HIP(hipEventSynchronize(t->done), "waiting for the response");
@@ -1235,6 +1237,7 @@ KA_API int ka_receive(ka_ticket* t, ka_value* outs, uint32_t nouts, int64_t time
   }
   int rc = ticket_wait(t, timeout_us);
   if (rc) return rc;
+  if (t->status) return set_error(t->status, "request failed");
   int result = KA_OK;
   for (uint32_t i = 0; i < nouts; ++i) {
     MsgVal& v = t->outs[i];
@@ -1291,6 +1294,7 @@ KA_API int ka_ticket_release(ka_ticket* t) {
   if (t->rc.fetch_sub(1) == 1) {
     System* sys = t->sys;
     msg_clear(t->outs);
+    delete t->hc;
     if (t->done) {
       if (!sys->destroyed.load())
         sys->put_event(t->done);
@@ -1399,9 +1403,11 @@ KA_API int ka_ref_serialize(const ka_ref* ref, void* buf, uint64_t cap, uint64_t
 }
 
 // ---- the composed WAH index ---------------------------------------------------------
-static int wah_actor(ka_system* sys, ka_actor** out) {
+// The built-in wah_index actor (sort of (value, row) pairs, then the encoder)
+// with a value-bits hint; one actor per hint, kept by the system.
+static int wah_actor(ka_system* sys, uint32_t value_bits, ka_actor** out) {
   std::lock_guard<std::mutex> g(sys->wah_mu);
-  if (!sys->wah_actor) {
+  if (!sys->wah_actor[value_bits]) {
     if (!sys->builtin) {
       ka_program* p = nullptr;
       int rc = ka_program_builtin(sys, &p);
@@ -1409,26 +1415,18 @@ static int wah_actor(ka_system* sys, ka_actor** out) {
       sys->builtin = p;  // released by ka_system_destroy
     }
     ka_program* prog = static_cast<ka_program*>(sys->builtin);
-    ka_arg sort_sig[3] = {};
-    sort_sig[0] = {KA_IN, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
-    sort_sig[1] = {KA_OUT, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
-    sort_sig[2] = {KA_OUT, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
-    ka_arg enc_sig[5] = {};
-    enc_sig[0] = {KA_IN, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
-    enc_sig[1] = {KA_IN, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
-    for (int i = 2; i < 5; ++i) enc_sig[i] = {KA_OUT, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
+    ka_arg sig[5] = {};
+    sig[0] = {KA_IN, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
+    sig[1] = {KA_PRIV, KA_U32, KA_VAL, KA_VAL, 1, nullptr, nullptr, &value_bits};
+    for (int i = 2; i < 5; ++i) sig[i] = {KA_OUT, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
     ka_nd_range r{};
     r.dims = 1;
-    ka_actor *sort = nullptr, *enc = nullptr, *comp = nullptr;
-    int rc = ka_spawn(sys, prog, "radix_sort_rows_u32", &r, sort_sig, 3, &sort);
-    if (!rc) rc = ka_spawn(sys, prog, "wah_encode_sorted", &r, enc_sig, 5, &enc);
-    if (!rc) rc = ka_compose(enc, sort, &comp);
-    if (sort) ka_actor_release(sort);
-    if (enc) ka_actor_release(enc);
+    ka_actor* act = nullptr;
+    int rc = ka_spawn(sys, prog, "wah_index", &r, sig, 5, &act);
     if (rc) return rc;
-    sys->wah_actor = comp;  // released by ka_system_destroy
+    sys->wah_actor[value_bits] = act;  // released by ka_system_destroy
   }
-  *out = static_cast<ka_actor*>(sys->wah_actor);
+  *out = static_cast<ka_actor*>(sys->wah_actor[value_bits]);
   return KA_OK;
 }
 
@@ -1436,10 +1434,12 @@ KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint
   KA_GUARD_BEGIN
   if (!sys || !out || (n && !values)) return set_error(KA_E_ARG, "null argument");
   if (n >= (1ull << 30)) return set_error(KA_E_ARG, "n must be below 2^30");
+  const uint32_t value_bits = (flags >> 8) & 0xFFu;
+  if (value_bits > 32) return set_error(KA_E_ARG, "KA_WAH_VALUE_BITS must be 0..32");
   int rc = sys->ensure_init();
   if (rc) return rc;
   ka_actor* act = nullptr;
-  if ((rc = wah_actor(sys, &act))) return rc;
+  if ((rc = wah_actor(sys, value_bits, &act))) return rc;
   ka_ref* in = nullptr;
   if (flags & KA_WAH_INPUT_DEVICE) {
     rc = ka_ref_wrap(sys, const_cast<uint32_t*>(values), KA_U32, n, KA_ACCESS_READ, &in);
@@ -1471,6 +1471,7 @@ KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint
   rc = ref_length(res[0].ref, &D);
   if (!rc) rc = ref_length(res[1].ref, &O);
   if (!rc) rc = ref_length(res[2].ref, &W);
+  if (!rc && O == 0 && n > 0) rc = set_error(KA_E_ARG, "a value is at or above 2^value_bits");
   if (!rc && O != D + 1) rc = set_error(KA_E_DEVICE, "inconsistent index lengths");
   if (!rc) {
     r.D = D;

@@ -112,10 +112,11 @@ struct System {
   std::mutex prof_mu;
   std::vector<ProfRec> prof_pending;
   std::map<std::string, std::pair<uint64_t, double>> prof_acc;
-  // built-in program and the composed index actor used by ka_wah_index
+  // built-in program and the index actors used by ka_wah_index (one per
+  // value-bits hint, 0 = none)
   std::mutex wah_mu;
   Program* builtin = nullptr;
-  Actor* wah_actor = nullptr;
+  Actor* wah_actor[33] = {};
 
   int ensure_init();   // lazily initialises HIP on first use
   int use_device();    // makes the system's device current for this thread
@@ -171,6 +172,7 @@ class CmdEnv final : public Env {
     return true;
   }
   LookbackArena* arena() override { return &sys_->streams[si_]->arena; }
+  uint32_t spin_limit() override { return sys_->lb_spin; }
   void prof_begin(const char* kernel) override {
     if (!sys_->profile) return;
     (void)kernel;
@@ -305,6 +307,16 @@ struct MsgVal {
 using Msg = std::vector<MsgVal>;
 void msg_clear(Msg& m);
 
+struct Ticket;
+
+// Completion of a ticket that the host finishes (a served request): wait()
+// blocks until the request is done (or timeout_us passes; < 0: no limit),
+// then fills the ticket's outputs; a failed request sets t->status.
+struct HostCompletion {
+  virtual ~HostCompletion() = default;
+  virtual int wait(Ticket* t, int64_t timeout_us) = 0;
+};
+
 struct Ticket {
   std::atomic<int> rc{1};
   System* sys = nullptr;
@@ -313,6 +325,7 @@ struct Ticket {
   hipEvent_t done = nullptr;
   uint32_t stream = 0;
   std::atomic<bool> complete{false};
+  HostCompletion* hc = nullptr;  // owned; null for device-ordered tickets
 };
 
 // Runs a message through an actor (all stages), queueing the device work.

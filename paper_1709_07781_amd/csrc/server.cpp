@@ -78,13 +78,19 @@ struct OutBuf {
 struct SrvReq {
   virtual ~SrvReq() {
     if (pin) sys->stage.give_back(pin);
+    if (dref) ref_release(dref);
+    for (auto* o : out_ref)
+      if (o) ref_release(o);
     if (outbuf) outbuf->release();
   }
   std::atomic<int> refs{2};  // the caller's handle and the server's
   System* sys = nullptr;
   uint32_t kind = 0;
   uint64_t n = 0;
-  void* pin = nullptr;  // the input, pinned
+  void* pin = nullptr;   // the input, pinned (host input)
+  Ref* dref = nullptr;   // the input on the device (+1 held until the batch has copied it)
+  bool out_refs = false; // outputs as device references
+  Ref* out_ref[3] = {nullptr, nullptr, nullptr};
   double arrival_us = 0;
   OutBuf* outbuf = nullptr;  // outputs: slices of the batch's pinned buffer
   const uint32_t* out[3] = {nullptr, nullptr, nullptr};
@@ -114,10 +120,11 @@ struct Batch {
   uint64_t n[3] = {0, 0, 0};
   void* d_buf = nullptr;
   uint64_t d_bytes = 0;
+  uint64_t d_out = 0, d_chain = 0;  // device offsets of the output region and of the chain values
   void* h_tab = nullptr;  // pinned request tables
   OutBuf* out = nullptr;
   // host output layout
-  uint64_t o_keys = 0, o_offs = 0, o_words = 0, o_ks = 0, o_ws = 0, o_lens = 0, o_scan = 0, o_chain = 0;
+  uint64_t o_keys = 0, o_offs = 0, o_words = 0, o_ks = 0, o_ws = 0, o_lens = 0, o_bad = 0, o_scan = 0, o_chain = 0;
   int rc = KA_OK;
 };
 
@@ -175,6 +182,7 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
   const uint64_t dcap = value_bits >= 32 ? nw : std::min<uint64_t>(nw, (uint64_t)rw << value_bits);
   const uint64_t d_keys = place(4 * dcap), d_offs = place(4 * (dcap + rw)), d_words = place(8 * nw);
   const uint64_t d_ks = place(4 * (rw + 1ull)), d_ws = place(4 * (rw + 1ull)), d_lens = place(5 * 8);
+  const uint64_t d_bad = place(4 * (rw + 1ull));  // per-request rejection flags
   const uint64_t d_scan = place(4 * ns);
   const uint64_t total = off;
   // host output layout: the WAH outputs and lengths in device order, then scan, then chain
@@ -184,7 +192,10 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
   b->o_ks = d_ks - d_keys;
   b->o_ws = d_ws - d_keys;
   b->o_lens = d_lens - d_keys;
+  b->o_bad = d_bad - d_keys;
   b->o_scan = d_scan - d_keys;
+  b->d_out = d_keys;
+  b->d_chain = d_vc;
   b->o_chain = total - d_keys;
   const uint64_t out_bytes = b->o_chain + 4 * nc;
 
@@ -226,8 +237,17 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
     for (int k = 0; k < 3 && e == hipSuccess; ++k) {
       uint64_t pos = 0;
       for (auto* r : b->reqs[k]) {
-        if (r->n && e == hipSuccess)
-          e = hipMemcpyAsync(dev + kind_off[k] + 4 * pos, r->pin, 4 * r->n, hipMemcpyHostToDevice, s);
+        if (r->n && e == hipSuccess) {
+          if (r->dref) {  // device input: ordered after its writer, copied on the device
+            if ((rc = ref_use_on(r->dref, b->si, false))) {
+              b->rc = rc;
+              return b;
+            }
+            e = hipMemcpyAsync(dev + kind_off[k] + 4 * pos, r->dref->ptr, 4 * r->n, hipMemcpyDeviceToDevice, s);
+          } else {
+            e = hipMemcpyAsync(dev + kind_off[k] + 4 * pos, r->pin, 4 * r->n, hipMemcpyHostToDevice, s);
+          }
+        }
         pos += r->n;
       }
     }
@@ -243,7 +263,8 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
     for (auto* r : b->reqs[KA_REQ_WAH]) biggest = std::max<uint32_t>(biggest, (uint32_t)r->n);
     if (rw)
       rc = launch_wah_batch(env, u32(d_vw), nw, u32(d_rw), rw, value_bits, u32(d_keys), u32(d_offs), u32(d_words),
-                            u32(d_ks), u32(d_ws), lens, lens + 1, lens + 2, lens + 3, lens + 4, 0, biggest);
+                            u32(d_ks), u32(d_ws), lens, lens + 1, lens + 2, lens + 3, lens + 4, 0, biggest,
+                            u32(d_bad));
     if (!rc && rs) rc = launch_segmented_scan(env, u32(d_vs), u32(d_scan), ns, u32(d_rs), rs);
     for (size_t i = 0; !rc && nc && i < chain_a.size(); ++i)
       rc = launch_affine(env, u32(d_vc), nc, nullptr, 0, chain_a[i], chain_b[i]);
@@ -282,8 +303,25 @@ void Server::complete(Batch* b) {
   uint64_t lens[5] = {0, 0, 0, 0, 0};
   if (!b->rc && !b->reqs[KA_REQ_WAH].empty()) {
     std::memcpy(lens, ho + b->o_lens, sizeof(lens));
-    if (lens[3] == 0) b->rc = KA_E_DEVICE;  // rejected on the device (values are checked at submit)
+    if (lens[3] == 0) b->rc = KA_E_DEVICE;  // the batch's tables are missing
   }
+  // Outputs wanted as device references: copied from the batch's device
+  // buffer into refs of their own on the batch's stream, before the buffer
+  // goes back to the pool (in stream order).
+  const char* dev = static_cast<const char*>(b->d_buf);
+  auto to_ref = [&](uint64_t dev_off, uint64_t count, Ref** out) -> int {
+    Ref* nr = nullptr;
+    int rc = ref_create(sys, KA_U32, count, b->si, false, &nr);
+    if (rc) return rc;
+    if (count && hipMemcpyAsync(nr->ptr, dev + dev_off, 4 * count, hipMemcpyDeviceToDevice,
+                                sys->streams[b->si]->s) != hipSuccess) {
+      (void)hipGetLastError();
+      ref_release(nr);
+      return set_error(KA_E_DEVICE, "server: result copy");
+    }
+    *out = nr;
+    return KA_OK;
+  };
   uint64_t done_ok = 0, done_bad = 0, elems = 0;
   std::vector<double> lat;
   for (int k = 0; k < 3; ++k) {
@@ -291,7 +329,9 @@ void Server::complete(Batch* b) {
     for (size_t j = 0; j < b->reqs[k].size(); ++j) {
       SrvReq* r = b->reqs[k][j];
       const uint64_t n = r->n;
-      if (!b->rc) {
+      int rrc = b->rc;
+      if (!rrc && k == KA_REQ_WAH && u32(b->o_bad)[j]) rrc = KA_E_ARG;  // a value at or above 2^value_bits
+      if (!rrc) {
         if (k == KA_REQ_WAH) {
           const uint32_t* ks = u32(b->o_ks);
           const uint32_t* ws = u32(b->o_ws);
@@ -306,6 +346,16 @@ void Server::complete(Batch* b) {
           r->out[0] = u32(k == KA_REQ_SCAN ? b->o_scan : b->o_chain) + pos;
           r->out_n[0] = n;
         }
+        if (r->out_refs) {
+          const int outs = k == KA_REQ_WAH ? 3 : 1;
+          for (int i = 0; i < outs && !rrc; ++i) {
+            const uint64_t at = k == KA_REQ_CHAIN ? b->d_chain + 4 * pos
+                                                  : b->d_out + (uint64_t)((const char*)r->out[i] - ho);
+            rrc = to_ref(at, r->out_n[i], &r->out_ref[i]);
+          }
+        }
+      }
+      if (!rrc) {
         b->out->refs.fetch_add(1);
         r->outbuf = b->out;
         ++done_ok;
@@ -319,7 +369,11 @@ void Server::complete(Batch* b) {
         sys->stage.give_back(r->pin);
         r->pin = nullptr;
       }
-      r->finish(b->rc ? b->rc : KA_OK);
+      if (r->dref) {  // its copy into the batch is queued before any later use of the memory
+        ref_release(r->dref);
+        r->dref = nullptr;
+      }
+      r->finish(rrc);
       r->release();
     }
   }
@@ -479,14 +533,16 @@ KA_API int ka_server_create(ka_system* sys, const ka_server_config* cfg, ka_serv
   KA_GUARD_END
 }
 
-KA_API int ka_server_submit(ka_server* srv, uint32_t kind, const uint32_t* data, uint64_t n, double arrival_us,
-                            ka_srv_req** out) {
-  KA_GUARD_BEGIN
-  if (!srv || !out || (n && !data)) return set_error(KA_E_ARG, "null argument");
+namespace {
+
+// Queues one request: host data (copied into pinned memory here) or a device
+// reference (retained until its batch has copied it).
+int server_enqueue(ka_server* srv, uint32_t kind, const uint32_t* data, Ref* dref, uint64_t n, double arrival_us,
+                   bool out_refs, SrvReq** out) {
   if (kind > KA_REQ_CHAIN) return set_error(KA_E_ARG, "unknown request kind");
   if (n >= (1ull << 30)) return set_error(KA_E_ARG, "n must be below 2^30");
   if (request_bytes(kind, n) > srv->budget) return set_error(KA_E_BUDGET, "request larger than the server budget");
-  if (kind == KA_REQ_WAH && srv->value_bits < 32) {
+  if (data && kind == KA_REQ_WAH && srv->value_bits < 32) {
     uint32_t over = 0;
     for (uint64_t i = 0; i < n; ++i) over |= data[i] >> srv->value_bits;
     if (over) return set_error(KA_E_ARG, "an index value is at or above 2^value_bits");
@@ -495,13 +551,18 @@ KA_API int ka_server_submit(ka_server* srv, uint32_t kind, const uint32_t* data,
   r->sys = srv->sys;
   r->kind = kind;
   r->n = n;
-  if (n) {
+  r->out_refs = out_refs;
+  if (n && data) {
     r->pin = srv->sys->stage.get(srv->sys, 4 * n);
     if (!r->pin) {
       delete r;
       return set_error(KA_E_OOM, "server: pinned staging");
     }
     std::memcpy(r->pin, data, 4 * n);
+  }
+  if (dref) {
+    ref_retain(dref);
+    r->dref = dref;
   }
   r->arrival_us = arrival_us > 0 ? arrival_us : clock_us();
   {
@@ -514,6 +575,101 @@ KA_API int ka_server_submit(ka_server* srv, uint32_t kind, const uint32_t* data,
   }
   srv->cv_loop.notify_all();
   *out = r;
+  return KA_OK;
+}
+
+// A ticket answered by a served request: waits on the request, then hands its
+// outputs on as host values (slices of the batch's pinned outputs, kept alive
+// by the ticket) or as the device references made for it.
+struct ServedTicket final : HostCompletion {
+  explicit ServedTicket(SrvReq* req) : r(req) {}
+  ~ServedTicket() override { r->release(); }
+  int wait(Ticket* t, int64_t timeout_us) override {
+    {
+      std::unique_lock<std::mutex> lk(r->mu);
+      if (timeout_us < 0) {
+        r->cv.wait(lk, [&] { return r->done; });
+      } else if (!r->cv.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return r->done; })) {
+        return set_error(KA_E_TIMEOUT, "response not ready");
+      }
+    }
+    if (r->rc) {
+      t->status = r->rc;
+      return set_error(r->rc, "request failed");
+    }
+    std::lock_guard<std::mutex> g(mu);
+    if (!filled) {
+      for (size_t i = 0; i < t->outs.size(); ++i) {
+        MsgVal& v = t->outs[i];
+        v.dtype = KA_U32;
+        if (r->out_refs) {
+          v.mode = KA_REF;
+          v.ref = r->out_ref[i];  // the ticket takes the request's reference
+          r->out_ref[i] = nullptr;
+        } else {
+          v.mode = KA_VAL;
+          v.host = r->out[i];
+          v.count = r->out_n[i];
+        }
+      }
+      filled = true;
+    }
+    return KA_OK;
+  }
+  SrvReq* r;
+  std::mutex mu;
+  bool filled = false;
+};
+
+}  // namespace
+
+KA_API int ka_server_submit(ka_server* srv, uint32_t kind, const uint32_t* data, uint64_t n, double arrival_us,
+                            ka_srv_req** out) {
+  KA_GUARD_BEGIN
+  if (!srv || !out || (n && !data)) return set_error(KA_E_ARG, "null argument");
+  SrvReq* r = nullptr;
+  int rc = server_enqueue(srv, kind, n ? data : nullptr, nullptr, n, arrival_us, false, &r);
+  if (rc) return rc;
+  *out = static_cast<ka_srv_req*>(r);
+  return KA_OK;
+  KA_GUARD_END
+}
+
+KA_API int ka_server_send(ka_server* srv, uint32_t kind, const ka_value* in, uint32_t nin, uint32_t flags,
+                          double arrival_us, ka_ticket** out) {
+  KA_GUARD_BEGIN
+  if (!srv || !out || !in) return set_error(KA_E_ARG, "null argument");
+  if (nin != 1) return set_error(KA_E_ARITY, "a served request is one message element");
+  if (flags & ~KA_SRV_OUTPUT_REFS) return set_error(KA_E_ARG, "unknown flags");
+  const ka_value& v = in[0];
+  const uint32_t* data = nullptr;
+  Ref* dref = nullptr;
+  uint64_t n = 0;
+  if (v.mode == KA_VAL) {
+    if (v.dtype != KA_U32) return set_error(KA_E_TYPE, "served requests take uint32 data");
+    if (v.count && !v.ptr) return set_error(KA_E_ARG, "null value data");
+    data = static_cast<const uint32_t*>(v.ptr);
+    n = v.count;
+  } else if (v.mode == KA_REF) {
+    if (!v.ref) return set_error(KA_E_ARG, "null reference");
+    if (v.ref->sys != srv->sys) return set_error(KA_E_ARG, "reference of another system");
+    if (v.ref->dtype != KA_U32) return set_error(KA_E_TYPE, "served requests take uint32 data");
+    dref = v.ref;
+    int rc = ref_length(dref, &n);
+    if (rc) return rc;
+  } else {
+    return set_error(KA_E_ARG, "unknown value mode");
+  }
+  SrvReq* r = nullptr;
+  int rc = server_enqueue(srv, kind, n ? data : nullptr, n ? dref : nullptr, n, arrival_us,
+                          (flags & KA_SRV_OUTPUT_REFS) != 0, &r);
+  if (rc) return rc;
+  ka_ticket* t = new ka_ticket();
+  t->sys = srv->sys;
+  srv->sys->retain();
+  t->outs.resize(kind == KA_REQ_WAH ? 3 : 1);
+  t->hc = new ServedTicket(r);  // holds the caller's reference of the request
+  *out = t;
   return KA_OK;
   KA_GUARD_END
 }

@@ -10,7 +10,7 @@ from ctypes import byref, c_void_p
 
 import numpy as np
 
-from . import (ka_wah_batch_result, KA_IN, KA_IN_OUT, KA_OUT, KA_PRIV, KA_REF, KA_SYS_PROFILE, KA_U32, KA_VAL, KA_WAH_INPUT_DEVICE,
+from . import (ka_wah_batch_result, KA_IN, KA_IN_OUT, KA_OUT, KA_PRIV, KA_REF, KA_SYS_PROFILE, KA_U32, KA_VAL, KA_WAH_INPUT_DEVICE, KA_WAH_VALUE_BITS,
                KA_WAH_OUTPUT_REFS, arg, check, ka_nd_range, ka_system_config, ka_value, ka_wah_result, lib,
                nd_range, ref, sig, val, values)
 
@@ -138,11 +138,12 @@ class Session:
         return p.value or 0
 
     # ---- composed index --------------------------------------------------------------
-    def wah_index(self, values_, refs: bool = False):
+    def wah_index(self, values_, refs: bool = False, value_bits: int = 0):
         """WAH index of a numpy uint32 array (host input) or a device tensor.
+        value_bits: every value is below 2^value_bits (0: no hint).
         Returns (keys, offsets, words) numpy arrays, or the result struct with refs."""
         res = ka_wah_result()
-        flags = KA_WAH_OUTPUT_REFS if refs else 0
+        flags = (KA_WAH_OUTPUT_REFS if refs else 0) | KA_WAH_VALUE_BITS(value_bits)
         if isinstance(values_, np.ndarray):
             v = np.ascontiguousarray(values_, dtype=np.uint32)
             check(lib.ka_wah_index(self.sys, v.ctypes.data if v.size else None, v.size, flags, byref(res)),
@@ -271,6 +272,20 @@ class Server:
         check(lib.ka_server_submit(self.srv, kind, d.ctypes.data if d.size else None, d.size, arrival_us, byref(r)),
               "ka_server_submit")
         return r
+
+    def send(self, kind: int, data, refs: bool = False, arrival_us: float = 0.0):
+        """ka_server_send: data is a numpy uint32 array (a host value) or a
+        ka_ref handle (a device reference); returns the ticket."""
+        from . import KA_SRV_OUTPUT_REFS
+        if isinstance(data, np.ndarray):
+            d = np.ascontiguousarray(data, dtype=np.uint32)
+            v = val(d.ctypes.data if d.size else None, d.size)
+        else:
+            v = ref(data)
+        t = c_void_p()
+        check(lib.ka_server_send(self.srv, kind, byref(v), 1, KA_SRV_OUTPUT_REFS if refs else 0, arrival_us,
+                                 byref(t)), "ka_server_send")
+        return t
 
     def wait(self, req, timeout_us: int = -1) -> int:
         return lib.ka_server_wait(req, timeout_us)

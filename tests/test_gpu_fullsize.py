@@ -42,6 +42,21 @@ def test_large_zipf_request_composed(sess):
     np.testing.assert_array_equal(words, ew)
 
 
+def test_large_zipf_request_wah_index_actor(sess):
+    """The benchmark's configuration: the built-in wah_index actor with the
+    16-bit hint (two passes over uint16 sort keys), device input, refs out."""
+    v = workloads.large_request()
+    dv = sess.upload(v)
+    res = sess.wah_index(dv, refs=True, value_bits=16)
+    got = tuple(sess.read(r) for r in (res.keys_ref, res.offsets_ref, res.words_ref))
+    for r in (res.keys_ref, res.offsets_ref, res.words_ref):
+        sess.release_ref(r)
+    ek, eo, ew = oracle.default().wah_index(v)
+    np.testing.assert_array_equal(got[0], ek)
+    np.testing.assert_array_equal(got[1], eo)
+    np.testing.assert_array_equal(got[2], ew)
+
+
 def test_affine_chain_2p24(sess):
     import paper_1709_07781_amd as ka
     a, b = workloads.chain_params()

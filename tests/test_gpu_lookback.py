@@ -77,3 +77,17 @@ def test_index_with_fallback(sess):
     exp = oracle.default().wah_index(v)
     for g, e in zip(got, exp):
         np.testing.assert_array_equal(g, e)
+
+
+@pytest.mark.parametrize("bits", [0, 16, 10])
+def test_index_hint_with_fallback(sess, bits):
+    """The encoder's two look-back chains (words, values) and the narrow-key
+    sort's table scans, every stall taking the fallback."""
+    n = (1 << 20) + 4096 * 7 + 13
+    v = workloads.zipf_values(4300 + bits, n)
+    if bits:
+        v = (v & np.uint32((1 << bits) - 1)).astype(np.uint32)
+    got = sess.wah_index(sess.upload(v), value_bits=bits)
+    exp = oracle.default().wah_index(v)
+    for g, e in zip(got, exp):
+        np.testing.assert_array_equal(g, e)

@@ -177,3 +177,75 @@ def test_served_mix_at_full_sizes(sess):
     finally:
         mixed.close()
         alone.close()
+
+
+def test_send_values_and_refs_through_tickets(sess):
+    """ka_server_send: host values and device references in, host values or
+    device references out through tickets (ka_receive); every result equals
+    the oracle's, batched with the others, in either form."""
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import Server
+    a, b = _chain()
+    ora = oracle.default()
+    reqs = _mix(60, seed=71, lo=4, hi=15)
+    reqs += [(workloads.KIND_WAH, np.zeros(0, np.uint32)), (workloads.KIND_CHAIN, np.zeros(0, np.uint32))]
+    srv = Server(sess, streams=2, max_batch=32, chain_a=a, chain_b=b)
+    held = []
+    try:
+        tickets = []
+        for i, (k, x) in enumerate(reqs):
+            dev_in = i % 2 == 1 and x.size > 0
+            data = sess.upload(x) if dev_in else x
+            if dev_in:
+                r = sess.wrap(data)
+                held.append((r, data))
+                data = r
+            tickets.append((srv.send(k, data, refs=(i % 3 == 0)), i % 3 == 0))
+        for (k, x), (t, refs) in zip(reqs, tickets):
+            n_out = 3 if k == workloads.KIND_WAH else 1
+            got = sess.receive(t, n_out)
+            if refs:
+                arrs = []
+                for r in got:
+                    arrs.append(sess.read(r))
+                    sess.release_ref(r)
+                got = arrs
+            sess.release_ticket(t)
+            for g, e in zip(got, _expected(ora, k, x, a, b)):
+                np.testing.assert_array_equal(g, e, err_msg=f"kind={k} n={x.size} refs={refs}")
+    finally:
+        srv.close()
+        for r, _ in held:
+            sess.release_ref(r)
+
+
+@pytest.mark.parametrize("base", [300, 3000])  # the one-work-group path, the tagged sort
+def test_send_device_value_beyond_bits_fails_alone(sess, base):
+    """A device-resident index request holding a value at or above
+    2^value_bits fails at ka_receive with KA_E_ARG; the requests batched with
+    it are unaffected."""
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import Server
+    ora = oracle.default()
+    good = [workloads.served_payload(workloads.KIND_WAH, base + base // 6 * i, 90 + i) for i in range(6)]
+    bad = good[2].copy()
+    bad[17] = 1 << 12
+    bad_dev = sess.upload(bad)
+    rbad = sess.wrap(bad_dev)
+    srv = Server(sess, streams=1, max_batch=16)
+    try:
+        ts = [srv.send(workloads.KIND_WAH, g) for g in good[:3]]
+        tb = srv.send(workloads.KIND_WAH, rbad)
+        ts += [srv.send(workloads.KIND_WAH, g) for g in good[3:]]
+        with pytest.raises(ka.KaError) as e:
+            sess.receive(tb, 3)
+        assert e.value.code == ka.KA_E_ARG
+        sess.release_ticket(tb)
+        for g, t in zip(good, ts):
+            got = sess.receive(t, 3)
+            sess.release_ticket(t)
+            for x, y in zip(got, ora.wah_index(g)):
+                np.testing.assert_array_equal(x, y)
+    finally:
+        srv.close()
+        sess.release_ref(rbad)
