@@ -175,13 +175,29 @@ KA_API int ka_system_memory(ka_system* sys, uint64_t* in_use, uint64_t* reserved
  *   radix_sort_rows_u32   (in keys; out skeys; out srows)         same with rows 0..n-1 (Sec. 4.1 part 1-2)
  *   wah_encode_sorted     (in skeys; in srows; out keys; out offsets; out words)
  *                                                                 Sec. 4.1 parts 3-6 on sorted pairs
- *   wah_index             (in values; priv value_bits; out keys; out offsets; out words)
+ *   wah_index             (in values; priv value_bits [, format]; out keys; out offsets;
+ *                          out words)
  *                                                                 Sec. 4.1 parts 1-6 in one actor: the
  *                                                                 sort, then the encoder (same words as
  *                                                                 the composition of the two actors above);
  *                                                                 value_bits as KA_WAH_VALUE_BITS (0 = no
  *                                                                 hint); a value at or above the hint
- *                                                                 gives every output length 0
+ *                                                                 gives every output length 0; format
+ *                                                                 KA_WAH_PAPER/CANONICAL/PLWAH
+ *   wah_lookup            (in queries; in keys; out slots)       slots[i] = d with keys[d] == queries[i],
+ *                                                                 else 0xFFFFFFFF (keys ascending: the
+ *                                                                 lookup table of Sec. 4.1)
+ *   wah_decode            (in words; priv format, ngroups; out groups)
+ *                                                                 one bitmap's words as ngroups 31-bit
+ *                                                                 group words (bit b of groups[g] = row
+ *                                                                 31 g + b); output length 0 if the words
+ *                                                                 describe more than ngroups groups
+ *   wah_combine           (in a; in b; priv op, in_format, out_format, ngroups; out words)
+ *                                                                 AND (op 0) or OR (op 1) of two bitmaps
+ *                                                                 of ngroups groups, re-encoded in
+ *                                                                 out_format (capacity 2 ngroups + 1; the
+ *                                                                 length is device-resident, 0 if an
+ *                                                                 input describes more groups)
  *   wah_index_batch       (in values; in req_off; priv value_bits; out keys; out offsets;
  *                          out words; out key_start; out word_start)
  *                                                                 the index of each of nreq requests
@@ -251,6 +267,29 @@ KA_API int ka_send(ka_actor* actor, const ka_value* args, uint32_t nargs, ka_tic
  * error code.  The ticket stays valid until ka_ticket_release, so receive may
  * be called again. */
 KA_API int ka_receive(ka_ticket* ticket, ka_value* outs, uint32_t nouts, int64_t timeout_us);
+/* One request of a batch: a message of nargs elements. */
+typedef struct ka_request {
+  const ka_value* args;
+  uint32_t nargs;
+} ka_request;
+
+/* Sends nreq independent requests to one actor as one batch (Sec. 3.6: data
+ * parallelism nested inside one kernel is an alternative level of composition
+ * to one actor invocation per request).  tickets[i] answers reqs[i] exactly as
+ * ka_send(actor, reqs[i].args, reqs[i].nargs) would (the caller provides nreq
+ * ticket slots and releases each ticket).  The built-in actors with a batched
+ * form run all requests in one pass of their kernels on the actor's stream:
+ * wah_index with a value-bits hint (one batched index build; a value at or
+ * above the hint fails only its own request, with KA_E_ARG at ka_receive),
+ * exclusive_scan_u32 (one scan of the concatenation, rebased per request) and
+ * affine_u32 (one launch over the concatenation; a request that sent a
+ * reference gets it back updated in place).  Each request is then one uint32
+ * element, a host value or a device reference; REF outputs are read-only
+ * views of the batch's output buffers.  Any other actor, or one with mapping
+ * functions, gets the requests one after another.  The call waits for the
+ * batch's per-request tables (index requests) or read-back (VAL outputs);
+ * REF outputs are handed on in stream order. */
+KA_API int ka_batch_run(ka_actor* actor, const ka_request* reqs, uint32_t nreq, ka_ticket** tickets);
 /* Number of response elements (available before completion). */
 KA_API int ka_ticket_arity(ka_ticket* ticket, uint32_t* n);
 KA_API int ka_ticket_release(ka_ticket* ticket);
@@ -288,6 +327,15 @@ KA_API int ka_ref_serialize(const ka_ref* ref, void* buf, uint64_t cap, uint64_t
  * runs ceil(b / 8) passes over 16-bit sort keys (Sec. 4.2 sorts with a fixed
  * cardinality of 16 bits).  A value at or above 2^b fails with KA_E_ARG. */
 #define KA_WAH_VALUE_BITS(b) (((uint32_t)(b) & 0x3Fu) << 8)
+/* Word format of the bitmaps (Sec. 4.1 calls fills homogeneous blocks; Sec. 6
+ * names PLWAH): KA_WAH_PAPER (default) one literal per non-empty group and
+ * 0-fills only; KA_WAH_CANONICAL a run of full groups (all 31 rows) becomes one
+ * 1-fill, bit 30 set, run length in bits 29..0; KA_WAH_PLWAH canonical with
+ * 25-bit fill lengths (bits 24..0), and a fill absorbs the group right after
+ * it when that group differs from the fill's groups in one bit only: bits
+ * 29..25 = 1 + that bit's index (0: none).  PLWAH needs n <= 31 (2^25 - 1). */
+enum { KA_WAH_PAPER = 0, KA_WAH_CANONICAL = 1, KA_WAH_PLWAH = 2 };
+#define KA_WAH_FORMAT(f) (((uint32_t)(f) & 0xFFu) << 16)
 
 typedef struct ka_wah_result {
   uint64_t n;        /* input elements */

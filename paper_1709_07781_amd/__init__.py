@@ -35,6 +35,13 @@ def KA_WAH_VALUE_BITS(b: int) -> int:
     return (b & 0x3F) << 8
 
 
+KA_WAH_PAPER, KA_WAH_CANONICAL, KA_WAH_PLWAH = 0, 1, 2
+
+
+def KA_WAH_FORMAT(f: int) -> int:
+    return (f & 0xFF) << 16
+
+
 # ---- structs (ka.h) -----------------------------------------------------------------
 class ka_system_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_uint32),
@@ -97,6 +104,10 @@ class ka_server_config(ctypes.Structure):
                 ("chain_a", ctypes.POINTER(ctypes.c_uint32)), ("chain_b", ctypes.POINTER(ctypes.c_uint32))]
 
 
+class ka_request(ctypes.Structure):
+    _fields_ = [("args", ctypes.POINTER(ka_value)), ("nargs", ctypes.c_uint32)]
+
+
 class ka_server_stats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64), ("elements", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("mean_batch", ctypes.c_double), ("p50_us", ctypes.c_double),
@@ -127,6 +138,7 @@ SIGNATURES = {
     "ka_send": [_P, ctypes.POINTER(ka_value), _U32, _PP],
     "ka_receive": [_P, ctypes.POINTER(ka_value), _U32, _I64],
     "ka_ticket_arity": [_P, _U32P],
+    "ka_batch_run": [_P, _P, _U32, _P],
     "ka_ticket_release": [_P],
     "ka_ref_info": [_P, _U32P, _U64P, _U32P],
     "ka_ref_capacity": [_P, _U64P],

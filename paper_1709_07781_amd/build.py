@@ -13,7 +13,7 @@ OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libka.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_elementwise.hip", "k_scan.hip", "k_sort.hip", "k_wah.hip", "k_batch.hip", "noalloc.hip", "builtins.cpp", "runtime.cpp", "server.cpp", "plan.cpp"]
+SOURCES = ["k_elementwise.hip", "k_scan.hip", "k_sort.hip", "k_wah.hip", "k_groups.hip", "k_batch.hip", "noalloc.hip", "builtins.cpp", "batch_run.cpp", "runtime.cpp", "server.cpp", "plan.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
           f"-I{os.path.join(ROOT, 'include')}"]

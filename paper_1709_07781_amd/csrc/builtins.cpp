@@ -31,6 +31,14 @@ uint64_t cap_wah_index(uint32_t i, uint64_t n, const std::vector<Bound>&) {
   if (i == 3) return n + 1;
   return n ? 2 * n : 1;
 }
+// wah_decode: (in words; priv format, ngroups; out groups[ngroups])
+uint64_t cap_decode(uint32_t, uint64_t, const std::vector<Bound>& args) {
+  return std::max<uint64_t>(args[1].priv[1], 1);
+}
+// wah_combine: (in a; in b; priv op, in_format, out_format, ngroups; out words[<= 2 ngroups])
+uint64_t cap_combine(uint32_t, uint64_t, const std::vector<Bound>& args) { return 2 * args[2].priv[3] + 1; }
+bool len_decode(uint32_t i) { return i == 2; }
+bool len_combine(uint32_t i) { return i == 3; }
 bool len_host(uint32_t) { return false; }
 bool len_batch(uint32_t i) { return i >= 3; }
 bool len_compact(uint32_t i) { return i == 1; }
@@ -99,12 +107,14 @@ int run_wah(LaunchCtx& c) {
                            const_cast<uint64_t*>(a[3].d_len), const_cast<uint64_t*>(a[4].d_len));
 }
 
-// wah_index: (in values; priv value_bits; out keys; out offsets; out words) --
-// parts 1-6 of Sec. 4.1 in one actor: the stable sort of (value, row) pairs,
-// then the encoder.  value_bits 1..16: every value is below 2^value_bits, the
-// sort runs ceil(value_bits / 8) passes over uint16 sort keys; 17..31: values
-// below 2^value_bits, the sort of uint32 keys; 0 or 32: any uint32 value.  A
-// value at or above 2^value_bits voids the result (every output length 0).
+// wah_index: (in values; priv value_bits [, format]; out keys; out offsets;
+// out words) -- parts 1-6 of Sec. 4.1 in one actor: the stable sort of
+// (value, row) pairs, then the encoder.  value_bits 1..16: every value is below
+// 2^value_bits, the sort runs ceil(value_bits / 8) passes over uint16 sort
+// keys; 17..31: values below 2^value_bits, the sort of uint32 keys; 0 or 32:
+// any uint32 value.  A value at or above 2^value_bits voids the result (every
+// output length 0).  format: 0 the paper's form (one literal per non-empty
+// group), 1 canonical WAH (runs of full groups as 1-fills), 2 PLWAH.
 int run_wah_index(LaunchCtx& c) {
   auto& a = *c.args;
   Env& env = *c.env;
@@ -122,8 +132,30 @@ int run_wah_index(LaunchCtx& c) {
   uint64_t* lk = const_cast<uint64_t*>(a[2].d_len);
   uint64_t* lo = const_cast<uint64_t*>(a[3].d_len);
   uint64_t* lw = const_cast<uint64_t*>(a[4].d_len);
+  const uint32_t fmt = (uint32_t)a[1].priv[1];
+  if (fmt > 2) return env.fail(KA_E_ARG, "wah_index: format must be 0 (paper), 1 (canonical) or 2 (PLWAH)");
+  if (fmt == 2 && n > 31ull * 0x1FFFFFFull)
+    return env.fail(KA_E_ARG, "wah_index: PLWAH fill lengths (25 bits) cover at most 31 * (2^25 - 1) rows");
   if (n == 0) return launch_wah_encode(env, nullptr, nullptr, 0, keys, offsets, words, lk, lo, lw);
   int rc;
+  if (fmt != 0) {  // canonical WAH or PLWAH: the sorted pairs' group list, then the format's encoder
+    uint32_t* reject = static_cast<uint32_t*>(env.scratch(4));
+    if (!reject) return env.fail(KA_E_OOM, "wah_index: scratch");
+    if (bits >= 1 && bits <= 16) {
+      uint16_t* sk = static_cast<uint16_t*>(env.scratch(2 * n));
+      uint32_t* sr = static_cast<uint32_t*>(env.scratch(4 * n));
+      if (!sk || !sr) return env.fail(KA_E_OOM, "wah_index: scratch");
+      if ((rc = launch_radix_sort_rows16(env, values, sk, sr, n, bits, reject))) return rc;
+      return launch_wah_encode_format16(env, sk, sr, n, fmt, keys, offsets, words, lk, lo, lw, reject);
+    }
+    uint32_t* sk = static_cast<uint32_t*>(env.scratch(4 * n));
+    uint32_t* sr = static_cast<uint32_t*>(env.scratch(4 * n));
+    if (!sk || !sr) return env.fail(KA_E_OOM, "wah_index: scratch");
+    if ((rc = launch_zero_u32(env, reject))) return rc;
+    if ((rc = launch_radix_sort_pairs(env, values, nullptr, sk, sr, n))) return rc;
+    if (bits >= 17 && bits <= 31 && (rc = launch_reject_above(env, sort_plan_keys_or(env), bits, reject))) return rc;
+    return launch_wah_encode_format(env, sk, sr, n, fmt, keys, offsets, words, lk, lo, lw, reject);
+  }
   if (bits >= 1 && bits <= 16) {
     uint32_t* reject = static_cast<uint32_t*>(env.scratch(4));
     uint16_t* sk = static_cast<uint16_t*>(env.scratch(2 * n));
@@ -139,6 +171,58 @@ int run_wah_index(LaunchCtx& c) {
   const bool check = bits >= 17 && bits <= 31;
   return launch_wah_encode(env, sk, sr, n, keys, offsets, words, lk, lo, lw, nullptr, 32,
                            check ? sort_plan_keys_or(env) : nullptr, check ? bits : 32u);
+}
+
+// wah_lookup: (in queries; in keys; out slots) -- slots[i] = the index d of
+// queries[i] in the lookup table keys (ascending), or 0xFFFFFFFF (Sec. 4.1
+// part 6 read back).
+int run_lookup(LaunchCtx& c) {
+  auto& a = *c.args;
+  if (c.n > a[0].cap || c.n > a[2].cap) return c.env->fail(KA_E_ARG, "wah_lookup: range exceeds a buffer");
+  return launch_wah_lookup(*c.env, static_cast<const uint32_t*>(a[1].ptr), a[1].d_len ? a[1].cap : a[1].len,
+                           a[1].d_len, static_cast<const uint32_t*>(a[0].ptr), c.n, static_cast<uint32_t*>(a[2].ptr));
+}
+
+// wah_decode: (in words; priv format, ngroups; out groups) -- one bitmap as
+// one 31-bit word per group (group g: rows 31 g .. 31 g + 30); the output
+// length is ngroups, or 0 if the words describe more groups.
+int run_decode(LaunchCtx& c) {
+  auto& a = *c.args;
+  Env& env = *c.env;
+  const uint32_t fmt = (uint32_t)a[1].priv[0];
+  const uint64_t ng = a[1].priv[1];
+  if (fmt > 2) return env.fail(KA_E_ARG, "wah_decode: format must be 0, 1 or 2");
+  if (ng >= (1ull << 32) || ng > a[2].cap) return env.fail(KA_E_ARG, "wah_decode: ngroups exceeds the output");
+  if (c.n > a[0].cap) return env.fail(KA_E_ARG, "wah_decode: range exceeds the words");
+  uint32_t* reject = static_cast<uint32_t*>(env.scratch(4));
+  if (!reject) return env.fail(KA_E_OOM, "wah_decode: scratch");
+  int rc;
+  if ((rc = launch_zero_u32(env, reject))) return rc;
+  if ((rc = launch_wah_decode(env, static_cast<const uint32_t*>(a[0].ptr), c.n, c.d_n, fmt, (uint32_t)ng,
+                              static_cast<uint32_t*>(a[2].ptr), reject)))
+    return rc;
+  return launch_len_unless(env, const_cast<uint64_t*>(a[2].d_len), ng, reject);
+}
+
+// wah_combine: (in a; in b; priv op, in_format, out_format, ngroups; out words)
+// -- AND (op 0) or OR (op 1) of two bitmaps over ngroups groups, encoded in
+// out_format; the output length is 0 if an input describes more groups.
+int run_combine(LaunchCtx& c) {
+  auto& a = *c.args;
+  Env& env = *c.env;
+  const uint32_t op = (uint32_t)a[2].priv[0], fin = (uint32_t)a[2].priv[1], fout = (uint32_t)a[2].priv[2];
+  const uint64_t ng = a[2].priv[3];
+  if (op > 1 || fin > 2 || fout > 2) return env.fail(KA_E_ARG, "wah_combine: op 0..1, formats 0..2");
+  if (ng >= (1ull << 31) || 2 * ng + 1 > a[3].cap) return env.fail(KA_E_ARG, "wah_combine: ngroups exceeds the output");
+  if (fout == 2 && ng > 0x1FFFFFFull) return env.fail(KA_E_ARG, "wah_combine: PLWAH fills cover at most 2^25 - 1 groups");
+  uint32_t* reject = static_cast<uint32_t*>(env.scratch(4));
+  if (!reject) return env.fail(KA_E_OOM, "wah_combine: scratch");
+  int rc;
+  if ((rc = launch_zero_u32(env, reject))) return rc;
+  return launch_wah_combine(env, static_cast<const uint32_t*>(a[0].ptr), a[0].d_len ? a[0].cap : a[0].len, a[0].d_len,
+                            static_cast<const uint32_t*>(a[1].ptr), a[1].d_len ? a[1].cap : a[1].len, a[1].d_len, fin,
+                            (uint32_t)ng, op, fout, static_cast<uint32_t*>(a[3].ptr), const_cast<uint64_t*>(a[3].d_len),
+                            reject);
 }
 
 // wah_index_batch: (in values; in req_off; priv value_bits [, largest request + 1];
@@ -190,6 +274,16 @@ std::vector<BuiltinKernel> make_registry() {
                len_wah,
                true,
                run_wah_index});
+  r.push_back({"wah_lookup", {{KA_IN, KA_U32}, {KA_IN, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_host, true,
+               run_lookup});
+  r.push_back({"wah_decode", {{KA_IN, KA_U32}, {KA_PRIV, KA_U32}, {KA_OUT, KA_U32}}, cap_decode, len_decode, false,
+               run_decode});
+  r.push_back({"wah_combine",
+               {{KA_IN, KA_U32}, {KA_IN, KA_U32}, {KA_PRIV, KA_U32}, {KA_OUT, KA_U32}},
+               cap_combine,
+               len_combine,
+               false,
+               run_combine});
   r.push_back({"wah_index_batch",
                {{KA_IN, KA_U32},
                 {KA_IN, KA_U32},

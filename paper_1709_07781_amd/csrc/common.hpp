@@ -87,6 +87,32 @@ int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, ui
 int launch_wah_encode16(Env& env, const uint16_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                         uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
                         uint64_t* d_len_words, const uint32_t* reject_flag = nullptr, uint32_t reject_shift = 32);
+// Index words in an encoder format (0 the paper's form, 1 canonical WAH with
+// 1-fills, 2 PLWAH) from sorted pairs, through the group list.  A fill longer
+// than the format's length field sets *reject (every output length 0).
+int launch_wah_encode_format(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t fmt,
+                             uint32_t* keys, uint32_t* offsets, uint32_t* words, uint64_t* len_keys,
+                             uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject);
+// One bitmap (m words, the count on the device when m_len is given) decoded
+// into ngroups 31-bit group words; more groups than ngroups sets *reject.
+int launch_wah_decode(Env& env, const uint32_t* words, uint64_t m_cap, const uint64_t* m_len, uint32_t fmt,
+                      uint32_t ngroups, uint32_t* groups, uint32_t* reject);
+// AND (op 0) / OR (op 1) of two bitmaps over ngroups groups, encoded in
+// out_fmt into words (capacity 2 ngroups), its length in *len_words.
+int launch_wah_combine(Env& env, const uint32_t* a, uint64_t a_cap, const uint64_t* a_len, const uint32_t* b,
+                       uint64_t b_cap, const uint64_t* b_len, uint32_t in_fmt, uint32_t ngroups, uint32_t op,
+                       uint32_t out_fmt, uint32_t* words, uint64_t* len_words, uint32_t* reject);
+// slots[i] = d with keys[d] == queries[i], or 0xFFFFFFFF (keys ascending).
+int launch_wah_lookup(Env& env, const uint32_t* keys, uint64_t d_cap, const uint64_t* d_len, const uint32_t* queries,
+                      uint64_t q, uint32_t* slots);
+int launch_wah_encode_format16(Env& env, const uint16_t* skeys, const uint32_t* srows, uint64_t n, uint32_t fmt,
+                               uint32_t* keys, uint32_t* offsets, uint32_t* words, uint64_t* len_keys,
+                               uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject);
+int launch_zero_u32(Env& env, uint32_t* p);
+// *reject = 1 if (*keys_or >> bits) != 0 (bits < 32).
+int launch_reject_above(Env& env, const uint32_t* keys_or, uint32_t bits, uint32_t* reject);
+// *len = *reject ? 0 : value.
+int launch_len_unless(Env& env, uint64_t* len, uint64_t value, const uint32_t* reject);
 // Batched index build: nreq requests, values concatenated, req_off[j] the
 // first position of request j (req_off[nreq] = n).  max_req: the largest
 // request, when the caller knows it (kMaxReqUnknown otherwise); batches of

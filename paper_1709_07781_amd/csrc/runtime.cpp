@@ -359,8 +359,31 @@ void ref_release(Ref* r) {
   if (!r || r->rc.fetch_sub(1) != 1) return;
   System* sys = r->sys;
   if (!r->borrowed && !sys->destroyed.load()) sys->pool.release(r->ptr, r->alloc_bytes, r->home, r->used_mask.load());
+  Ref* parent = r->parent;
   delete static_cast<ka_ref*>(r);
   sys->release();
+  if (parent) ref_release(parent);
+}
+
+int ref_view(Ref* parent, uint64_t offset, uint64_t count, Ref** out) {
+  const uint32_t es = dtype_size(parent->dtype);
+  if (offset > parent->cap || count > parent->cap - offset) return set_error(KA_E_ARG, "view beyond its buffer");
+  ka_ref* r = new ka_ref();
+  r->sys = parent->sys;
+  parent->sys->retain();
+  r->dtype = parent->dtype;
+  r->access = KA_ACCESS_READ;
+  r->ptr = static_cast<char*>(parent->ptr) + offset * es;
+  r->cap = count;
+  r->borrowed = true;
+  r->len_known.store(true);
+  r->len = count;
+  r->home = parent->home;
+  r->used_mask.store(parent->used_mask.load());
+  ref_retain(parent);
+  r->parent = parent;
+  *out = r;
+  return KA_OK;
 }
 
 int ref_sync(Ref* r) {
@@ -409,6 +432,7 @@ int ref_use_on(Ref* r, uint32_t si, bool write) {
     r->used_mask.store(1ull << si);
   else
     r->used_mask.fetch_or(1ull << si);
+  for (Ref* p = r->parent; p; p = p->parent) p->used_mask.fetch_or(1ull << si);  // the memory is the parent's
   return KA_OK;
 }
 
@@ -466,7 +490,7 @@ static void to_c_values(const Msg& m, std::vector<ka_value>& out) {
   }
 }
 
-static int from_c_values(const ka_value* vals, uint32_t n, Msg& out) {
+int msg_from_values(const ka_value* vals, uint32_t n, Msg& out) {
   out.clear();
   for (uint32_t i = 0; i < n; ++i) {
     const ka_value& c = vals[i];
@@ -515,7 +539,7 @@ static int apply_map(ka_map_fn fn, void* ud, Msg& m) {
   }
   if (n_out > cap) n_out = cap;
   Msg res;
-  rc = from_c_values(out.data(), n_out, res);
+  rc = msg_from_values(out.data(), n_out, res);
   // VAL data returned by the function are only valid during the call: copy.
   for (auto& v : res) {
     if (v.mode == KA_VAL && !v.ref && v.count) {
@@ -535,7 +559,7 @@ static int apply_map(ka_map_fn fn, void* ud, Msg& m) {
 }
 
 // Uploads a host value into a fresh device buffer on stream si.
-static int upload(System* sys, const MsgVal& v, uint32_t si, Ref** out) {
+int msg_upload(System* sys, const MsgVal& v, uint32_t si, Ref** out) {
   Ref* r = nullptr;
   int rc = ref_create(sys, v.dtype, v.count, si, false, &r);
   if (rc) return rc;
@@ -674,7 +698,7 @@ static int run_kernel_actor(Actor* a, Msg& msg, Msg& out, uint32_t si) {
     Bound& b = args[i];
     Ref* r = nullptr;
     if (v.mode == KA_VAL) {
-      if ((rc = upload(sys, v, si, &r))) {
+      if ((rc = msg_upload(sys, v, si, &r))) {
         cleanup();
         return rc;
       }
@@ -902,11 +926,12 @@ KA_API int ka_system_destroy(ka_system* sys) {
   if (sys->destroyed.exchange(true)) return set_error(KA_E_STATE, "system already destroyed");
   {
     std::lock_guard<std::mutex> g(sys->wah_mu);
-    for (auto& a : sys->wah_actor)
-      if (a) {
-        ka_actor_release(static_cast<ka_actor*>(a));
-        a = nullptr;
-      }
+    for (auto& row : sys->wah_actor)
+      for (auto& a : row)
+        if (a) {
+          ka_actor_release(static_cast<ka_actor*>(a));
+          a = nullptr;
+        }
     if (sys->builtin) {
       ka_program_release(static_cast<ka_program*>(sys->builtin));
       sys->builtin = nullptr;
@@ -1175,7 +1200,7 @@ KA_API int ka_send(ka_actor* actor, const ka_value* args, uint32_t nargs, ka_tic
   System* sys = actor->sys;
   if (sys->destroyed.load()) return set_error(KA_E_STATE, "system was destroyed");
   Msg in, res;
-  int rc = from_c_values(args, nargs, in);
+  int rc = msg_from_values(args, nargs, in);
   if (rc) {
     msg_clear(in);
     return rc;
@@ -1404,10 +1429,11 @@ KA_API int ka_ref_serialize(const ka_ref* ref, void* buf, uint64_t cap, uint64_t
 
 // ---- the composed WAH index ---------------------------------------------------------
 // The built-in wah_index actor (sort of (value, row) pairs, then the encoder)
-// with a value-bits hint; one actor per hint, kept by the system.
-static int wah_actor(ka_system* sys, uint32_t value_bits, ka_actor** out) {
+// with a value-bits hint and a word format; one actor per pair, kept by the
+// system.
+static int wah_actor(ka_system* sys, uint32_t value_bits, uint32_t format, ka_actor** out) {
   std::lock_guard<std::mutex> g(sys->wah_mu);
-  if (!sys->wah_actor[value_bits]) {
+  if (!sys->wah_actor[value_bits][format]) {
     if (!sys->builtin) {
       ka_program* p = nullptr;
       int rc = ka_program_builtin(sys, &p);
@@ -1417,16 +1443,17 @@ static int wah_actor(ka_system* sys, uint32_t value_bits, ka_actor** out) {
     ka_program* prog = static_cast<ka_program*>(sys->builtin);
     ka_arg sig[5] = {};
     sig[0] = {KA_IN, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
-    sig[1] = {KA_PRIV, KA_U32, KA_VAL, KA_VAL, 1, nullptr, nullptr, &value_bits};
+    const uint32_t priv[2] = {value_bits, format};
+    sig[1] = {KA_PRIV, KA_U32, KA_VAL, KA_VAL, 2, nullptr, nullptr, priv};
     for (int i = 2; i < 5; ++i) sig[i] = {KA_OUT, KA_U32, KA_REF, KA_REF, 0, nullptr, nullptr, nullptr};
     ka_nd_range r{};
     r.dims = 1;
     ka_actor* act = nullptr;
     int rc = ka_spawn(sys, prog, "wah_index", &r, sig, 5, &act);
     if (rc) return rc;
-    sys->wah_actor[value_bits] = act;  // released by ka_system_destroy
+    sys->wah_actor[value_bits][format] = act;  // released by ka_system_destroy
   }
-  *out = static_cast<ka_actor*>(sys->wah_actor[value_bits]);
+  *out = static_cast<ka_actor*>(sys->wah_actor[value_bits][format]);
   return KA_OK;
 }
 
@@ -1435,11 +1462,13 @@ KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint
   if (!sys || !out || (n && !values)) return set_error(KA_E_ARG, "null argument");
   if (n >= (1ull << 30)) return set_error(KA_E_ARG, "n must be below 2^30");
   const uint32_t value_bits = (flags >> 8) & 0xFFu;
+  const uint32_t format = (flags >> 16) & 0xFFu;
   if (value_bits > 32) return set_error(KA_E_ARG, "KA_WAH_VALUE_BITS must be 0..32");
+  if (format > 2) return set_error(KA_E_ARG, "KA_WAH_FORMAT must be 0..2");
   int rc = sys->ensure_init();
   if (rc) return rc;
   ka_actor* act = nullptr;
-  if ((rc = wah_actor(sys, value_bits, &act))) return rc;
+  if ((rc = wah_actor(sys, value_bits, format, &act))) return rc;
   ka_ref* in = nullptr;
   if (flags & KA_WAH_INPUT_DEVICE) {
     rc = ka_ref_wrap(sys, const_cast<uint32_t*>(values), KA_U32, n, KA_ACCESS_READ, &in);
@@ -1450,7 +1479,7 @@ KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint
     v.host = values;
     v.count = n;
     Ref* r = nullptr;
-    rc = upload(sys, v, act->stream, &r);
+    rc = msg_upload(sys, v, act->stream, &r);
     in = static_cast<ka_ref*>(r);
   }
   if (rc) return rc;
@@ -1551,7 +1580,7 @@ KA_API int ka_wah_batch(ka_system* sys, const uint32_t* values, uint64_t n, cons
     v.host = values;
     v.count = n;
     Ref* rr = nullptr;
-    rc = upload(sys, v, act->stream, &rr);
+    rc = msg_upload(sys, v, act->stream, &rr);
     in = static_cast<ka_ref*>(rr);
   }
   if (rc) {

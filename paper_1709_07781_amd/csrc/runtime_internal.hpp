@@ -116,7 +116,7 @@ struct System {
   // value-bits hint, 0 = none)
   std::mutex wah_mu;
   Program* builtin = nullptr;
-  Actor* wah_actor[33] = {};
+  Actor* wah_actor[33][3] = {};  // [value bits][format]
 
   int ensure_init();   // lazily initialises HIP on first use
   int use_device();    // makes the system's device current for this thread
@@ -214,6 +214,7 @@ struct Ref {
   uint64_t len = 0;
   uint32_t home = 0;  // stream of the last writer
   std::atomic<uint64_t> used_mask{0};
+  Ref* parent = nullptr;  // a view: elements of the parent's buffer (+1 held on the parent)
 };
 
 // Allocates a pool-backed ref of `count` elements on stream `si`.  With
@@ -228,6 +229,9 @@ int ref_length(Ref* r, uint64_t* len);
 // Orders stream si after the last writer of r (and, for a write, after every
 // stream that used r) and records the use.
 int ref_use_on(Ref* r, uint32_t si, bool write);
+// A read-only view of count elements of parent from element `offset` on; it
+// keeps the parent alive, and its uses are recorded on the parent too.
+int ref_view(Ref* parent, uint64_t offset, uint64_t count, Ref** out);
 
 // ---- programs and built-in kernels -------------------------------------------
 struct Bound {  // one signature argument bound for a launch
@@ -330,6 +334,10 @@ struct Ticket {
 
 // Runs a message through an actor (all stages), queueing the device work.
 int actor_run(Actor* a, Msg& in, Msg& out, uint32_t si);
+// Copies a C message into a Msg (REF values retained).
+int msg_from_values(const ka_value* vals, uint32_t n, Msg& out);
+// Uploads a host value into a new ref on stream si (pinned staging).
+int msg_upload(System* sys, const MsgVal& v, uint32_t si, Ref** out);
 
 }  // namespace ka
 

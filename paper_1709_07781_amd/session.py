@@ -102,6 +102,20 @@ class Session:
         finally:
             self.release_ticket(t)
 
+    def batch_run(self, actor, requests):
+        """ka_batch_run: requests is a list of messages (each a list of
+        ka_value); returns one ticket per request."""
+        from . import ka_request
+        n = len(requests)
+        msgs = [values(*m) for m in requests]  # kept alive until the call returns
+        reqs = (ka_request * max(n, 1))()
+        for i, m in enumerate(msgs):
+            reqs[i].args = ctypes.cast(m, ctypes.POINTER(ka_value))
+            reqs[i].nargs = len(requests[i])
+        tickets = (c_void_p * max(n, 1))()
+        check(lib.ka_batch_run(actor, reqs, n, tickets), "ka_batch_run")
+        return [c_void_p(tickets[i]) for i in range(n)]
+
     # ---- refs ----------------------------------------------------------------------
     def wrap(self, tensor) -> c_void_p:
         """Borrowed ref over a contiguous 4-byte torch tensor on the device."""
@@ -138,12 +152,14 @@ class Session:
         return p.value or 0
 
     # ---- composed index --------------------------------------------------------------
-    def wah_index(self, values_, refs: bool = False, value_bits: int = 0):
+    def wah_index(self, values_, refs: bool = False, value_bits: int = 0, fmt: int = 0):
         """WAH index of a numpy uint32 array (host input) or a device tensor.
-        value_bits: every value is below 2^value_bits (0: no hint).
+        value_bits: every value is below 2^value_bits (0: no hint); fmt: word
+        format (0 paper, 1 canonical, 2 PLWAH).
         Returns (keys, offsets, words) numpy arrays, or the result struct with refs."""
+        from . import KA_WAH_FORMAT
         res = ka_wah_result()
-        flags = (KA_WAH_OUTPUT_REFS if refs else 0) | KA_WAH_VALUE_BITS(value_bits)
+        flags = (KA_WAH_OUTPUT_REFS if refs else 0) | KA_WAH_VALUE_BITS(value_bits) | KA_WAH_FORMAT(fmt)
         if isinstance(values_, np.ndarray):
             v = np.ascontiguousarray(values_, dtype=np.uint32)
             check(lib.ka_wah_index(self.sys, v.ctypes.data if v.size else None, v.size, flags, byref(res)),
