@@ -1,8 +1,11 @@
 #!/usr/bin/env python3
-"""Throughput of the composed WAH index pipeline (radix sort (.) WAH encode) on
-one MI355X: input elements/s over K requests of 2^26 Zipf(1.1) uint32 values
-already resident in HBM, with the HBM roofline of the dominant kernel and of
-the whole pipeline, and the CPU oracle timed on the host beside it.
+"""Throughput of the WAH index pipeline (radix sort of (value, row) pairs, then
+the WAH encoder) on one MI355X: input elements/s over K requests of 2^26
+Zipf(1.1) uint32 values already resident in HBM, built by the wah_index actor
+with the 16-bit value hint (the paper sorts with a fixed cardinality of 16
+bits), with the HBM roofline of the dominant kernel and of the whole pipeline,
+the composition of the two stage actors timed beside it, and the CPU oracle
+timed on the host.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -26,7 +29,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 SORT_KERNELS = ("radix_upsweep0", "radix_plan", "radix_upsweep", "exclusive_scan_u32", "radix_scatter")
-ENCODE_KERNELS = ("wah_count", "wah_offsets", "wah_write")
+ENCODE_KERNELS = ("wah_write",)
 KERNELS = SORT_KERNELS + ENCODE_KERNELS
 # Counter summary of the dominant kernel (FETCH_SIZE / WRITE_SIZE runs of this
 # script under rocprofv3), valid while the kernel's sources hash to what it names.
@@ -129,12 +132,13 @@ def plain_request_leg(sess, args) -> dict:
     import workloads
 
     v = workloads.plain_request()
+    hint = ka.KA_WAH_VALUE_BITS(10)  # values below 1024
     reps = 50
     e2e = []
     for k in range(reps + 3):
         t0 = time.perf_counter()
         res = ka.ka_wah_result()
-        ka.check(ka.lib.ka_wah_index(sess.sys, v.ctypes.data, v.size, 0, ctypes.byref(res)))
+        ka.check(ka.lib.ka_wah_index(sess.sys, v.ctypes.data, v.size, hint, ctypes.byref(res)))
         dt = time.perf_counter() - t0
         D, W = res.D, res.W
         ka.check(ka.lib.ka_wah_result_free(ctypes.byref(res)))
@@ -148,7 +152,7 @@ def plain_request_leg(sess, args) -> dict:
         t0 = time.perf_counter()
         res = ka.ka_wah_result()
         ka.check(ka.lib.ka_wah_index(sess.sys, ctypes.c_void_p(dv.data_ptr()), v.size,
-                                     ka.KA_WAH_INPUT_DEVICE | ka.KA_WAH_OUTPUT_REFS, ctypes.byref(res)))
+                                     ka.KA_WAH_INPUT_DEVICE | ka.KA_WAH_OUTPUT_REFS | hint, ctypes.byref(res)))
         dt = time.perf_counter() - t0
         ka.check(ka.lib.ka_wah_result_free(ctypes.byref(res)))
         if k >= 3:
@@ -156,7 +160,8 @@ def plain_request_leg(sess, args) -> dict:
     e2e_ms = float(np.median(e2e)) * 1e3
     dev_ms = float(np.median(dev)) * 1e3
     log(f"[bench] plain 2^16 request: {e2e_ms:.3f} ms end to end (host in/out), {dev_ms:.3f} ms from HBM")
-    return {"workload": "2^16 values uniform below 1024, one ka_wah_index call", "n": int(v.size), "D": int(D),
+    return {"workload": "2^16 values uniform below 1024, one ka_wah_index call (10-bit value hint)", "n": int(v.size),
+            "D": int(D),
             "W": int(W), "e2e_ms_median": e2e_ms, "e2e_elements_per_s": v.size / (e2e_ms * 1e-3),
             "device_resident_ms_median": dev_ms, "device_resident_elements_per_s": v.size / (dev_ms * 1e-3),
             "requests": reps, "how": "wall time per call on the host (waits for the result), median"}
@@ -174,7 +179,8 @@ def pcie_inclusive_leg(sess, v, args) -> dict:
     for k in range(4):
         t0 = time.perf_counter()
         res = ka.ka_wah_result()
-        ka.check(ka.lib.ka_wah_index(sess.sys, v.ctypes.data, v.size, 0, ctypes.byref(res)))
+        ka.check(ka.lib.ka_wah_index(sess.sys, v.ctypes.data, v.size, ka.KA_WAH_VALUE_BITS(args.value_bits),
+                                     ctypes.byref(res)))
         dt = time.perf_counter() - t0
         D, W = res.D, res.W
         ka.check(ka.lib.ka_wah_result_free(ctypes.byref(res)))
@@ -628,6 +634,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-log2", type=int, default=26)
     ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--value-bits", type=int, default=16,
+                    help="large: the index actor's value hint (every value below 2^bits; 0 = no hint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-extra-legs", action="store_true",
@@ -676,14 +684,21 @@ def main() -> int:
     dv = sess.upload(v)
     torch.cuda.synchronize()
 
-    # The composed actor: wah_encode_sorted (.) radix_sort_rows_u32, refs in and out.
+    # The index actor: wah_index with the value hint (sort of (value, row)
+    # pairs, then the encoder, queued by one actor), refs in and out.
+    import ctypes
+    hint = (ctypes.c_uint32 * 2)(args.value_bits, 0)
+    index_actor = sess.spawn("wah_index", [ka.arg(ka.KA_IN), ka.arg(ka.KA_PRIV, count=2, init=hint)]
+                             + [ka.arg(ka.KA_OUT)] * 3)
+    # The composition of the two stage actors (wah_encode_sorted (.)
+    # radix_sort_rows_u32, no hint), timed beside it.
     sort = sess.spawn("radix_sort_rows_u32", [ka.arg(ka.KA_IN), ka.arg(ka.KA_OUT), ka.arg(ka.KA_OUT)])
     enc = sess.spawn("wah_encode_sorted", [ka.arg(ka.KA_IN), ka.arg(ka.KA_IN)] + [ka.arg(ka.KA_OUT)] * 3)
     pipe = sess.compose(enc, sort)
     vin = sess.wrap(dv)
 
-    def step(keep=False):
-        outs = sess.request(pipe, ka.ref(vin), n_out=3)
+    def step(keep=False, actor=index_actor):
+        outs = sess.request(actor, ka.ref(vin), n_out=3)
         if keep:
             return outs
         for r in outs:
@@ -719,6 +734,18 @@ def main() -> int:
     ms_per_step = dev_ms / args.steps
     for r in last:
         sess.release_ref(r)
+    # the composed two-actor pipeline, same input and timing
+    for _ in range(args.warmup):
+        step(actor=pipe)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step(actor=pipe)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    composed_ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"[bench] composed stage actors: {composed_ms:.4f} ms per request")
     # per-kernel device times for the roofline: a second region with the library's events
     prof_ms, _, last = timed_region(True)
     prof = {k: sess.profile(k) for k in KERNELS}
@@ -731,14 +758,19 @@ def main() -> int:
     # of the sorted pairs by the encoder (8n), and the index it writes
     # (4W + 8D + 4).
     pipe_bytes = 16 * P * n + 8 * n + 4 * W + 8 * D + 4
-    # What this implementation moves on top: the upsweep of every pass after
-    # the first re-reads the keys (4n per pass) and the encoder reads the
-    # sorted pairs twice (its count kernel, 8n); the first scatter pass reads
-    # no rows (-4n).
-    overhead_bytes = 4 * n * (P - 1) + 8 * n - 4 * n
-    # The dominant kernel, k_radix_scatter: the first active pass reads keys
-    # (rows are made from positions) and writes keys and rows; every later one
-    # reads and writes both.
+    # What this implementation moves instead: with the 16-bit hint the sort
+    # keys are stored as uint16 between passes (6 B per pair); every pass
+    # counts its digits from the keys (upsweep: 4n, then 2n); the first pass
+    # reads uint32 values and makes the rows; the encoder reads the sorted
+    # pairs once.
+    if 1 <= args.value_bits <= 16:
+        moved_bytes = (4 * n + 10 * n) + (P - 1) * (2 * n + 12 * n) + 6 * n + 4 * W + 8 * D + 4
+    else:
+        moved_bytes = (4 * n + 12 * n) + (P - 1) * (4 * n + 16 * n) + 8 * n + 4 * W + 8 * D + 4
+    # The dominant kernel, k_radix_scatter: per launch the bytes of the
+    # method's pair pass (4-byte keys): the first pass reads keys (rows are
+    # made from positions) and writes keys and rows, every later one reads
+    # and writes both.  The uint16 sort keys move fewer bytes than these.
     scatter_bytes = 12 * n + 16 * n * (P - 1)
     launches, scatter_ms = prof["radix_scatter"]
     per_launch_bytes = scatter_bytes * args.steps / max(launches, 1)
@@ -796,25 +828,29 @@ def main() -> int:
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "large single request: 2^26 uint32 values Zipf(s=1.1) over 2^16 distinct values, "
-                               "row ids 0..n-1, composed sort->WAH-encode pipeline, per-stage launches, "
-                               "input resident in HBM",
-                   "n": n, "D": D, "W": W, "radix_passes": P, "seed": args.seed},
+                               "row ids 0..n-1, sort->WAH-encode pipeline (wah_index actor, 16-bit value hint), "
+                               "per-stage launches, input resident in HBM",
+                   "n": n, "D": D, "W": W, "radix_passes": P, "value_bits": args.value_bits, "seed": args.seed},
         "roofline": {"bound": "hbm", "kernel": "k_radix_scatter", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launches": launches, "avg_launch_ms": avg_launch_ms,
                      "algorithmic_bytes_per_launch": per_launch_bytes},
-        "pipeline": {"algorithmic_bytes": pipe_bytes, "overhead_bytes": overhead_bytes,
+        "pipeline": {"algorithmic_bytes": pipe_bytes, "moved_bytes": moved_bytes,
                      "bytes_formula": "16*P*n + 8*n + 4*W + 8*D + 4", "ms": ms_per_step, "achieved_GBs": pipe_gbs,
+                     "moved_GBs": moved_bytes / (ms_per_step * 1e-3) / 1e9,
                      "frac": pipe_gbs / HBM_PEAK_GBS, "profiled_ms_per_step": prof_ms / args.steps,
                      "kernel_ms_per_step": {k: prof[k][1] / args.steps for k in prof},
                      "launches_per_step": {k: prof[k][0] / args.steps for k in prof},
                      "wall_s": wall},
+        "composed_stage_actors": {"ms": composed_ms, "elements_per_s": n / (composed_ms * 1e-3),
+                                  "frac": pipe_bytes / (composed_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                  "how": "wah_encode_sorted (.) radix_sort_rows_u32, no value hint, same input"},
         "cpu_baseline": cpu,
         "plain_request": plain,
         "pcie_inclusive": pcie,
         "parity": parity,
     }
-    for a in (pipe, sort, enc):
+    for a in (pipe, sort, enc, index_actor):
         sess.release_actor(a)
     sess.release_ref(vin)
     sess.close()

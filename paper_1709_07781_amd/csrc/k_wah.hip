@@ -238,8 +238,15 @@ __global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const KeyT* __restri
       bit_of[i] = (valid >> i) & 1u ? rr[c] - grp_of[i] * kGroupRows : 31u;
     }
   }
-  const uint32_t kprev = tid ? s_k[pidx(e0 - 1)] : s_behind[0];
-  const uint32_t cprev = (tid ? s_r[pidx(e0 - 1)] : s_behind[1]) / kGroupRows;
+  // The element before this work-item's first: the previous work-item's last
+  // (a shuffle; lane 0 reads it from LDS: the wave before, or the look-behind).
+  const uint32_t lane = lane_id();
+  uint32_t kprev = (uint32_t)__shfl_up((int)key[kEncItems - 1], 1);
+  uint32_t cprev = (uint32_t)__shfl_up((int)grp_of[kEncItems - 1], 1);
+  if (lane == 0) {
+    kprev = tid ? s_k[pidx(e0 - 1)] : s_behind[0];
+    cprev = (tid ? s_r[pidx(e0 - 1)] : s_behind[1]) / kGroupRows;
+  }
 
   // ---- group and value heads, words and values emitted ------------------------------
   uint32_t heads = 0, segs = 0, gaps = 0;  // bit i: element i starts a group / a value / has a fill
@@ -272,16 +279,33 @@ __global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const KeyT* __restri
     lb_publish_raw(status + tile, lb_pack_pair(tile_nw, tile_ns, tile == 0 ? kLbInclusive : kLbAggregate));
 
   // ---- the last group may run past this work-item's elements (at most 30
-  // further elements, into the look-ahead): collect its bits now -------------------
+  // further elements): collect its bits now.  They are the elements of the next
+  // work-items before their first group head ("lead"): a group holds at most 31
+  // elements, so it reaches at most two work-items further, and the second
+  // one has a head.  Shuffles within the wave; the wave's last two lanes read
+  // ahead in LDS (the next wave's elements, or the look-ahead).  Lanes with
+  // invalid elements have no head and no lead bits, which ends a group at the
+  // tile's (and the input's) end.
+  const uint32_t lead_n = heads ? (uint32_t)__builtin_ctz(heads) : (uint32_t)kEncItems;
+  uint32_t lead = 0;
+#pragma unroll
+  for (int i = 0; i < kEncItems; ++i)
+    if ((uint32_t)i < lead_n) lead |= (1u << bit_of[i]) & ~kFill;  // bit 31 marks invalid elements
+  const uint32_t lead1 = (uint32_t)__shfl_down((int)lead, 1), lead2 = (uint32_t)__shfl_down((int)lead, 2);
+  const uint32_t nohead1 = (uint32_t)__shfl_down((int)(heads == 0u), 1);
   uint32_t tail = 0;
   if (e0 + kEncItems <= tile_n) {
-    const uint32_t kl = key[kEncItems - 1], cl = grp_of[kEncItems - 1];
-    for (uint32_t j = e0 + kEncItems; j < avail; ++j) {
-      const uint32_t kj = s_k[pidx(j)];
-      const uint32_t rj = s_r[pidx(j)];
-      const uint32_t cj = rj / kGroupRows;
-      if (kj != kl || cj != cl) break;
-      tail |= 1u << (rj - cj * kGroupRows);
+    if (lane < 62) {
+      tail = lead1 | (nohead1 ? lead2 : 0u);
+    } else {
+      const uint32_t kl = key[kEncItems - 1], cl = grp_of[kEncItems - 1];
+      for (uint32_t j = e0 + kEncItems; j < avail; ++j) {
+        const uint32_t kj = s_k[pidx(j)];
+        const uint32_t rj = s_r[pidx(j)];
+        const uint32_t cj = rj / kGroupRows;
+        if (kj != kl || cj != cl) break;
+        tail |= 1u << (rj - cj * kGroupRows);
+      }
     }
   }
   __syncthreads();  // the staged input is dead from here on

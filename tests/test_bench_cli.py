@@ -38,7 +38,10 @@ def test_traffic_summary_is_well_formed():
               "write_scale", "sources_sha256"):
         assert k in t, k
     assert t["kernel"] == "k_radix_scatter" and t["n_log2"] == 26
-    assert 0.9 < t["hbm_bytes_per_launch"] / t["algorithmic_bytes_per_launch"] < 1.5
+    # The method's pair passes move 4-byte keys; the sort behind the benchmark
+    # stores 16-bit keys between passes, so its launches move 10n and 12n
+    # bytes against 12n and 16n algorithmic (0.79), plus any waste.
+    assert 0.7 < t["hbm_bytes_per_launch"] / t["algorithmic_bytes_per_launch"] < 1.5
     assert re.fullmatch(r"[0-9a-f]{64}", t["sources_sha256"])
     # the digest function reads the sources the summary was taken from
     assert re.fullmatch(r"[0-9a-f]{64}", bench.sources_digest(bench.SCATTER_SOURCES))
