@@ -517,6 +517,93 @@ def bench_served(args) -> int:
     return 0 if parity_ok else 1
 
 
+def bench_spawn(args) -> int:
+    """The paper's first benchmark (Sec. 5.1): wall-clock time to create the
+    runtime and spawn N actors, then to make sure they are usable by sending
+    one message to the last one and waiting for its response; mean of R runs
+    with 95% confidence intervals.  Kernel actors (affine_u32 of the built-in
+    program; add_u32 of a gfx950 code object loaded per run) against host-only
+    actors (composed actors over two affine stages: they run no kernel of their
+    own, the closest thing here to CAF's event-based actors)."""
+    import ctypes
+
+    import paper_1709_07781_amd as ka
+
+    hsaco = os.path.join(ROOT, "tests", "kernels", "user_kernels.hsaco")
+    counts = [int(c) for c in args.spawn_counts.split(",")]
+    runs = args.spawn_runs
+    m = 1024
+    x = np.arange(m, dtype=np.uint32)
+    P = ctypes.c_void_p
+
+    def one_run(kind: str, n: int) -> float:
+        t0 = time.perf_counter()
+        cfg = ka.ka_system_config()
+        sysh, prog = P(), P()
+        ka.check(ka.lib.ka_system_create(ctypes.byref(cfg), ctypes.byref(sysh)))
+        if kind == "code_object":
+            ka.check(ka.lib.ka_program_load(sysh, hsaco.encode(), ctypes.byref(prog)))
+        else:
+            ka.check(ka.lib.ka_program_builtin(sysh, ctypes.byref(prog)))
+        ca, cb = (ctypes.c_uint32 * 1)(3), (ctypes.c_uint32 * 1)(1)
+        aff_sig = ka.sig(ka.arg(ka.KA_IN_OUT, in_mode=ka.KA_VAL, out_mode=ka.KA_VAL),
+                         ka.arg(ka.KA_PRIV, count=1, init=ca), ka.arg(ka.KA_PRIV, count=1, init=cb))
+        add_sig = ka.sig(ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_IN, in_mode=ka.KA_VAL),
+                         ka.arg(ka.KA_OUT, out_mode=ka.KA_VAL))
+        rng = ka.nd_range(global0=m)
+        actors, stages = [], []
+        if kind == "composed":
+            for _ in range(2):
+                st = P()
+                ka.check(ka.lib.ka_spawn(sysh, prog, b"affine_u32", ctypes.byref(rng), aff_sig, 3, ctypes.byref(st)))
+                stages.append(st)
+        for _ in range(n):
+            a = P()
+            if kind == "builtin":
+                ka.check(ka.lib.ka_spawn(sysh, prog, b"affine_u32", ctypes.byref(rng), aff_sig, 3, ctypes.byref(a)))
+            elif kind == "code_object":
+                ka.check(ka.lib.ka_spawn(sysh, prog, b"add_u32", ctypes.byref(rng), add_sig, 3, ctypes.byref(a)))
+            else:
+                ka.check(ka.lib.ka_compose(stages[0], stages[1], ctypes.byref(a)))
+            actors.append(a)
+        msg = [ka.val(x.ctypes.data, m)] * (2 if kind == "code_object" else 1)
+        t = P()
+        ka.check(ka.lib.ka_send(actors[-1], ka.values(*msg), len(msg), ctypes.byref(t)))
+        out = np.empty(m, np.uint32)
+        o = (ka.ka_value * 1)()
+        o[0].ptr, o[0].count = out.ctypes.data, m
+        ka.check(ka.lib.ka_receive(t, o, 1, -1))
+        dt = time.perf_counter() - t0
+        ka.check(ka.lib.ka_ticket_release(t))
+        for a in actors + stages:
+            ka.check(ka.lib.ka_actor_release(a))
+        ka.check(ka.lib.ka_program_release(prog))
+        ka.check(ka.lib.ka_system_destroy(sysh))
+        return dt
+
+    import torch
+    torch.cuda.set_device(0)
+    one_run("builtin", 1)  # the process's first HIP initialisation, not counted
+    res = {}
+    for kind in ("builtin", "code_object", "composed"):
+        rows = []
+        for n in counts:
+            ts = [one_run(kind, n) for _ in range(runs)]
+            mean = float(np.mean(ts))
+            ci = 1.96 * float(np.std(ts, ddof=1)) / np.sqrt(len(ts)) if len(ts) > 1 else 0.0
+            rows.append({"actors": n, "mean_ms": mean * 1e3, "ci95_ms": ci * 1e3})
+            log(f"[bench] spawn {kind}: {n} actors {mean * 1e3:.3f} ms +- {ci * 1e3:.3f}")
+        ns = np.array([r["actors"] for r in rows], float)
+        ms = np.array([r["mean_ms"] for r in rows])
+        slope, icept = np.polyfit(ns, ms, 1) if len(ns) > 1 else (0.0, float(ms[0]))
+        res[kind] = {"runs": rows, "per_actor_us": slope * 1e3, "intercept_ms": icept}
+    out = {"metric": "wall-clock time to create the runtime and spawn N actors (Sec. 5.1)", "unit": "ms",
+           "higher_is_better": False, "runs_per_point": runs, "message": f"one request of {m} uint32 to the last actor",
+           "kinds": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_chain(args) -> int:
     """The actor-overhead chain: 8 affine actors composed with device-resident
     refs, the same stages with a host round trip per stage (values in and out),
@@ -640,7 +727,9 @@ def main() -> int:
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-extra-legs", action="store_true",
                     help="skip the plain 2^16 request leg and the PCIe-inclusive leg of the default workload")
-    ap.add_argument("--workload", choices=("large", "batched", "served", "chain"), default="large",
+    ap.add_argument("--spawn-counts", default="1,10,100,1000,5000", help="spawn: actor counts")
+    ap.add_argument("--spawn-runs", type=int, default=50, help="spawn: runs per count (the paper: mean of 50)")
+    ap.add_argument("--workload", choices=("large", "batched", "served", "chain", "spawn"), default="large",
                     help="large: the 2^26 Zipf request (default); batched: 4096 requests of 2^10..2^20 values, "
                          "one batched pass against 4096 plain per-request pipelines; served: Poisson arrivals of "
                          "the 40/30/30 index/scan/chain mix at several rates, batched server against the plain "
@@ -666,6 +755,8 @@ def main() -> int:
         return bench_served(args)
     if args.workload == "chain":
         return bench_chain(args)
+    if args.workload == "spawn":
+        return bench_spawn(args)
 
     import torch
     import paper_1709_07781_amd as ka

@@ -258,6 +258,16 @@ KA_API int ka_actor_release(ka_actor* actor);
  * device is done).  Device work of a chain is enqueued before the call
  * returns; stages hand references on before the device finishes (Sec. 3.5). */
 KA_API int ka_send(ka_actor* actor, const ka_value* args, uint32_t nargs, ka_ticket** out);
+/* Sends a message to `target` whose response goes to `reply_to` instead of
+ * the sender (Sec. 3.4: CAF's send_as and other ways to route an OpenCL
+ * actor's result): target's response is reply_to's message, and the ticket
+ * answers with reply_to's response.  Each actor's work is queued on its own
+ * stream, the handoff ordered by the references.  The other ways of the same
+ * passage: a post-processing function (ka_actor_set_mapping) may send its
+ * result to other actors with ka_send, and one that returns no values
+ * suppresses the response (the ticket then has arity 0); composition is
+ * ka_compose. */
+KA_API int ka_send_as(ka_actor* target, ka_actor* reply_to, const ka_value* args, uint32_t nargs, ka_ticket** out);
 /* Waits for the response (timeout_us < 0: forever; 0: poll).  For each VAL
  * output, outs[i].count is set to the produced count and, if outs[i].ptr is
  * non-NULL, that many elements are copied there (KA_E_ARG, with count set, if

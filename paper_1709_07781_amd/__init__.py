@@ -136,6 +136,7 @@ SIGNATURES = {
     "ka_actor_retain": [_P],
     "ka_actor_release": [_P],
     "ka_send": [_P, ctypes.POINTER(ka_value), _U32, _PP],
+    "ka_send_as": [_P, _P, ctypes.POINTER(ka_value), _U32, _PP],
     "ka_receive": [_P, ctypes.POINTER(ka_value), _U32, _I64],
     "ka_ticket_arity": [_P, _U32P],
     "ka_batch_run": [_P, _P, _U32, _P],

@@ -1226,6 +1226,42 @@ KA_API int ka_send(ka_actor* actor, const ka_value* args, uint32_t nargs, ka_tic
   KA_GUARD_END
 }
 
+KA_API int ka_send_as(ka_actor* target, ka_actor* reply_to, const ka_value* args, uint32_t nargs, ka_ticket** out) {
+  KA_GUARD_BEGIN
+  if (!target || !reply_to || !out || (nargs && !args)) return set_error(KA_E_ARG, "null argument");
+  System* sys = target->sys;
+  if (reply_to->sys != sys) return set_error(KA_E_ARG, "actors of different systems");
+  if (sys->destroyed.load()) return set_error(KA_E_STATE, "system was destroyed");
+  Msg in, mid, res;
+  int rc = msg_from_values(args, nargs, in);
+  if (rc) {
+    msg_clear(in);
+    return rc;
+  }
+  // target's response becomes reply_to's message, on each actor's own stream
+  rc = actor_run(target, in, mid, target->stream);
+  msg_clear(in);
+  if (!rc) rc = actor_run(reply_to, mid, res, reply_to->stream);
+  msg_clear(mid);
+  if (rc) {
+    msg_clear(res);
+    return rc;
+  }
+  const uint32_t si = reply_to->stream;
+  ka_ticket* t = new ka_ticket();
+  t->sys = sys;
+  sys->retain();
+  t->outs = std::move(res);
+  t->stream = si;
+  if (sys->inited && sys->init_rc == KA_OK) {
+    t->done = sys->get_event();
+    if (t->done) hipEventRecord(t->done, sys->streams[si]->s);
+  }
+  *out = t;
+  return KA_OK;
+  KA_GUARD_END
+}
+
 static int ticket_wait(ka_ticket* t, int64_t timeout_us) {
   if (t->hc) return t->hc->wait(t, timeout_us);
   if (t->complete.load() || !t->done) return KA_OK;

@@ -227,3 +227,65 @@ def test_in_place_write_waits_for_reads_on_other_streams():
         s.release_ref(rx)
     finally:
         s.close()
+
+
+def test_send_as_routes_the_response(sess):
+    """ka_send_as: the scan actor's response goes to the affine actor, whose
+    response answers the ticket (Sec. 3.4: send_as)."""
+    ka = _ka()
+    a, b = 0x01000193, 77
+    v = workloads.u32(40, 70_001)
+    scan = sess.spawn("exclusive_scan_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_OUT)])
+    aff = sess.affine_actor(a, b, in_mode=ka.KA_REF, out_mode=ka.KA_VAL)
+    t = c_void_p()
+    try:
+        ka.check(ka.lib.ka_send_as(scan, aff, ka.values(ka.val(v.ctypes.data, v.size)), 1, byref(t)))
+        (y,) = sess.receive(t, 1)
+        sess.release_ticket(t)
+    finally:
+        sess.release_actor(scan)
+        sess.release_actor(aff)
+    o = oracle.default()
+    exp = o.affine_chain(o.exclusive_scan(v), np.array([a], np.uint32), np.array([b], np.uint32))
+    np.testing.assert_array_equal(y, exp)
+
+
+def test_post_redirects_and_suppresses_the_response(sess):
+    """A post-processing function sends the kernel's result on to another
+    actor (ka_send from inside the mapping) and returns nothing: the original
+    request's response is suppressed (arity 0), the redirected one carries the
+    result (Sec. 3.4)."""
+    ka = _ka()
+    a, b = 5, 11
+    aff = sess.affine_actor(a, b, in_mode=ka.KA_REF, out_mode=ka.KA_VAL)
+    sent = []
+
+    @ka.ka_map_fn
+    def post(inp, n_in, out, n_out, cap, ud):
+        t = c_void_p()
+        rc = ka.lib.ka_send(aff, inp, n_in, byref(t))
+        if rc:
+            return rc
+        sent.append(t)
+        n_out[0] = 0
+        return 0
+
+    scan = sess.spawn("exclusive_scan_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_OUT)])
+    ka.check(ka.lib.ka_actor_set_mapping(scan, ka.ka_map_fn(), post, None))  # no pre-processing
+    v = workloads.u32(41, 9_999)
+    try:
+        t = sess.send(scan, ka.val(v.ctypes.data, v.size))
+        n = ctypes.c_uint32()
+        ka.check(ka.lib.ka_ticket_arity(t, byref(n)))
+        assert n.value == 0
+        assert sess.receive(t, 0) == []
+        sess.release_ticket(t)
+        assert len(sent) == 1
+        (y,) = sess.receive(sent[0], 1)
+        sess.release_ticket(sent[0])
+    finally:
+        sess.release_actor(scan)
+        sess.release_actor(aff)
+    o = oracle.default()
+    exp = o.affine_chain(o.exclusive_scan(v), np.array([a], np.uint32), np.array([b], np.uint32))
+    np.testing.assert_array_equal(y, exp)
