@@ -326,9 +326,12 @@ def bench_batched(args) -> int:
     b_gbs = batch_bytes / (b_ms * 1e-3) / 1e9
     g_gbs = batch_bytes / (g_ms * 1e-3) / 1e9
     sc_launches, sc_ms = prof["radix_scatter"]
-    P_tag, _ = active_passes(((np.repeat(np.arange(nreq, dtype=np.uint32), sizes) << np.uint32(12)) | v)
-                            if N else v)
-    sc_bytes = (12 * N + 16 * N * (P_tag - 1)) * args.steps
+    # The batch's sort: values below 2^12 take the segmented sort (each
+    # request sorted inside its own positions over 16-bit keys), 2 passes of
+    # 8-bit digits; the method's pair-pass bytes per launch as for one request
+    # (12 N for the first pass, 16 N for each later one).
+    P_sort = 2
+    sc_bytes = (12 * N + 16 * N * (P_sort - 1)) * args.steps
     sc_gbs = sc_bytes / max(sc_launches, 1) / (sc_ms / max(sc_launches, 1) * 1e-3) / 1e9
     log(f"[bench] batched: sum of per-request bytes {batch_bytes / 1e9:.2f} GB: actor {b_gbs:.0f} GB/s, "
         f"graph {g_gbs:.0f} GB/s")
@@ -369,7 +372,7 @@ def bench_batched(args) -> int:
         "roofline": {"bound": "hbm", "kernel": "k_radix_scatter", "achieved": sc_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": sc_gbs / HBM_PEAK_GBS, "traffic": None,
                      "launches": sc_launches, "avg_launch_ms": sc_ms / max(sc_launches, 1),
-                     "algorithmic_bytes_per_launch": sc_bytes / max(sc_launches, 1), "tag_passes": P_tag},
+                     "algorithmic_bytes_per_launch": sc_bytes / max(sc_launches, 1), "sort_passes": P_sort},
         "pipeline": {"algorithmic_bytes": batch_bytes,
                      "bytes_formula": "sum over requests of 16*P_j*n_j + 8*n_j + 4*W_j + 8*D_j + 4",
                      "actor_GBs": b_gbs, "actor_frac": b_gbs / HBM_PEAK_GBS, "graph_GBs": g_gbs,

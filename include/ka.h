@@ -414,13 +414,16 @@ KA_API int ka_wah_batch_result_free(ka_wah_batch_result* res);
  * boundaries req_off[0..nreq], n = req_off[nreq]) recorded once into a HIP graph
  * on the plan's own stream and replayed by each run (Sec. 3.6: with the stages
  * composed, the per-stage launch work is the overhead left).  With
- * KA_PLAN_AUTOTUNE it records one graph per sort tile shape (8192 keys as
- * 1024 x 8 or 512 x 16 work-items x keys, 4096 keys as 512 x 8) and its first
- * run times them all on the real values and keeps the fastest.  The plan owns
+ * KA_PLAN_AUTOTUNE it records one graph per sort variant and its first run
+ * times them all on the real values and keeps the fastest: variant 0 sorts
+ * each request inside its own positions over 16-bit keys when value_bits <=
+ * 16 (ceil(value_bits / 8) passes, 1024 x 8 work-items x keys per tile), else
+ * the request-tagged keys with that tile; variants 1 and 2 sort the
+ * request-tagged 32-bit keys with 512 x 16 and 512 x 8.  The plan owns
  * its input, outputs and scratch (nothing is allocated per run); outputs are
  * those of ka_wah_batch.  Requirements on req_off and value_bits as there. */
-#define KA_PLAN_AUTOTUNE 1u /* record one graph per sort tile shape; the first run picks the fastest */
-#define KA_PLAN_SHAPE(s) (((uint32_t)(s) + 1u) << 8) /* record tile shape s only (0, 1 or 2) */
+#define KA_PLAN_AUTOTUNE 1u /* record one graph per sort variant; the first run picks the fastest */
+#define KA_PLAN_SHAPE(s) (((uint32_t)(s) + 1u) << 8) /* record sort variant s only (0, 1 or 2) */
 KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_t nreq, uint32_t value_bits,
                                 uint32_t flags, ka_batch_plan** out);
 /* The device buffer (n uint32) the graph reads the values from. */

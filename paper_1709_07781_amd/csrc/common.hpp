@@ -68,6 +68,15 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
                             uint32_t* srows, uint64_t n, int shape = 0);
 // Number of tile shapes launch_radix_sort_pairs offers (shape 0 is the default).
 int sort_shape_count();
+// Sort of a batch of requests (request j: values[req_off[j] .. req_off[j+1]),
+// all below 2^value_bits, value_bits 1..16) by value inside each request,
+// stable: skeys[i] = j << value_bits | value, srows[i] = the position inside
+// the request, request j's pairs at [req_off[j], req_off[j+1]).  A value at or
+// above 2^value_bits sets req_bad[j] (or *bad without req_bad); the caller
+// clears them.
+int launch_radix_sort_segments(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
+                               uint32_t value_bits, uint32_t* skeys, uint32_t* srows, uint32_t* bad,
+                               uint32_t* req_bad);
 // Device address of the OR of all keys of the last launch_radix_sort_pairs on
 // this stream (valid once that sort has run, for n > 0).
 const uint32_t* sort_plan_keys_or(Env& env);

@@ -4,13 +4,16 @@
 // per-request index).
 //
 // The requests' values are concatenated; request j owns positions
-// [req_off[j], req_off[j+1]).  Each value is tagged with its request in the
-// key's high bits, key = j << value_bits | value, so that one stable radix
-// sort of the tagged keys (rows = batch positions) orders every request by
-// value at once, requests in order.  The WAH encoder then sees a new value
-// wherever the request changes and takes rows relative to the request's first
-// position, which gives each request exactly its own index.  Finally the one
-// lookup table is split per request:
+// [req_off[j], req_off[j+1]).  With values of at most 16 bits the segmented
+// sort (k_sort.hip) orders every request by value inside its own positions,
+// with rows relative to the request, and writes each key tagged with its
+// request, key = j << value_bits | value.  Wider values are tagged first and
+// one stable radix sort of the tagged keys (rows = batch positions) orders
+// every request by value at once, requests in order.  The WAH encoder then
+// sees a new value wherever the request changes (and, after the tagged sort,
+// takes rows relative to the request's first position), which gives each
+// request exactly its own index.  Finally the one lookup table is split per
+// request:
 //   key_start[j]   first lookup entry of request j (key_start[nreq] = D),
 //   word_start[j]  first word of request j (word_start[nreq] = W),
 //   keys[d]        the value (request tag removed),
@@ -431,8 +434,9 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
     return check_launch(env, "batch_small_place launch");
   }
 
+  const bool segmented = value_bits <= 16 && sort_shape == 0;
   uint32_t* bad = static_cast<uint32_t*>(env.scratch(4));
-  uint32_t* tkeys = static_cast<uint32_t*>(env.scratch(4 * (n ? n : 1)));
+  uint32_t* tkeys = segmented ? bad : static_cast<uint32_t*>(env.scratch(4 * (n ? n : 1)));
   uint32_t* skeys = static_cast<uint32_t*>(env.scratch(4 * (n ? n : 1)));
   uint32_t* srows = static_cast<uint32_t*>(env.scratch(4 * (n ? n : 1)));
   uint32_t* g_off = static_cast<uint32_t*>(env.scratch(4 * (n + 1)));
@@ -441,18 +445,28 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
   int rc = launch_fill_u32(env, bad, 1, 0);
   if (rc) return rc;
   if (req_bad && (rc = launch_fill_u32(env, req_bad, nreq, 0))) return rc;
+  // Values of at most 16 bits: the segmented sort orders each request by value
+  // in ceil(value_bits / 8) passes over 16-bit keys and makes request-relative
+  // rows; wider values: every value tagged with its request in the key's high
+  // bits, one sort of the tagged keys over all requests (value_bits + the bits
+  // of nreq - 1 passes' worth of digits), rows made relative by the encoder.
   if (n) {
-    const uint64_t blocks = (n + kKeyTile - 1) / kKeyTile;
-    env.prof_begin("batch_keys");
-    k_batch_map<TagOp><<<dim3((uint32_t)blocks), dim3(kKeyBlock), 0, env.stream()>>>(values, tkeys, nn, req_off, nreq,
-                                                                                    TagOp{value_bits, req_bad}, bad);
-    env.prof_end("batch_keys");
-    if ((rc = check_launch(env, "batch_keys launch"))) return rc;
-    if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n, sort_shape))) return rc;
+    if (segmented) {
+      if ((rc = launch_radix_sort_segments(env, values, n, req_off, nreq, value_bits, skeys, srows, bad, req_bad)))
+        return rc;
+    } else {
+      const uint64_t blocks = (n + kKeyTile - 1) / kKeyTile;
+      env.prof_begin("batch_keys");
+      k_batch_map<TagOp><<<dim3((uint32_t)blocks), dim3(kKeyBlock), 0, env.stream()>>>(
+          values, tkeys, nn, req_off, nreq, TagOp{value_bits, req_bad}, bad);
+      env.prof_end("batch_keys");
+      if ((rc = check_launch(env, "batch_keys launch"))) return rc;
+      if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n, sort_shape))) return rc;
+    }
   }
-  // The tagged keys are the encoder's keys; rows become request-relative.
-  if ((rc = launch_wah_encode(env, skeys, srows, n, keys, g_off, words, len_keys, g_len, len_words, req_off,
-                              value_bits)))
+  // The tagged keys are the encoder's keys; rows are (or become) request-relative.
+  if ((rc = launch_wah_encode(env, skeys, srows, n, keys, g_off, words, len_keys, g_len, len_words,
+                              segmented ? nullptr : req_off, segmented ? 32u : value_bits)))
     return rc;
   const uint32_t sgrid = std::min<uint32_t>(kSplitGrid, (nreq + kSplitBlock) / kSplitBlock);
   env.prof_begin("batch_split");

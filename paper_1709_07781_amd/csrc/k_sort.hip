@@ -86,6 +86,9 @@ struct PassIoT {
   DK* dst_keys;
   uint32_t* dst_rows;
   bool implicit_rows;
+  uint32_t row_origin = 0;  // implicit rows: position - row_origin
+  uint32_t key_or = 0;      // keys written as (key & key_and) | key_or (kTag scatters only)
+  uint32_t key_and = ~0u;
 };
 using PassIo = PassIoT<uint32_t, uint32_t>;
 
@@ -153,21 +156,22 @@ constexpr int kUpWaves = kUpBlock / 64;
 // the position in the pass's output of the tile's first key with digit d.
 // All of a work-item's loads are issued before the first key is counted; with
 // kOrAnd the OR and the AND of the tile's keys are written too.
+// The tile is keys[base, base + len); digit d's count goes to
+// table[d * stride + col] (the plan-driven and fixed sorts: stride = tile
+// count, col = tile; the segmented sort: its request's part of the table).
 template <int kTile, int kRounds, bool kOrAnd, class SK>
-__device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32_t shift, uint32_t tile, uint32_t n,
-                                             uint32_t ntiles, uint32_t* __restrict__ table,
-                                             uint32_t* __restrict__ orand) {
+__device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32_t shift, uint32_t base, uint32_t len,
+                                             uint32_t* __restrict__ table, uint64_t col, uint64_t stride,
+                                             uint32_t tile, uint32_t* __restrict__ orand) {
   constexpr int kUpVecs = kTile / 4 / kUpBlock;  // 4-key loads per work-item
   constexpr uintptr_t kAlign = 4 * sizeof(SK) - 1;
   __shared__ uint32_t s_hist[kUpWaves][kRadix];
   __shared__ uint32_t s_or[kUpWaves], s_and[kUpWaves];
   const uint32_t tid = threadIdx.x, w = tid / 64;
-  const uint32_t base = tile * kTile;
-  const uint32_t len = min((uint32_t)kTile, n - base);
 
   // Key 4 (j * kUpBlock + tid) + c of the tile in k[j][c].
   uint32_t k[kUpVecs][4];
-  if (len == (uint32_t)kTile && (reinterpret_cast<uintptr_t>(keys) & kAlign) == 0) {
+  if (len == (uint32_t)kTile && (reinterpret_cast<uintptr_t>(keys + base) & kAlign) == 0) {
 #pragma unroll
     for (int j = 0; j < kUpVecs; ++j) load_key4(keys + base, (uint64_t)j * kUpBlock + tid, k[j]);
   } else {
@@ -208,7 +212,7 @@ __device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32
   uint32_t c = 0;
 #pragma unroll
   for (int ww = 0; ww < kUpWaves; ++ww) c += s_hist[ww][tid];
-  table[(uint64_t)tid * ntiles + tile] = c;
+  table[(uint64_t)tid * stride + col] = c;
   if (kOrAnd && tid == 0) {
     uint32_t o = 0, a = ~0u;
 #pragma unroll
@@ -233,8 +237,9 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
     if (!((active >> pass) & 1u)) return;  // uniform over the grid
     keys = pass_io(buf, active, pass).src_keys;
   }
-  upsweep_tile<kTile, kFirst ? 1 : 2, kFirst>(keys, pass * kRadixBits, xcd_tile(blockIdx.x, ntiles), n, ntiles,
-                                              table, orand);
+  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+  upsweep_tile<kTile, kFirst ? 1 : 2, kFirst>(keys, pass * kRadixBits, tile * kTile, min((uint32_t)kTile, n - tile * kTile),
+                                              table, tile, ntiles, tile, orand);
 }
 
 // Upsweep of a fixed pass (no plan) over uint32 or uint16 keys.  Work-group 0
@@ -244,7 +249,9 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_count(const SK* __restrict__
                                                           uint32_t shift, uint32_t n, uint32_t ntiles,
                                                           uint32_t* __restrict__ reject) {
   if (reject && blockIdx.x == 0 && threadIdx.x == 0) *reject = 0u;
-  upsweep_tile<kTile, kRounds, false>(keys, shift, xcd_tile(blockIdx.x, ntiles), n, ntiles, table, nullptr);
+  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+  upsweep_tile<kTile, kRounds, false>(keys, shift, tile * kTile, min((uint32_t)kTile, n - tile * kTile), table, tile,
+                                      ntiles, tile, nullptr);
 }
 
 // The sort plan from the OR and the AND of every tile's keys: a pass moves
@@ -338,7 +345,7 @@ __device__ __forceinline__ void scatter_load(const IO& io, uint32_t base, uint32
     for (int i = 0; i < kItems; ++i) key[i] = __builtin_nontemporal_load(io.src_keys + base + wbase + i * 64 + lane);
     if (io.implicit_rows) {
 #pragma unroll
-      for (int i = 0; i < kItems; ++i) row[i] = base + wbase + i * 64 + lane;
+      for (int i = 0; i < kItems; ++i) row[i] = base + wbase + i * 64 + lane - io.row_origin;
     } else {
 #pragma unroll
       for (int i = 0; i < kItems; ++i)
@@ -351,7 +358,7 @@ __device__ __forceinline__ void scatter_load(const IO& io, uint32_t base, uint32
       const uint32_t g = base + local;
       const bool valid = local < tile_n;
       key[i] = valid ? (uint32_t)io.src_keys[g] : 0u;
-      row[i] = valid ? (io.implicit_rows ? g : io.src_rows[g]) : 0u;
+      row[i] = valid ? (io.implicit_rows ? g - io.row_origin : io.src_rows[g]) : 0u;
     }
   }
 }
@@ -360,7 +367,7 @@ __device__ __forceinline__ void scatter_load(const IO& io, uint32_t base, uint32
 // (their loads may still be in flight); dstart = the table entry of digit
 // threadIdx.x for this tile.  Starts and ends with a barrier.  With kCheck a
 // key at or above 2^check_shift sets *reject to 1.
-template <int kBlock, int kItems, bool kCheck = false, class IO>
+template <int kBlock, int kItems, bool kCheck = false, bool kTag = false, class IO>
 __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, const IO& io, uint32_t shift,
                                              uint32_t tile_n, uint32_t dstart, const uint32_t (&key)[kItems],
                                              const uint32_t (&row)[kItems], uint32_t check_shift = 32,
@@ -442,7 +449,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
       const uint2 v = L.kr[p];
       const uint32_t k = v.x;
       const uint32_t g = L.dbase[(k >> shift) & (kRadix - 1)] + p;
-      io.dst_keys[g] = (std::remove_pointer_t<decltype(io.dst_keys)>)k;
+      io.dst_keys[g] = (std::remove_pointer_t<decltype(io.dst_keys)>)(kTag ? (k & io.key_and) | io.key_or : k);
       io.dst_rows[g] = v.y;
     }
   }
@@ -551,6 +558,101 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
   return kOk;
 }
 
+// ---------------------------------------------------------------------------------
+// the segmented sort: a batch of requests, keys sorted inside each request
+// ---------------------------------------------------------------------------------
+// Request j owns positions [req_off[j], req_off[j+1]); its tiles are its
+// positions cut at the multiples of kTile, so tile l of request j covers
+// [max(req_off[j], (c0 + l) kTile), min(req_off[j+1], (c0 + l + 1) kTile)) with
+// c0 = req_off[j] / kTile (whole tiles stay aligned).  tile_base[j] is the
+// number of tiles of the requests before j.  The digit table holds request j's
+// counts at 256 tile_base[j] + d ntiles_j + l: scanned in that order, each
+// entry is the position in the batch of the tile's first key with digit d, and
+// no key leaves its request.  Rows are made relative to the request's first
+// position; the last pass writes the key tagged with its request (j <<
+// value_bits | key), which is what the encoder and the per-request split read.
+template <int kTile>
+__global__ __launch_bounds__(256) void k_seg_tiles(const uint32_t* __restrict__ req_off, uint32_t nreq,
+                                                   uint32_t* __restrict__ ntiles) {
+  for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j <= nreq; j += gridDim.x * 256) {
+    uint32_t nt = 0;
+    if (j < nreq && req_off[j + 1] > req_off[j])
+      nt = (req_off[j + 1] + (uint32_t)kTile - 1u) / (uint32_t)kTile - req_off[j] / (uint32_t)kTile;
+    ntiles[j] = nt;
+  }
+}
+
+// The table's length for its scan: 256 entries per tile of the batch.
+__global__ void k_seg_table_len(const uint32_t* __restrict__ tile_base, uint32_t nreq, uint64_t* __restrict__ len) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *len = (uint64_t)kRadix * tile_base[nreq];
+}
+
+struct SegTile {
+  uint32_t j, l, base, len, nt;
+};
+
+// Request and place of tile t < tile_base[nreq]: the last request j with
+// tile_base[j] <= t (empty requests share their successor's base).
+template <int kTile>
+__device__ __forceinline__ SegTile seg_tile(const uint32_t* __restrict__ req_off, const uint32_t* __restrict__ tile_base,
+                                            uint32_t nreq, uint32_t t) {
+  uint32_t lo = 0, hi = nreq;
+  while (hi - lo > 1u) {
+    const uint32_t mid = (lo + hi) / 2u;
+    if (tile_base[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  SegTile s;
+  s.j = lo;
+  s.l = t - tile_base[lo];
+  s.nt = tile_base[lo + 1] - tile_base[lo];
+  const uint32_t r0 = req_off[lo], r1 = req_off[lo + 1], c0 = r0 / (uint32_t)kTile;
+  s.base = max(r0, (c0 + s.l) * (uint32_t)kTile);
+  s.len = min(r1, (c0 + s.l + 1u) * (uint32_t)kTile) - s.base;
+  return s;
+}
+
+template <int kTile, int kRounds, class SK>
+__global__ __launch_bounds__(kUpBlock) void k_seg_count(const SK* __restrict__ keys, uint32_t* __restrict__ table,
+                                                        uint32_t shift, const uint32_t* __restrict__ req_off,
+                                                        const uint32_t* __restrict__ tile_base, uint32_t nreq,
+                                                        uint32_t ub) {
+  const uint32_t t = xcd_tile(blockIdx.x, ub);
+  if (t >= tile_base[nreq]) return;  // uniform over the work-group
+  const SegTile s = seg_tile<kTile>(req_off, tile_base, nreq, t);
+  upsweep_tile<kTile, kRounds, false>(keys, shift, s.base, s.len, table, (uint64_t)kRadix * tile_base[s.j] + s.l, s.nt,
+                                      t, nullptr);
+}
+
+// kCheck (the first pass): a key at or above 2^value_bits flags its request
+// (req_bad[j]) or, without req_bad, the batch (*bad).  kTag (the last pass):
+// keys are written as j << value_bits | key.
+template <int kBlock, int kItems, bool kCheck, bool kTag, class SK, class DK>
+__global__ __launch_bounds__(kBlock) void k_seg_scatter(PassIoT<SK, DK> io, const uint32_t* __restrict__ table,
+                                                        uint32_t shift, const uint32_t* __restrict__ req_off,
+                                                        const uint32_t* __restrict__ tile_base, uint32_t nreq,
+                                                        uint32_t ub, uint32_t value_bits, uint32_t* __restrict__ bad,
+                                                        uint32_t* __restrict__ req_bad) {
+  constexpr int kTile = kBlock * kItems;
+  __shared__ ScatterLds<kBlock, kItems> L;
+  const uint32_t t = xcd_tile(blockIdx.x, ub);
+  if (t >= tile_base[nreq]) return;  // uniform over the work-group
+  const SegTile s = seg_tile<kTile>(req_off, tile_base, nreq, t);
+  const uint32_t dstart =
+      threadIdx.x < kRadix ? table[(uint64_t)kRadix * tile_base[s.j] + (uint64_t)threadIdx.x * s.nt + s.l] : 0u;
+  io.row_origin = req_off[s.j];
+  if (kTag) {
+    io.key_and = value_bits < 32 ? (1u << value_bits) - 1u : ~0u;
+    io.key_or = value_bits < 32 ? s.j << value_bits : 0u;
+  }
+  uint32_t key[kItems], row[kItems];
+  scatter_load<kBlock, kItems>(io, s.base, s.len, key, row);
+  scatter_tile<kBlock, kItems, kCheck, kTag>(L, io, shift, s.len, dstart, key, row, value_bits,
+                                             req_bad ? req_bad + s.j : bad);
+}
+
 // The narrow-key sort: keys below 2^value_bits, value_bits <= 16, rows
 // 0..n-1.  ceil(value_bits / 8) fixed passes (no plan, no skipped launches);
 // from the first pass on the keys are stored as uint16 (6 bytes per pair
@@ -604,9 +706,83 @@ int sort16_with_shape(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t*
   return check_launch(env, "radix_scatter launch");
 }
 
+// The segmented sort of a batch (values below 2^value_bits, value_bits <= 16):
+// uint16 keys between passes, request-relative rows, tagged uint32 keys out.
+int seg_sort(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
+             uint32_t value_bits, uint32_t* skeys, uint32_t* srows, uint32_t* bad, uint32_t* req_bad) {
+  constexpr int kBlock = kShapes[0].block, kItems = kShapes[0].items, kTile = kBlock * kItems;
+  const uint32_t passes = (value_bits + kRadixBits - 1) / kRadixBits;
+  const uint64_t ub64 = (n + kTile - 1) / kTile + nreq;  // tiles: at most one more per request
+  if (ub64 >= (1ull << 31)) return env.fail(kErrArg, "segmented sort: too many tiles");
+  const uint32_t ub = (uint32_t)ub64, nn = (uint32_t)n;
+  uint32_t* ntiles = static_cast<uint32_t*>(env.scratch(4ull * (nreq + 1)));
+  uint32_t* tile_base = static_cast<uint32_t*>(env.scratch(4ull * (nreq + 1)));
+  uint64_t* tlen = static_cast<uint64_t*>(env.scratch(8));
+  uint32_t* table = static_cast<uint32_t*>(env.scratch((uint64_t)kRadix * ub * 4));
+  uint32_t* offs = static_cast<uint32_t*>(env.scratch((uint64_t)kRadix * ub * 4));
+  uint16_t* kb = passes > 1 ? static_cast<uint16_t*>(env.scratch(2 * n)) : nullptr;
+  uint32_t* rb = passes > 1 ? static_cast<uint32_t*>(env.scratch(4 * n)) : nullptr;
+  if (!ntiles || !tile_base || !tlen || !table || !offs || (passes > 1 && (!kb || !rb)))
+    return env.fail(kErrOom, "segmented sort: scratch");
+  int rc;
+  env.prof_begin("seg_tiles");
+  k_seg_tiles<kTile><<<dim3(std::min<uint32_t>((nreq + 256) / 256, 1024)), dim3(256), 0, env.stream()>>>(req_off, nreq,
+                                                                                                      ntiles);
+  env.prof_end("seg_tiles");
+  if ((rc = check_launch(env, "seg_tiles launch"))) return rc;
+  if ((rc = launch_exclusive_scan(env, ntiles, tile_base, nreq + 1ull, nullptr))) return rc;
+  k_seg_table_len<<<dim3(1), dim3(64), 0, env.stream()>>>(tile_base, nreq, tlen);
+  if ((rc = check_launch(env, "seg_table_len launch"))) return rc;
+  const uint64_t tcap = (uint64_t)kRadix * ub;
+  // pass 0: uint32 values in (checked), uint16 keys out -- or tagged keys if it is the only pass
+  env.prof_begin("radix_upsweep0");
+  k_seg_count<kTile, 1, uint32_t><<<dim3(ub), dim3(kUpBlock), 0, env.stream()>>>(values, table, 0, req_off, tile_base,
+                                                                                  nreq, ub);
+  env.prof_end("radix_upsweep0");
+  if ((rc = check_launch(env, "seg_count launch"))) return rc;
+  if ((rc = launch_exclusive_scan(env, table, offs, tcap, tlen))) return rc;
+  env.prof_begin("radix_scatter");
+  if (passes == 1) {
+    PassIoT<uint32_t, uint32_t> io{values, nullptr, skeys, srows, true};
+    k_seg_scatter<kBlock, kItems, true, true><<<dim3(ub), dim3(kBlock), 0, env.stream()>>>(
+        io, offs, 0u, req_off, tile_base, nreq, ub, value_bits, bad, req_bad);
+  } else {
+    PassIoT<uint32_t, uint16_t> io{values, nullptr, kb, rb, true};
+    k_seg_scatter<kBlock, kItems, true, false><<<dim3(ub), dim3(kBlock), 0, env.stream()>>>(
+        io, offs, 0u, req_off, tile_base, nreq, ub, value_bits, bad, req_bad);
+  }
+  env.prof_end("radix_scatter");
+  if ((rc = check_launch(env, "seg_scatter launch"))) return rc;
+  if (passes == 1) return kOk;
+  // pass 1: uint16 keys in, tagged uint32 keys out
+  env.prof_begin("radix_upsweep");
+  k_seg_count<kTile, 2, uint16_t><<<dim3(ub), dim3(kUpBlock), 0, env.stream()>>>(kb, table, kRadixBits, req_off,
+                                                                                  tile_base, nreq, ub);
+  env.prof_end("radix_upsweep");
+  if ((rc = check_launch(env, "seg_count launch"))) return rc;
+  if ((rc = launch_exclusive_scan(env, table, offs, tcap, tlen))) return rc;
+  PassIoT<uint16_t, uint32_t> io1{kb, rb, skeys, srows, false};
+  env.prof_begin("radix_scatter");
+  k_seg_scatter<kBlock, kItems, false, true><<<dim3(ub), dim3(kBlock), 0, env.stream()>>>(
+      io1, offs, kRadixBits, req_off, tile_base, nreq, ub, value_bits, bad, req_bad);
+  env.prof_end("radix_scatter");
+  return check_launch(env, "seg_scatter launch");
+}
+
 }  // namespace
 
 int sort_shape_count() { return kNumShapes; }
+
+int launch_radix_sort_segments(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
+                               uint32_t value_bits, uint32_t* skeys, uint32_t* srows, uint32_t* bad,
+                               uint32_t* req_bad) {
+  if (n == 0) return kOk;
+  if (!values || !req_off || !skeys || !srows || !bad || nreq == 0)
+    return env.fail(kErrArg, "segmented sort: null buffer");
+  if (value_bits == 0 || value_bits > 16) return env.fail(kErrArg, "segmented sort: value_bits must be 1..16");
+  if (n >= (1ull << 31)) return env.fail(kErrArg, "segmented sort: n must be below 2^31");
+  return seg_sort(env, values, n, req_off, nreq, value_bits, skeys, srows, bad, req_bad);
+}
 
 const uint32_t* sort_plan_keys_or(Env& env) {
   return reinterpret_cast<const uint32_t*>(static_cast<const char*>(env.arena()->plan) + offsetof(SortPlan, keys_or));

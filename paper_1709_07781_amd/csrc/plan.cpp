@@ -129,7 +129,8 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
   p->value_bits = value_bits;
   // ---- one allocation: input, table, outputs, look-back state, scratch arena -----------
   const uint64_t n1 = n ? n : 1;
-  const uint64_t sort_tiles = (n + 8191) / 8192, enc_tiles = (n + 4095) / 4096;
+  // the segmented sort cuts tiles at request boundaries: at most one more per request
+  const uint64_t sort_tiles = (n + 8191) / 8192 + nreq, enc_tiles = (n + 4095) / 4096;
   const uint64_t scan_tiles = 2 * ((256 * sort_tiles + 4095) / 4096) + 2;  // scan tiles hold >= 4096 entries
   const uint64_t arena_bytes = 24 * n1 + 16ull * nreq + 2 * sort_tiles * 2064 + 8 * enc_tiles + (64ull << 10);
   uint64_t off = 0;

@@ -154,3 +154,18 @@ def test_batch_tagged_path_rejects_wide_values(sess):
     good = v & np.uint32(0xFFF)
     got = sess.wah_batch(good, off, 12)
     _check(got, off, good, oracle.default())
+
+
+@pytest.mark.parametrize("bits", [4, 8, 9, 12, 16, 17, 20])
+def test_batch_value_widths_and_tile_edges(sess, bits):
+    """Values of 1..16 bits take the segmented sort (tiles cut at request
+    boundaries and at the multiples of 8192, one or two passes over 16-bit
+    keys); wider values the tagged sort.  Requests straddle tile edges, hold
+    exactly a tile, are empty or hold one value."""
+    sizes = [0, 1, 8191, 8192, 8193, 3, 0, 20000, 16384 + 5, 7, 0, 40000, 1, 8192 * 3 - 2]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    v = workloads.uniform_values(30 + bits, int(off[-1]), 1 << bits)
+    v[:: 97] = (1 << bits) - 1  # the largest value appears in most requests
+    res = sess.wah_batch(v, off, bits)
+    _check(res, off, v, oracle.default())
