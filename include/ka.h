@@ -164,6 +164,14 @@ KA_API int ka_system_synchronize(ka_system* sys);
 KA_API int ka_system_stream(ka_system* sys, uint32_t i, void** stream);
 /* Device memory currently held by the system, in bytes (in use and cached). */
 KA_API int ka_system_memory(ka_system* sys, uint64_t* in_use, uint64_t* reserved);
+/* How many times a device-resident length (the count a kernel produced, e.g.
+ * compact_nonzero_u32's) was read back on the host, each a wait for its
+ * producer: by ka_ref_info, ka_ref_read, ka_receive of a value output,
+ * ka_batch_run of a reference input, or an actor that must plan its launch on
+ * the host (wah_index_batch).  Sorts,
+ * encoders, scans, compaction and queries read such counts on the device, so a
+ * composition of them adds nothing here.  Never waits. */
+KA_API int ka_system_length_reads(ka_system* sys, uint64_t* count);
 
 /* ---- programs (Sec. 3.2: kernels looked up by name) ------------------------------ */
 /* The built-in kernels, compiled ahead of time for gfx950:

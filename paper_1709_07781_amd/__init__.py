@@ -126,6 +126,7 @@ SIGNATURES = {
     "ka_system_synchronize": [_P],
     "ka_system_stream": [_P, _U32, _PP],
     "ka_system_memory": [_P, _U64P, _U64P],
+    "ka_system_length_reads": [_P, _U64P],
     "ka_program_builtin": [_P, _PP],
     "ka_program_load": [_P, ctypes.c_char_p, _PP],
     "ka_program_release": [_P],

@@ -80,7 +80,7 @@ int run_sort_rows(LaunchCtx& c) {
   if (c.n > k.cap || c.n > sk.cap || c.n > sr.cap)
     return c.env->fail(KA_E_ARG, "radix_sort_rows_u32: range exceeds a buffer");
   return launch_radix_sort_pairs(*c.env, static_cast<const uint32_t*>(k.ptr), nullptr, static_cast<uint32_t*>(sk.ptr),
-                                 static_cast<uint32_t*>(sr.ptr), c.n);
+                                 static_cast<uint32_t*>(sr.ptr), c.n, 0, c.d_n);
 }
 
 // radix_sort_pairs_u32: (in keys; in rows; out skeys; out srows)
@@ -92,7 +92,7 @@ int run_sort_pairs(LaunchCtx& c) {
   if (c.n > k.cap || c.n > r.cap || c.n > sk.cap || c.n > sr.cap)
     return c.env->fail(KA_E_ARG, "radix_sort_pairs_u32: range exceeds a buffer");
   return launch_radix_sort_pairs(*c.env, static_cast<const uint32_t*>(k.ptr), static_cast<const uint32_t*>(r.ptr),
-                                 static_cast<uint32_t*>(sk.ptr), static_cast<uint32_t*>(sr.ptr), c.n);
+                                 static_cast<uint32_t*>(sk.ptr), static_cast<uint32_t*>(sr.ptr), c.n, 0, c.d_n);
 }
 
 // wah_encode_sorted: (in skeys; in srows; out keys; out offsets; out words)
@@ -104,7 +104,8 @@ int run_wah(LaunchCtx& c) {
   return launch_wah_encode(*c.env, static_cast<const uint32_t*>(a[0].ptr), static_cast<const uint32_t*>(a[1].ptr), c.n,
                            static_cast<uint32_t*>(a[2].ptr), static_cast<uint32_t*>(a[3].ptr),
                            static_cast<uint32_t*>(a[4].ptr), const_cast<uint64_t*>(a[2].d_len),
-                           const_cast<uint64_t*>(a[3].d_len), const_cast<uint64_t*>(a[4].d_len));
+                           const_cast<uint64_t*>(a[3].d_len), const_cast<uint64_t*>(a[4].d_len), nullptr, 32, nullptr, 32,
+                           c.d_n);
 }
 
 // wah_index: (in values; priv value_bits [, format]; out keys; out offsets;
@@ -133,6 +134,7 @@ int run_wah_index(LaunchCtx& c) {
   uint64_t* lo = const_cast<uint64_t*>(a[3].d_len);
   uint64_t* lw = const_cast<uint64_t*>(a[4].d_len);
   const uint32_t fmt = (uint32_t)a[1].priv[1];
+  const uint64_t* d_n = c.d_n;  // the count on the device (n is then the capacity)
   if (fmt > 2) return env.fail(KA_E_ARG, "wah_index: format must be 0 (paper), 1 (canonical) or 2 (PLWAH)");
   if (fmt == 2 && n > 31ull * 0x1FFFFFFull)
     return env.fail(KA_E_ARG, "wah_index: PLWAH fill lengths (25 bits) cover at most 31 * (2^25 - 1) rows");
@@ -145,32 +147,32 @@ int run_wah_index(LaunchCtx& c) {
       uint16_t* sk = static_cast<uint16_t*>(env.scratch(2 * n));
       uint32_t* sr = static_cast<uint32_t*>(env.scratch(4 * n));
       if (!sk || !sr) return env.fail(KA_E_OOM, "wah_index: scratch");
-      if ((rc = launch_radix_sort_rows16(env, values, sk, sr, n, bits, reject))) return rc;
-      return launch_wah_encode_format16(env, sk, sr, n, fmt, keys, offsets, words, lk, lo, lw, reject);
+      if ((rc = launch_radix_sort_rows16(env, values, sk, sr, n, bits, reject, 0, d_n))) return rc;
+      return launch_wah_encode_format16(env, sk, sr, n, fmt, keys, offsets, words, lk, lo, lw, reject, d_n);
     }
     uint32_t* sk = static_cast<uint32_t*>(env.scratch(4 * n));
     uint32_t* sr = static_cast<uint32_t*>(env.scratch(4 * n));
     if (!sk || !sr) return env.fail(KA_E_OOM, "wah_index: scratch");
     if ((rc = launch_zero_u32(env, reject))) return rc;
-    if ((rc = launch_radix_sort_pairs(env, values, nullptr, sk, sr, n))) return rc;
+    if ((rc = launch_radix_sort_pairs(env, values, nullptr, sk, sr, n, 0, d_n))) return rc;
     if (bits >= 17 && bits <= 31 && (rc = launch_reject_above(env, sort_plan_keys_or(env), bits, reject))) return rc;
-    return launch_wah_encode_format(env, sk, sr, n, fmt, keys, offsets, words, lk, lo, lw, reject);
+    return launch_wah_encode_format(env, sk, sr, n, fmt, keys, offsets, words, lk, lo, lw, reject, d_n);
   }
   if (bits >= 1 && bits <= 16) {
     uint32_t* reject = static_cast<uint32_t*>(env.scratch(4));
     uint16_t* sk = static_cast<uint16_t*>(env.scratch(2 * n));
     uint32_t* sr = static_cast<uint32_t*>(env.scratch(4 * n));
     if (!reject || !sk || !sr) return env.fail(KA_E_OOM, "wah_index: scratch");
-    if ((rc = launch_radix_sort_rows16(env, values, sk, sr, n, bits, reject))) return rc;
-    return launch_wah_encode16(env, sk, sr, n, keys, offsets, words, lk, lo, lw, reject, 0);
+    if ((rc = launch_radix_sort_rows16(env, values, sk, sr, n, bits, reject, 0, d_n))) return rc;
+    return launch_wah_encode16(env, sk, sr, n, keys, offsets, words, lk, lo, lw, reject, 0, d_n);
   }
   uint32_t* sk = static_cast<uint32_t*>(env.scratch(4 * n));
   uint32_t* sr = static_cast<uint32_t*>(env.scratch(4 * n));
   if (!sk || !sr) return env.fail(KA_E_OOM, "wah_index: scratch");
-  if ((rc = launch_radix_sort_pairs(env, values, nullptr, sk, sr, n))) return rc;
+  if ((rc = launch_radix_sort_pairs(env, values, nullptr, sk, sr, n, 0, d_n))) return rc;
   const bool check = bits >= 17 && bits <= 31;
   return launch_wah_encode(env, sk, sr, n, keys, offsets, words, lk, lo, lw, nullptr, 32,
-                           check ? sort_plan_keys_or(env) : nullptr, check ? bits : 32u);
+                           check ? sort_plan_keys_or(env) : nullptr, check ? bits : 32u, d_n);
 }
 
 // wah_lookup: (in queries; in keys; out slots) -- slots[i] = the index d of
@@ -180,7 +182,8 @@ int run_lookup(LaunchCtx& c) {
   auto& a = *c.args;
   if (c.n > a[0].cap || c.n > a[2].cap) return c.env->fail(KA_E_ARG, "wah_lookup: range exceeds a buffer");
   return launch_wah_lookup(*c.env, static_cast<const uint32_t*>(a[1].ptr), a[1].d_len ? a[1].cap : a[1].len,
-                           a[1].d_len, static_cast<const uint32_t*>(a[0].ptr), c.n, static_cast<uint32_t*>(a[2].ptr));
+                           a[1].d_len, static_cast<const uint32_t*>(a[0].ptr), c.n, static_cast<uint32_t*>(a[2].ptr),
+                           c.d_n);
 }
 
 // wah_decode: (in words; priv format, ngroups; out groups) -- one bitmap as
@@ -254,27 +257,27 @@ std::vector<BuiltinKernel> make_registry() {
   r.push_back({"exclusive_scan_u32", {{KA_IN, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_host, false, run_scan});
   r.push_back({"compact_nonzero_u32", {{KA_IN, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_compact, false,
                run_compact});
-  r.push_back({"radix_sort_rows_u32", {{KA_IN, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_host, true,
+  r.push_back({"radix_sort_rows_u32", {{KA_IN, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_host, false,
                run_sort_rows});
   r.push_back({"radix_sort_pairs_u32",
                {{KA_IN, KA_U32}, {KA_IN, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}},
                cap_same,
                len_host,
-               true,
+               false,
                run_sort_pairs});
   r.push_back({"wah_encode_sorted",
                {{KA_IN, KA_U32}, {KA_IN, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}},
                cap_wah,
                len_wah,
-               true,
+               false,
                run_wah});
   r.push_back({"wah_index",
                {{KA_IN, KA_U32}, {KA_PRIV, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}, {KA_OUT, KA_U32}},
                cap_wah_index,
                len_wah,
-               true,
+               false,
                run_wah_index});
-  r.push_back({"wah_lookup", {{KA_IN, KA_U32}, {KA_IN, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_host, true,
+  r.push_back({"wah_lookup", {{KA_IN, KA_U32}, {KA_IN, KA_U32}, {KA_OUT, KA_U32}}, cap_same, len_host, false,
                run_lookup});
   r.push_back({"wah_decode", {{KA_IN, KA_U32}, {KA_PRIV, KA_U32}, {KA_OUT, KA_U32}}, cap_decode, len_decode, false,
                run_decode});

@@ -65,7 +65,7 @@ int launch_exclusive_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t 
 int launch_compact_nonzero(Env& env, const uint32_t* in, uint32_t* out, uint64_t n_cap, const uint64_t* d_n,
                            uint64_t* d_out_len);
 int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows, uint32_t* skeys,
-                            uint32_t* srows, uint64_t n, int shape = 0);
+                            uint32_t* srows, uint64_t n, int shape = 0, const uint64_t* d_n = nullptr);
 // Number of tile shapes launch_radix_sort_pairs offers (shape 0 is the default).
 int sort_shape_count();
 // Sort of a batch of requests (request j: values[req_off[j] .. req_off[j+1]),
@@ -84,24 +84,27 @@ const uint32_t* sort_plan_keys_or(Env& env);
 // 1..16, with uint16 sorted keys; a key at or above 2^value_bits sets
 // *reject to 1 (0 otherwise; *reject is device memory).
 int launch_radix_sort_rows16(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t* srows, uint64_t n,
-                             uint32_t value_bits, uint32_t* reject, int shape = 0);
+                             uint32_t value_bits, uint32_t* reject, int shape = 0, const uint64_t* d_n = nullptr);
 // WAH encoder over sorted pairs.  reject_flag, when given, voids the result
 // (every output length 0) if (*reject_flag >> reject_shift) != 0 once the
 // earlier kernels of the stream have run.
 int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                       uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
                       uint64_t* d_len_words, const uint32_t* req_base = nullptr, uint32_t req_shift = 32,
-                      const uint32_t* reject_flag = nullptr, uint32_t reject_shift = 32);
+                      const uint32_t* reject_flag = nullptr, uint32_t reject_shift = 32,
+                      const uint64_t* d_n = nullptr);
 // The same over uint16 sorted keys (values below 2^16).
 int launch_wah_encode16(Env& env, const uint16_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                         uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
-                        uint64_t* d_len_words, const uint32_t* reject_flag = nullptr, uint32_t reject_shift = 32);
+                        uint64_t* d_len_words, const uint32_t* reject_flag = nullptr, uint32_t reject_shift = 32,
+                        const uint64_t* d_n = nullptr);
 // Index words in an encoder format (0 the paper's form, 1 canonical WAH with
 // 1-fills, 2 PLWAH) from sorted pairs, through the group list.  A fill longer
 // than the format's length field sets *reject (every output length 0).
 int launch_wah_encode_format(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t fmt,
                              uint32_t* keys, uint32_t* offsets, uint32_t* words, uint64_t* len_keys,
-                             uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject);
+                             uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject,
+                             const uint64_t* d_n = nullptr);
 // One bitmap (m words, the count on the device when m_len is given) decoded
 // into ngroups 31-bit group words; more groups than ngroups sets *reject.
 int launch_wah_decode(Env& env, const uint32_t* words, uint64_t m_cap, const uint64_t* m_len, uint32_t fmt,
@@ -112,11 +115,13 @@ int launch_wah_combine(Env& env, const uint32_t* a, uint64_t a_cap, const uint64
                        uint64_t b_cap, const uint64_t* b_len, uint32_t in_fmt, uint32_t ngroups, uint32_t op,
                        uint32_t out_fmt, uint32_t* words, uint64_t* len_words, uint32_t* reject);
 // slots[i] = d with keys[d] == queries[i], or 0xFFFFFFFF (keys ascending).
+// q_len, when given, is the query count on the device (at most q).
 int launch_wah_lookup(Env& env, const uint32_t* keys, uint64_t d_cap, const uint64_t* d_len, const uint32_t* queries,
-                      uint64_t q, uint32_t* slots);
+                      uint64_t q, uint32_t* slots, const uint64_t* q_len = nullptr);
 int launch_wah_encode_format16(Env& env, const uint16_t* skeys, const uint32_t* srows, uint64_t n, uint32_t fmt,
                                uint32_t* keys, uint32_t* offsets, uint32_t* words, uint64_t* len_keys,
-                               uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject);
+                               uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject,
+                               const uint64_t* d_n = nullptr);
 int launch_zero_u32(Env& env, uint32_t* p);
 // *reject = 1 if (*keys_or >> bits) != 0 (bits < 32).
 int launch_reject_above(Env& env, const uint32_t* keys_or, uint32_t bits, uint32_t* reject);

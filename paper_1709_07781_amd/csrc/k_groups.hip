@@ -58,8 +58,9 @@ uint32_t grid_for(uint64_t cap) {
 // head[i] = 1 if pair i starts a group (first pair, new key or new chunk).
 template <class KeyT>
 __global__ __launch_bounds__(kBlock) void k_group_heads(const KeyT* __restrict__ skeys,
-                                                        const uint32_t* __restrict__ srows, uint32_t n,
-                                                        uint32_t* __restrict__ head) {
+                                                        const uint32_t* __restrict__ srows, uint32_t n_cap,
+                                                        const uint64_t* __restrict__ d_n, uint32_t* __restrict__ head) {
+  const uint32_t n = dev_count(n_cap, d_n);
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     bool h = i == 0;
     if (!h) h = skeys[i] != skeys[i - 1] || srows[i] / kRows != srows[i - 1] / kRows;
@@ -72,11 +73,13 @@ __global__ __launch_bounds__(kBlock) void k_group_heads(const KeyT* __restrict__
 // The last pair writes the group count.
 template <class KeyT>
 __global__ __launch_bounds__(kBlock) void k_group_write(const KeyT* __restrict__ skeys,
-                                                        const uint32_t* __restrict__ srows, uint32_t n,
+                                                        const uint32_t* __restrict__ srows, uint32_t n_cap,
+                                                        const uint64_t* __restrict__ d_n,
                                                         const uint32_t* __restrict__ head,
                                                         const uint32_t* __restrict__ gpos,
                                                         uint32_t* __restrict__ gkey, uint32_t* __restrict__ gchunk,
                                                         uint32_t* __restrict__ glit, uint64_t* __restrict__ k_len) {
+  const uint32_t n = dev_count(n_cap, d_n);
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     if (i == n - 1) *k_len = (uint64_t)gpos[i] + head[i];
     if (!head[i]) continue;
@@ -333,9 +336,10 @@ __global__ __launch_bounds__(kBlock) void k_nonempty_groups(const uint32_t* __re
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_lookup(const uint32_t* __restrict__ keys, uint64_t dcap,
                                                    const uint64_t* __restrict__ d_len,
-                                                   const uint32_t* __restrict__ queries, uint32_t q,
+                                                   const uint32_t* __restrict__ queries, uint32_t q_cap,
+                                                   const uint64_t* __restrict__ q_len,
                                                    uint32_t* __restrict__ slots) {
-  const uint32_t D = dev_count(dcap, d_len);
+  const uint32_t D = dev_count(dcap, d_len), q = dev_count(q_cap, q_len);
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < q; i += gridDim.x * kBlock) {
     const uint32_t x = queries[i];
     uint32_t lo = 0, hi = D;  // first key >= x
@@ -417,7 +421,7 @@ int encode_groups(Env& env, uint32_t fmt, const Groups& g, uint64_t cap, const u
 template <class KeyT>
 int encode_format_impl(Env& env, const KeyT* skeys, const uint32_t* srows, uint64_t n, uint32_t fmt, uint32_t* keys,
                        uint32_t* offsets, uint32_t* words, uint64_t* len_keys, uint64_t* len_offsets,
-                       uint64_t* len_words, uint32_t* reject) {
+                       uint64_t* len_words, uint32_t* reject, const uint64_t* d_n) {
   if (fmt > kFmtPlwah) return env.fail(kErrArg, "unknown WAH format");
   if (!offsets || !len_keys || !len_offsets || !len_words || !reject)
     return env.fail(kErrArg, "wah encoder: null output");
@@ -436,13 +440,13 @@ int encode_format_impl(Env& env, const KeyT* skeys, const uint32_t* srows, uint6
   if (n) {
     const uint32_t grid = grid_for(n), nn = (uint32_t)n;
     env.prof_begin("group_heads");
-    k_group_heads<KeyT><<<dim3(grid), dim3(kBlock), 0, env.stream()>>>(skeys, srows, nn, head);
+    k_group_heads<KeyT><<<dim3(grid), dim3(kBlock), 0, env.stream()>>>(skeys, srows, nn, d_n, head);
     env.prof_end("group_heads");
     if ((rc = check_launch(env, "group_heads launch"))) return rc;
-    if ((rc = launch_exclusive_scan(env, head, gpos, n, nullptr))) return rc;
+    if ((rc = launch_exclusive_scan(env, head, gpos, n, d_n))) return rc;
     env.prof_begin("group_write");
-    k_group_write<KeyT><<<dim3(grid), dim3(kBlock), 0, env.stream()>>>(skeys, srows, nn, head, gpos, gkey, gchunk,
-                                                                       glit, k_len);
+    k_group_write<KeyT><<<dim3(grid), dim3(kBlock), 0, env.stream()>>>(skeys, srows, nn, d_n, head, gpos, gkey,
+                                                                       gchunk, glit, k_len);
     env.prof_end("group_write");
     if ((rc = check_launch(env, "group_write launch"))) return rc;
   }
@@ -452,16 +456,16 @@ int encode_format_impl(Env& env, const KeyT* skeys, const uint32_t* srows, uint6
 
 int launch_wah_encode_format(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t fmt,
                              uint32_t* keys, uint32_t* offsets, uint32_t* words, uint64_t* len_keys,
-                             uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject) {
+                             uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject, const uint64_t* d_n) {
   return encode_format_impl(env, skeys, srows, n, fmt, keys, offsets, words, len_keys, len_offsets, len_words,
-                            reject);
+                            reject, d_n);
 }
 
 int launch_wah_encode_format16(Env& env, const uint16_t* skeys, const uint32_t* srows, uint64_t n, uint32_t fmt,
                                uint32_t* keys, uint32_t* offsets, uint32_t* words, uint64_t* len_keys,
-                               uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject) {
+                               uint64_t* len_offsets, uint64_t* len_words, uint32_t* reject, const uint64_t* d_n) {
   return encode_format_impl(env, skeys, srows, n, fmt, keys, offsets, words, len_keys, len_offsets, len_words,
-                            reject);
+                            reject, d_n);
 }
 
 int launch_reject_above(Env& env, const uint32_t* keys_or, uint32_t bits, uint32_t* reject) {
@@ -536,12 +540,13 @@ int launch_wah_combine(Env& env, const uint32_t* a, uint64_t a_cap, const uint64
 }
 
 int launch_wah_lookup(Env& env, const uint32_t* keys, uint64_t d_cap, const uint64_t* d_len, const uint32_t* queries,
-                      uint64_t q, uint32_t* slots) {
+                      uint64_t q, uint32_t* slots, const uint64_t* q_len) {
   if (q == 0) return kOk;
   if (!queries || !slots || (d_cap && !keys)) return env.fail(kErrArg, "wah lookup: null buffer");
   if (q >= (1ull << 32)) return env.fail(kErrArg, "wah lookup: too many queries");
   env.prof_begin("wah_lookup");
-  k_lookup<<<dim3(grid_for(q)), dim3(kBlock), 0, env.stream()>>>(keys, d_cap, d_len, queries, (uint32_t)q, slots);
+  k_lookup<<<dim3(grid_for(q)), dim3(kBlock), 0, env.stream()>>>(keys, d_cap, d_len, queries, (uint32_t)q, q_len,
+                                                                         slots);
   env.prof_end("wah_lookup");
   return check_launch(env, "lookup launch");
 }

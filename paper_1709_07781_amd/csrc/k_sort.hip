@@ -145,6 +145,14 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles) {
 #endif
 }
 
+// Elements of tile `tile` (kTile each) out of n: n_cap, or the count *d_n
+// written on the device by an earlier stage (grids are then sized by the
+// capacity and the tiles past the count are empty).
+__device__ __forceinline__ uint32_t tile_len(uint32_t tile, uint32_t kTile, uint32_t n_cap, const uint64_t* d_n) {
+  const uint32_t n = (uint32_t)device_count(n_cap, d_n), base = tile * kTile;
+  return base < n ? min(kTile, n - base) : 0u;
+}
+
 // ---------------------------------------------------------------------------------
 // upsweep: digit counts of one tile into the digit-major table
 // ---------------------------------------------------------------------------------
@@ -230,7 +238,8 @@ __device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32
 template <bool kFirst, int kTile>
 __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, const SortPlan* __restrict__ plan,
                                                             uint32_t* __restrict__ table, uint32_t* __restrict__ orand,
-                                                            uint32_t pass, uint32_t n, uint32_t ntiles) {
+                                                            uint32_t pass, uint32_t n_cap, uint32_t ntiles,
+                                                            const uint64_t* __restrict__ d_n) {
   const uint32_t* keys = buf.keys_in;
   if (!kFirst) {
     const uint32_t active = plan->active;
@@ -238,7 +247,7 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
     keys = pass_io(buf, active, pass).src_keys;
   }
   const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-  upsweep_tile<kTile, kFirst ? 1 : 2, kFirst>(keys, pass * kRadixBits, tile * kTile, min((uint32_t)kTile, n - tile * kTile),
+  upsweep_tile<kTile, kFirst ? 1 : 2, kFirst>(keys, pass * kRadixBits, tile * kTile, tile_len(tile, kTile, n_cap, d_n),
                                               table, tile, ntiles, tile, orand);
 }
 
@@ -246,11 +255,12 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
 // of the first pass clears *reject.
 template <int kTile, int kRounds, class SK>
 __global__ __launch_bounds__(kUpBlock) void k_radix_count(const SK* __restrict__ keys, uint32_t* __restrict__ table,
-                                                          uint32_t shift, uint32_t n, uint32_t ntiles,
-                                                          uint32_t* __restrict__ reject) {
+                                                          uint32_t shift, uint32_t n_cap, uint32_t ntiles,
+                                                          uint32_t* __restrict__ reject,
+                                                          const uint64_t* __restrict__ d_n) {
   if (reject && blockIdx.x == 0 && threadIdx.x == 0) *reject = 0u;
   const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-  upsweep_tile<kTile, kRounds, false>(keys, shift, tile * kTile, min((uint32_t)kTile, n - tile * kTile), table, tile,
+  upsweep_tile<kTile, kRounds, false>(keys, shift, tile * kTile, tile_len(tile, kTile, n_cap, d_n), table, tile,
                                       ntiles, tile, nullptr);
 }
 
@@ -460,7 +470,8 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
 template <int kBlock, int kItems>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const SortPlan* __restrict__ plan,
                                                           const uint32_t* __restrict__ table, uint32_t pass,
-                                                          uint32_t n, uint32_t ntiles) {
+                                                          uint32_t n_cap, uint32_t ntiles,
+                                                          const uint64_t* __restrict__ d_n) {
   constexpr int kTile = kBlock * kItems;
   __shared__ ScatterLds<kBlock, kItems> L;
   const uint32_t active = plan->active;
@@ -468,7 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   const PassIo io = pass_io(buf, active, pass);
   const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
   const uint32_t base = tile * kTile;
-  const uint32_t tile_n = min((uint32_t)kTile, n - base);
+  const uint32_t tile_n = tile_len(tile, kTile, n_cap, d_n);
+  if (tile_n == 0) return;  // past a device-resident count
   // This tile's output position for each digit: loaded first, used last.
   const uint32_t dstart = threadIdx.x < kRadix ? table[(uint64_t)threadIdx.x * ntiles + tile] : 0u;
   uint32_t key[kItems], row[kItems];
@@ -481,13 +493,15 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
 // 2^check_shift sets *reject.
 template <int kBlock, int kItems, bool kCheck, class SK, class DK>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter_fixed(PassIoT<SK, DK> io, const uint32_t* __restrict__ table,
-                                                                uint32_t shift, uint32_t n, uint32_t ntiles,
-                                                                uint32_t check_shift, uint32_t* __restrict__ reject) {
+                                                                uint32_t shift, uint32_t n_cap, uint32_t ntiles,
+                                                                uint32_t check_shift, uint32_t* __restrict__ reject,
+                                                                const uint64_t* __restrict__ d_n) {
   constexpr int kTile = kBlock * kItems;
   __shared__ ScatterLds<kBlock, kItems> L;
   const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
   const uint32_t base = tile * kTile;
-  const uint32_t tile_n = min((uint32_t)kTile, n - base);
+  const uint32_t tile_n = tile_len(tile, kTile, n_cap, d_n);
+  if (tile_n == 0) return;  // past a device-resident count
   const uint32_t dstart = threadIdx.x < kRadix ? table[(uint64_t)threadIdx.x * ntiles + tile] : 0u;
   uint32_t key[kItems], row[kItems];
   scatter_load<kBlock, kItems>(io, base, tile_n, key, row);
@@ -500,7 +514,7 @@ namespace {
 
 template <int kBlock, int kItems>
 int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32_t* skeys, uint32_t* srows,
-                    uint64_t n) {
+                    uint64_t n, const uint64_t* d_n) {
   constexpr int kTile = kBlock * kItems;
   SortPlan* plan = reinterpret_cast<SortPlan*>(env.arena()->plan);
   const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
@@ -526,7 +540,7 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
     if (pass == 0) {
       env.prof_begin("radix_upsweep0");
       k_radix_upsweep<true, kTile><<<dim3(g_up0), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand, pass,
-                                                                                      nn, ntiles);
+                                                                                      nn, ntiles, d_n);
       env.prof_end("radix_upsweep0");
       int rc = check_launch(env, "radix_upsweep launch");
       if (rc) return rc;
@@ -538,7 +552,7 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
     } else {
       env.prof_begin("radix_upsweep");
       k_radix_upsweep<false, kTile><<<dim3(g_up), dim3(kUpBlock), 0, env.stream()>>>(buf, plan, table, orand,
-                                                                                       pass, nn, ntiles);
+                                                                                       pass, nn, ntiles, d_n);
       env.prof_end("radix_upsweep");
       int rc = check_launch(env, "radix_upsweep launch");
       if (rc) return rc;
@@ -550,7 +564,7 @@ int sort_with_shape(Env& env, const uint32_t* keys, const uint32_t* rows, uint32
     if (rc) return rc;
     env.prof_begin("radix_scatter");
     k_radix_scatter<kBlock, kItems><<<dim3(g_sc), dim3(kBlock), 0, env.stream()>>>(
-        buf, static_cast<const SortPlan*>(plan), offs, pass, nn, ntiles);
+        buf, static_cast<const SortPlan*>(plan), offs, pass, nn, ntiles, d_n);
     env.prof_end("radix_scatter");
     rc = check_launch(env, "radix_scatter launch");
     if (rc) return rc;
@@ -660,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_scatter(PassIoT<SK, DK> io, cons
 // *reject (cleared by its upsweep); the sort's output is then unspecified.
 template <int kBlock, int kItems>
 int sort16_with_shape(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t* srows, uint64_t n,
-                      uint32_t value_bits, uint32_t* reject) {
+                      uint32_t value_bits, uint32_t* reject, const uint64_t* d_n) {
   constexpr int kTile = kBlock * kItems;
   const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
   const uint32_t nn = (uint32_t)n;
@@ -680,28 +694,28 @@ int sort16_with_shape(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t*
   // pass 0: uint32 values in, uint16 keys out
   env.prof_begin("radix_upsweep0");
   k_radix_count<kTile, 1, uint32_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(keys, table, 0, nn, ntiles,
-                                                                                       reject);
+                                                                                       reject, d_n);
   env.prof_end("radix_upsweep0");
   if ((rc = check_launch(env, "radix_count launch"))) return rc;
   if ((rc = launch_exclusive_scan(env, table, offs, tlen, nullptr))) return rc;
   PassIoT<uint32_t, uint16_t> io0{keys, nullptr, passes > 1 ? kb : skeys, passes > 1 ? rb : srows, true};
   env.prof_begin("radix_scatter");
   k_radix_scatter_fixed<kBlock, kItems, true><<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(
-      io0, offs, 0u, nn, ntiles, value_bits, reject);
+      io0, offs, 0u, nn, ntiles, value_bits, reject, d_n);
   env.prof_end("radix_scatter");
   if ((rc = check_launch(env, "radix_scatter launch"))) return rc;
   if (passes == 1) return kOk;
   // pass 1: uint16 keys in and out
   env.prof_begin("radix_upsweep");
   k_radix_count<kTile, 2, uint16_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(kb, table, kRadixBits, nn,
-                                                                                       ntiles, nullptr);
+                                                                                       ntiles, nullptr, d_n);
   env.prof_end("radix_upsweep");
   if ((rc = check_launch(env, "radix_count launch"))) return rc;
   if ((rc = launch_exclusive_scan(env, table, offs, tlen, nullptr))) return rc;
   PassIoT<uint16_t, uint16_t> io1{kb, rb, skeys, srows, false};
   env.prof_begin("radix_scatter");
   k_radix_scatter_fixed<kBlock, kItems, false><<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(
-      io1, offs, kRadixBits, nn, ntiles, 32u, nullptr);
+      io1, offs, kRadixBits, nn, ntiles, 32u, nullptr, d_n);
   env.prof_end("radix_scatter");
   return check_launch(env, "radix_scatter launch");
 }
@@ -789,7 +803,7 @@ const uint32_t* sort_plan_keys_or(Env& env) {
 }
 
 int launch_radix_sort_rows16(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t* srows, uint64_t n,
-                             uint32_t value_bits, uint32_t* reject, int shape) {
+                             uint32_t value_bits, uint32_t* reject, int shape, const uint64_t* d_n) {
   if (!reject) return env.fail(kErrArg, "radix_sort16: null reject flag");
   if (value_bits == 0 || value_bits > 16) return env.fail(kErrArg, "radix_sort16: value_bits must be 1..16");
   if (n == 0) return launch_fill_u32(env, reject, 1, 0);
@@ -797,28 +811,31 @@ int launch_radix_sort_rows16(Env& env, const uint32_t* keys, uint16_t* skeys, ui
   if (n >= (1ull << 31)) return env.fail(kErrArg, "radix_sort16: n must be below 2^31");
   switch (shape) {
     case 0:
-      return sort16_with_shape<kShapes[0].block, kShapes[0].items>(env, keys, skeys, srows, n, value_bits, reject);
+      return sort16_with_shape<kShapes[0].block, kShapes[0].items>(env, keys, skeys, srows, n, value_bits, reject,
+                                                                      d_n);
     case 1:
-      return sort16_with_shape<kShapes[1].block, kShapes[1].items>(env, keys, skeys, srows, n, value_bits, reject);
+      return sort16_with_shape<kShapes[1].block, kShapes[1].items>(env, keys, skeys, srows, n, value_bits, reject,
+                                                                      d_n);
     case 2:
-      return sort16_with_shape<kShapes[2].block, kShapes[2].items>(env, keys, skeys, srows, n, value_bits, reject);
+      return sort16_with_shape<kShapes[2].block, kShapes[2].items>(env, keys, skeys, srows, n, value_bits, reject,
+                                                                      d_n);
     default:
       return env.fail(kErrArg, "radix_sort16: unknown tile shape");
   }
 }
 
 int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows, uint32_t* skeys,
-                            uint32_t* srows, uint64_t n, int shape) {
+                            uint32_t* srows, uint64_t n, int shape, const uint64_t* d_n) {
   if (n == 0) return kOk;
   if (!keys || !skeys || !srows) return env.fail(kErrArg, "radix_sort: null buffer");
   if (n >= (1ull << 31)) return env.fail(kErrArg, "radix_sort: n must be below 2^31");
   switch (shape) {
     case 0:
-      return sort_with_shape<kShapes[0].block, kShapes[0].items>(env, keys, rows, skeys, srows, n);
+      return sort_with_shape<kShapes[0].block, kShapes[0].items>(env, keys, rows, skeys, srows, n, d_n);
     case 1:
-      return sort_with_shape<kShapes[1].block, kShapes[1].items>(env, keys, rows, skeys, srows, n);
+      return sort_with_shape<kShapes[1].block, kShapes[1].items>(env, keys, rows, skeys, srows, n, d_n);
     case 2:
-      return sort_with_shape<kShapes[2].block, kShapes[2].items>(env, keys, rows, skeys, srows, n);
+      return sort_with_shape<kShapes[2].block, kShapes[2].items>(env, keys, rows, skeys, srows, n, d_n);
     default:
       return env.fail(kErrArg, "radix_sort: unknown tile shape");
   }

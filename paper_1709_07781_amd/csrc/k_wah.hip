@@ -160,7 +160,8 @@ struct Reject {
 // launch.
 template <bool kVec, class KeyT>
 __global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const KeyT* __restrict__ skeys,
-                                                         const uint32_t* __restrict__ srows, uint32_t n,
+                                                         const uint32_t* __restrict__ srows, uint32_t n_cap,
+                                                         const uint64_t* __restrict__ d_n,
                                                          uint64_t* __restrict__ status, uint32_t spin_limit,
                                                          uint32_t* __restrict__ out_keys,
                                                          uint32_t* __restrict__ out_offsets,
@@ -178,6 +179,19 @@ __global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const KeyT* __restri
 
   const uint32_t tid = threadIdx.x, tile = blockIdx.x;
   const uint32_t base = tile * kEncTile;
+  // n_cap pairs, or the count written on the device by an earlier stage: the
+  // grid then covers the capacity and the tiles past the count leave at once
+  // (tile 0 of an empty input writes the empty index).
+  const uint32_t n = (uint32_t)device_count(n_cap, d_n);
+  if (base >= n) {
+    if (tile == 0 && tid == 0) {
+      out_offsets[0] = 0;
+      *len_keys = 0;
+      *len_offsets = 1;
+      *len_words = 0;
+    }
+    return;
+  }
   const uint32_t tile_n = min((uint32_t)kEncTile, n - base);
   const uint32_t avail = min((uint32_t)(kEncTile + kLook), n - base);  // readable from base on
 
@@ -379,7 +393,8 @@ __global__ void k_wah_clear(uint64_t* __restrict__ status, uint32_t ntiles) {
 template <class KeyT>
 int encode_impl(Env& env, const KeyT* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys, uint32_t* offsets,
                 uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets, uint64_t* d_len_words,
-                const uint32_t* req_base, uint32_t req_shift, const uint32_t* reject_flag, uint32_t reject_shift) {
+                const uint32_t* req_base, uint32_t req_shift, const uint32_t* reject_flag, uint32_t reject_shift,
+                const uint64_t* d_n) {
   if (!offsets || !d_len_keys || !d_len_offsets || !d_len_words)
     return env.fail(kErrArg, "wah_encode_sorted: null output");
   if (n >= (1ull << 30)) return env.fail(kErrArg, "wah_encode_sorted: n must be below 2^30");
@@ -403,11 +418,11 @@ int encode_impl(Env& env, const KeyT* skeys, const uint32_t* srows, uint64_t n, 
   env.prof_begin("wah_write");
   if (vec)
     k_wah_write<true, KeyT><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(
-        skeys, srows, nn, status, env.spin_limit(), keys, offsets, words, br, rej, d_len_keys, d_len_offsets,
+        skeys, srows, nn, d_n, status, env.spin_limit(), keys, offsets, words, br, rej, d_len_keys, d_len_offsets,
         d_len_words);
   else
     k_wah_write<false, KeyT><<<dim3(ntiles), dim3(kEncBlock), 0, env.stream()>>>(
-        skeys, srows, nn, status, env.spin_limit(), keys, offsets, words, br, rej, d_len_keys, d_len_offsets,
+        skeys, srows, nn, d_n, status, env.spin_limit(), keys, offsets, words, br, rej, d_len_keys, d_len_offsets,
         d_len_words);
   env.prof_end("wah_write");
   return check_launch(env, "wah_write launch");
@@ -418,16 +433,17 @@ int encode_impl(Env& env, const KeyT* skeys, const uint32_t* srows, uint64_t n, 
 int launch_wah_encode(Env& env, const uint32_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                       uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
                       uint64_t* d_len_words, const uint32_t* req_base, uint32_t req_shift,
-                      const uint32_t* reject_flag, uint32_t reject_shift) {
+                      const uint32_t* reject_flag, uint32_t reject_shift, const uint64_t* d_n) {
   return encode_impl(env, skeys, srows, n, keys, offsets, words, d_len_keys, d_len_offsets, d_len_words, req_base,
-                     req_shift, reject_flag, reject_shift);
+                     req_shift, reject_flag, reject_shift, d_n);
 }
 
 int launch_wah_encode16(Env& env, const uint16_t* skeys, const uint32_t* srows, uint64_t n, uint32_t* keys,
                         uint32_t* offsets, uint32_t* words, uint64_t* d_len_keys, uint64_t* d_len_offsets,
-                        uint64_t* d_len_words, const uint32_t* reject_flag, uint32_t reject_shift) {
+                        uint64_t* d_len_words, const uint32_t* reject_flag, uint32_t reject_shift,
+                        const uint64_t* d_n) {
   return encode_impl(env, skeys, srows, n, keys, offsets, words, d_len_keys, d_len_offsets, d_len_words, nullptr, 32u,
-                     reject_flag, reject_shift);
+                     reject_flag, reject_shift, d_n);
 }
 
 }  // namespace ka

@@ -404,6 +404,7 @@ int ref_length(Ref* r, uint64_t* len) {
   }
   int rc = ref_sync(r);
   if (rc) return rc;
+  r->sys->length_reads.fetch_add(1);
   uint64_t v = 0;
   KA_HIP(hipMemcpy(&v, r->d_len, sizeof(v), hipMemcpyDeviceToHost), "length read-back");
   if (v > r->cap) v = r->cap;
@@ -992,6 +993,12 @@ KA_API int ka_system_memory(ka_system* sys, uint64_t* in_use, uint64_t* reserved
   if (!sys) return set_error(KA_E_ARG, "null system");
   if (in_use) *in_use = sys->pool.in_use();
   if (reserved) *reserved = sys->pool.reserved();
+  return KA_OK;
+}
+
+KA_API int ka_system_length_reads(ka_system* sys, uint64_t* count) {
+  if (!sys || !count) return set_error(KA_E_ARG, "null argument");
+  *count = sys->length_reads.load();
   return KA_OK;
 }
 

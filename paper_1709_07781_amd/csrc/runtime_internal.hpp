@@ -106,6 +106,7 @@ struct System {
   Pool pool;
   HostStage stage;
   std::atomic<bool> profile{false};
+  std::atomic<uint64_t> length_reads{0};  // device-resident lengths read back on the host (each waits)
   uint32_t lb_spin = kLbSpinLimit;  // look-back spin limit (KA_LOOKBACK_SPIN)
   std::mutex ev_mu;
   std::vector<hipEvent_t> events;  // pool of timing-disabled events

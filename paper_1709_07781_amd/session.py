@@ -229,6 +229,12 @@ class Session:
         check(lib.ka_system_memory(self.sys, byref(a), byref(b)), "ka_system_memory")
         return a.value, b.value
 
+    def length_reads(self):
+        """Device-resident lengths read back on the host so far."""
+        c = ctypes.c_uint64()
+        check(lib.ka_system_length_reads(self.sys, byref(c)), "ka_system_length_reads")
+        return c.value
+
     def close(self):
         if self.prog:
             lib.ka_program_release(self.prog)
