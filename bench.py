@@ -229,8 +229,9 @@ def bench_batched(args) -> int:
         w0 = time.perf_counter()
         ev0.record(stream)
         for k in range(steps):
+            a = time.perf_counter()
             fn()
-            log(f"[bench] step {k + 1}/{steps}")
+            log(f"[bench] step {k + 1}/{steps} ({1e3 * (time.perf_counter() - a):.2f} ms on the host)")
         ev1.record(stream)
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / steps, (time.perf_counter() - w0) / steps
@@ -244,9 +245,11 @@ def bench_batched(args) -> int:
             for r in sess.request(pipe, ka.ref(views[j]), n_out=3):
                 sess.release_ref(r)
 
-    for _ in range(args.warmup):
-        batched_step()
     plain_step()  # warm-up of the per-request path (pool sizes)
+    sess.profile_reset()
+    for _ in range(args.warmup):  # then of the batched step: its blocks are cached when the timing starts
+        batched_step()
+    torch.cuda.synchronize()
     sess.profile_reset()
     b_ms, b_wall = timed(batched_step, args.steps)
     prof = {k: sess.profile(k) for k in KERNELS + ("batch_keys", "batch_split")}
@@ -276,7 +279,28 @@ def bench_batched(args) -> int:
         return e0.elapsed_time(e1) / steps
 
     g_ms = graph_ms(off, dv, args.steps)
-    log(f"[bench] batched: actor {b_ms:.3f} ms, graph {g_ms:.3f} ms, plain {p_ms:.1f} ms")
+
+    def any_graph_ms(scale, steps):
+        """The same batch through a plan recorded for any batch of up to
+        scale x its values and requests (one graph for every batch)."""
+        plan = BatchPlan(sess, None, 12, autotune=True, any_batch=(int(scale * N), int(scale * nreq), 0))
+        pstream = torch.cuda.ExternalStream(plan.stream_handle())
+        plan.run_batch(dv, off)  # table and values in, every sort variant timed
+        for _ in range(args.warmup):
+            plan.run(None)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(pstream)
+        for _ in range(steps):
+            plan.run(None)
+        e1.record(pstream)
+        torch.cuda.synchronize()
+        plan.close()
+        return e0.elapsed_time(e1) / steps
+
+    ga_ms, ga2_ms = any_graph_ms(1, args.steps), any_graph_ms(1.5, args.steps)
+    log(f"[bench] batched: actor {b_ms:.3f} ms, graph {g_ms:.3f} ms, any-batch graph {ga_ms:.3f} ms "
+        f"(capacities 1.5x: {ga2_ms:.3f} ms), plain {p_ms:.1f} ms")
     # a batch of small requests (sizes 2^4..2^10), where launch work matters more
     soff, sv = workloads.batched_requests(seed=40, count=4096, lo_log2=4, hi_log2=10)
     sdv = sess.upload(sv)
@@ -366,6 +390,10 @@ def bench_batched(args) -> int:
                   "how": "ka_batch_plan, autotuned: the same batch recorded into a HIP graph per sort tile "
                          "shape, the fastest on the first run replayed",
                   "shape": tuned[0][0], "first_run_ms_per_shape": tuned[0][1][:3]},
+        "graph_any_batch": {"ms_per_step": ga_ms, "capacity_1p5x_ms_per_step": ga2_ms,
+                            "how": "ka_batch_plan_create_any: one graph recorded for capacities (values, requests) "
+                                   "that serves any batch within them; capacities equal to this batch, and 1.5 "
+                                   "times it (the grids sized by the capacity, the counts read on the device)"},
         "small_batch": {"workload": "4096 requests, sizes log-uniform in [2^4, 2^10], values below 2^12",
                         "n": int(soff[-1]), "actor_ms": s_ms, "graph_ms": sg_ms, "plain_ms": sp_ms,
                         "shape": tuned[1][0], "first_run_ms_per_shape": tuned[1][1][:3]},
@@ -419,8 +447,10 @@ def bench_served(args) -> int:
         starts = (dseeds % np.uint64(pool_n)).astype(np.int64)
         starts = np.minimum(starts, pool_n - sizes)
         res = {"rate_per_s": rate, "requests": count, "warmup_requests": warm}
-        batched_kw = dict(streams=args.served_streams, max_batch=1024, max_batch_bytes=args.served_batch_mb << 20)
-        for form, kw in (("batched", batched_kw), ("plain", dict(streams=1, max_batch=1))):
+        batched_kw = dict(streams=args.served_streams, max_batch=1024, max_batch_bytes=args.served_batch_mb << 20,
+                          copy_threads=args.served_copy_threads)
+        plain_kw = dict(streams=1, max_batch=1, copy_threads=args.served_copy_threads)
+        for form, kw in (("batched", batched_kw), ("plain", plain_kw)):
             srv = Server(sess, chain_a=a, chain_b=b, **kw)
 
             def run(lo, hi, keep=None):
@@ -513,7 +543,7 @@ def bench_served(args) -> int:
                                "(values below 2^12) / 30% exclusive scan / 30% 8-stage affine chain, host data, "
                                "latency from the scheduled arrival to completion on the host",
                    "rates": rates, "budget_bytes": 64 << 30, "batched_streams": args.served_streams,
-                   "batch_mib": args.served_batch_mb},
+                   "batch_mib": args.served_batch_mb, "copy_threads": args.served_copy_threads or 4},
         "served": rows,
     }
     print(json.dumps(out), flush=True)
@@ -744,6 +774,8 @@ def main() -> int:
     ap.add_argument("--served-max", type=int, default=20000)
     ap.add_argument("--served-streams", type=int, default=2, help="served: streams of the batched server")
     ap.add_argument("--served-batch-mb", type=int, default=16, help="served: MiB of input per batch")
+    ap.add_argument("--served-copy-threads", type=int, default=0,
+                    help="served: threads copying a large payload into pinned memory (0: the library's 4)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run the in-place affine kernel over 2^n words 3 times "
                          "(a plain copy of known size, for scaling the HBM counters)")

@@ -434,6 +434,18 @@ KA_API int ka_wah_batch_result_free(ka_wah_batch_result* res);
 #define KA_PLAN_SHAPE(s) (((uint32_t)(s) + 1u) << 8) /* record sort variant s only (0, 1 or 2) */
 KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_t nreq, uint32_t value_bits,
                                 uint32_t flags, ka_batch_plan** out);
+/* A plan for any batch of at most max_requests requests and max_values values
+ * in all (each request at most max_request_values values; 0 = no bound, and a
+ * bound of 1024 or less selects the one-work-group-per-request path): its
+ * graphs are recorded once for these capacities and serve every batch that
+ * fits.  The request table lives on the device, a batch of fewer requests is
+ * padded with empty ones, and the kernels read the value count from the table.
+ * The plan starts out holding an empty batch; ka_batch_plan_run_batch gives it
+ * the next one.  value_bits plus the bits of max_requests - 1 must not exceed
+ * 32; max_values < 2^30. */
+KA_API int ka_batch_plan_create_any(ka_system* sys, uint64_t max_values, uint32_t max_requests,
+                                    uint32_t max_request_values, uint32_t value_bits, uint32_t flags,
+                                    ka_batch_plan** out);
 /* The device buffer (n uint32) the graph reads the values from. */
 KA_API int ka_batch_plan_input(ka_batch_plan* plan, uint32_t** values_dev);
 /* The plan's hipStream_t (runs are ordered on it). */
@@ -441,8 +453,15 @@ KA_API int ka_batch_plan_stream(ka_batch_plan* plan, void** stream);
 /* Copies values (host memory, or device memory with KA_WAH_INPUT_DEVICE; NULL:
  * the input buffer already holds them) and launches the graph; does not wait. */
 KA_API int ka_batch_plan_run(ka_batch_plan* plan, const uint32_t* values, uint32_t flags);
+/* Any-batch plans: a new batch (req_off: nreq + 1 host entries, as for
+ * ka_wah_batch, nreq <= max_requests, req_off[nreq] <= max_values), then as
+ * ka_batch_plan_run with its values (n = req_off[nreq]); does not wait.
+ * KA_E_STATE for a plan recorded for one batch shape. */
+KA_API int ka_batch_plan_run_batch(ka_batch_plan* plan, const uint32_t* values, const uint32_t* req_off,
+                                   uint32_t nreq, uint32_t flags);
 /* Waits for the last run and returns its outputs as host arrays (free with
- * ka_wah_batch_result_free); KA_E_ARG if a value was at or above 2^value_bits. */
+ * ka_wah_batch_result_free); KA_E_ARG if a value was at or above 2^value_bits.
+ * An any-batch plan returns its last batch's requests only. */
 KA_API int ka_batch_plan_result(ka_batch_plan* plan, ka_wah_batch_result* out);
 /* The tile shape the runs use (-1 before the first run of an autotuned plan)
  * and, for an autotuned plan, the time of its first run with each shape
@@ -467,6 +486,8 @@ typedef struct ka_server_config {
   uint32_t chain_len;        /* affine chain stages and their parameters (a_i odd) */
   const uint32_t* chain_a;
   const uint32_t* chain_b;
+  uint32_t copy_threads;     /* threads that copy a host payload of 1 MiB or more into pinned memory,
+                                the submitting thread included (0 = 4; 1 = the submitting thread alone) */
 } ka_server_config;
 
 typedef struct ka_server_stats {

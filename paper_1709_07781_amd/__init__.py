@@ -101,7 +101,8 @@ class ka_server_config(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("max_batch_bytes", ctypes.c_uint64),
                 ("hbm_budget_bytes", ctypes.c_uint64),
                 ("value_bits", ctypes.c_uint32), ("chain_len", ctypes.c_uint32),
-                ("chain_a", ctypes.POINTER(ctypes.c_uint32)), ("chain_b", ctypes.POINTER(ctypes.c_uint32))]
+                ("chain_a", ctypes.POINTER(ctypes.c_uint32)), ("chain_b", ctypes.POINTER(ctypes.c_uint32)),
+                ("copy_threads", ctypes.c_uint32)]
 
 
 class ka_request(ctypes.Structure):
@@ -162,6 +163,8 @@ SIGNATURES = {
     "ka_batch_plan_input": [_P, _PP],
     "ka_batch_plan_stream": [_P, _PP],
     "ka_batch_plan_run": [_P, _P, _U32],
+    "ka_batch_plan_create_any": [_P, _U64, _U32, _U32, _U32, _U32, _PP],
+    "ka_batch_plan_run_batch": [_P, _P, _P, _U32, _U32],
     "ka_batch_plan_result": [_P, ctypes.POINTER(ka_wah_batch_result)],
     "ka_batch_plan_destroy": [_P],
     "ka_server_create": [_P, ctypes.POINTER(ka_server_config), _PP],

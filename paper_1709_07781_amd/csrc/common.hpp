@@ -139,7 +139,8 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
                      uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
                      uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
                      uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape = 0,
-                     uint32_t max_req = kMaxReqUnknown, uint32_t* req_bad = nullptr);
+                     uint32_t max_req = kMaxReqUnknown, uint32_t* req_bad = nullptr,
+                     const uint64_t* d_n = nullptr);
 // Exclusive scan of each of nreq requests concatenated in in[0..n) (req_off as
 // for the batched index).
 int launch_segmented_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* req_off,
@@ -148,6 +149,8 @@ int launch_fill_u64(Env& env, uint64_t* p, uint64_t count, uint64_t value);
 int launch_fill_u32(Env& env, uint32_t* p, uint64_t count, uint32_t value);
 int launch_set_len(Env& env, uint64_t* d_len, uint64_t value);
 int launch_copy_len(Env& env, uint64_t* dst, const uint64_t* src);
+// *dst = *src (a uint32 count, e.g. a request table's last entry, as a length).
+int launch_len_from_u32(Env& env, uint64_t* dst, const uint32_t* src);
 
 // Status codes shared with ka.h.
 constexpr int kOk = 0, kErrArg = -1, kErrDevice = -5, kErrOom = -6, kErrLaunch = -10;

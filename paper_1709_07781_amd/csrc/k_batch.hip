@@ -81,13 +81,16 @@ struct RebaseOp {  // a batch-wide exclusive scan minus its value at the request
 // once; when there are at most kKeyReqs of them their boundaries are searched
 // in LDS.  Any `over` bit an op reports sets *bad.
 template <class Op>
-__global__ __launch_bounds__(kKeyBlock) void k_batch_map(const uint32_t* in, uint32_t* out, uint32_t n,
+__global__ __launch_bounds__(kKeyBlock) void k_batch_map(const uint32_t* in, uint32_t* out, uint32_t n_cap,
                                                          const uint32_t* __restrict__ req_off, uint32_t nreq, Op op,
-                                                         uint32_t* __restrict__ bad) {
+                                                         uint32_t* __restrict__ bad,
+                                                         const uint64_t* __restrict__ d_n = nullptr) {
   __shared__ uint32_t s_off[kKeyReqs + 1];
   __shared__ uint32_t s_j[2];
   const uint32_t tid = threadIdx.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * kKeyTile;
+  const uint32_t n = (uint32_t)device_count(n_cap, d_n);  // the count on the device: tiles past it leave
+  if (b0 >= n) return;
   const uint32_t len = (uint32_t)min((uint64_t)kKeyTile, n - b0);
   if (tid < 2) s_j[tid] = request_of(req_off, 0, nreq, tid == 0 ? b0 : b0 + len - 1);
   __syncthreads();
@@ -397,7 +400,7 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
                      uint32_t value_bits, uint32_t* keys, uint32_t* offsets, uint32_t* words, uint32_t* key_start,
                      uint32_t* word_start, uint64_t* len_keys, uint64_t* len_offsets, uint64_t* len_words,
                      uint64_t* len_key_start, uint64_t* len_word_start, int sort_shape, uint32_t max_req,
-                     uint32_t* req_bad) {
+                     uint32_t* req_bad, const uint64_t* d_n) {
   if (!req_off || !offsets || !key_start || !word_start || !len_keys || !len_offsets || !len_words || !len_key_start ||
       !len_word_start)
     return env.fail(kErrArg, "wah_index_batch: null buffer");
@@ -458,15 +461,15 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
       const uint64_t blocks = (n + kKeyTile - 1) / kKeyTile;
       env.prof_begin("batch_keys");
       k_batch_map<TagOp><<<dim3((uint32_t)blocks), dim3(kKeyBlock), 0, env.stream()>>>(
-          values, tkeys, nn, req_off, nreq, TagOp{value_bits, req_bad}, bad);
+          values, tkeys, nn, req_off, nreq, TagOp{value_bits, req_bad}, bad, d_n);
       env.prof_end("batch_keys");
       if ((rc = check_launch(env, "batch_keys launch"))) return rc;
-      if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n, sort_shape))) return rc;
+      if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n, sort_shape, d_n))) return rc;
     }
   }
   // The tagged keys are the encoder's keys; rows are (or become) request-relative.
   if ((rc = launch_wah_encode(env, skeys, srows, n, keys, g_off, words, len_keys, g_len, len_words,
-                              segmented ? nullptr : req_off, segmented ? 32u : value_bits)))
+                              segmented ? nullptr : req_off, segmented ? 32u : value_bits, nullptr, 32u, d_n)))
     return rc;
   const uint32_t sgrid = std::min<uint32_t>(kSplitGrid, (nreq + kSplitBlock) / kSplitBlock);
   env.prof_begin("batch_split");

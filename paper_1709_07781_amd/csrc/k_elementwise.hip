@@ -72,6 +72,10 @@ __global__ void k_copy_len(uint64_t* dst, const uint64_t* src) {
   if (threadIdx.x == 0) *dst = *src;
 }
 
+__global__ void k_len_from_u32(uint64_t* dst, const uint32_t* src) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
 inline uint32_t fill_grid(uint64_t count) {
   uint64_t g = (count + 255) / 256;
   if (g > 4096) g = 4096;
@@ -116,6 +120,11 @@ int launch_set_len(Env& env, uint64_t* d_len, uint64_t value) {
 int launch_copy_len(Env& env, uint64_t* dst, const uint64_t* src) {
   k_copy_len<<<dim3(1), dim3(64), 0, env.stream()>>>(dst, src);
   return check_launch(env, "copy_len launch");
+}
+
+int launch_len_from_u32(Env& env, uint64_t* dst, const uint32_t* src) {
+  k_len_from_u32<<<dim3(1), dim3(64), 0, env.stream()>>>(dst, src);
+  return check_launch(env, "len_from_u32 launch");
 }
 
 }  // namespace ka

@@ -109,11 +109,9 @@ __device__ __forceinline__ PassIo pass_io(const PassBuffers& buf, uint32_t activ
 // LDS add of 1 to bin d by every active lane, aggregated over lanes that share
 // a bin: in each of kRounds rounds the first remaining lane's bin takes the
 // count of all remaining lanes with that bin in one add; the lanes left after
-// the rounds add 1 each.  One round suits keys in input order; after an LSD
-// pass a tile's keys are grouped by their lower digits, equal keys sit
-// together and the next digit is concentrated in few values, where a second
-// round removes most same-address adds (measured on Zipf keys: pass 1 -12 us,
-// while a second round in pass 0 costs +9 us).
+// the rounds add 1 each.  One round suits keys in input order (a second round
+// in the first pass cost +9 us on Zipf keys); the later passes count in
+// registers instead (upsweep_tile with kRounds < 0).
 template <int kRounds>
 __device__ __forceinline__ void lds_add_aggregated(uint32_t* bins, uint32_t d, bool valid) {
   uint64_t rest = __ballot(valid);
@@ -194,17 +192,45 @@ __device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32
   for (int i = tid; i < kUpWaves * kRadix; i += kUpBlock) (&s_hist[0][0])[i] = 0;
   __syncthreads();
   uint32_t kor = 0, kand = ~0u;
+  // kRounds < 0: two digits are counted in registers -- 0 and the digit of the
+  // wave's first key -- and every other key adds 1 in LDS.  After the first
+  // pass of an LSD sort a tile's keys share their low digit and the next digit
+  // is concentrated in few values, the most often 0 for small values or else
+  // likely the first key's; the aggregated adds' ballots and lane reads cost
+  // more there (measured on 16-bit Zipf keys: 62 -> 42 us; uniform keys 51 ->
+  // 44 us).
+  uint32_t c0 = 0, ch = 0;
+  const uint32_t hot = (uint32_t)__builtin_amdgcn_readfirstlane((int)((k[0][0] >> shift) & (kRadix - 1)));
 #pragma unroll
   for (int j = 0; j < kUpVecs; ++j)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const bool valid = 4 * (j * kUpBlock + tid) + c < len;
-      lds_add_aggregated<kRounds>(s_hist[w], (k[j][c] >> shift) & (kRadix - 1), valid);
+      if (kRounds < 0) {
+        const uint32_t d = (k[j][c] >> shift) & (kRadix - 1);
+        if (valid) {
+          if (d == hot)
+            ++ch;
+          else if (d == 0)
+            ++c0;
+          else
+            atomicAdd(&s_hist[w][d], 1u);
+        }
+      } else {
+        lds_add_aggregated<(kRounds < 0 ? 0 : kRounds)>(s_hist[w], (k[j][c] >> shift) & (kRadix - 1), valid);
+      }
       if (kOrAnd && valid) {
         kor |= k[j][c];
         kand &= k[j][c];
       }
     }
+  if (kRounds < 0) {
+    const uint32_t z = wave_sum(c0), h = wave_sum(ch);
+    if (lane_id() == 0) {
+      if (z) atomicAdd(&s_hist[w][0], z);
+      if (h) atomicAdd(&s_hist[w][hot], h);
+    }
+  }
   if (kOrAnd) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -247,7 +273,7 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
     keys = pass_io(buf, active, pass).src_keys;
   }
   const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-  upsweep_tile<kTile, kFirst ? 1 : 2, kFirst>(keys, pass * kRadixBits, tile * kTile, tile_len(tile, kTile, n_cap, d_n),
+  upsweep_tile<kTile, kFirst ? 1 : -1, kFirst>(keys, pass * kRadixBits, tile * kTile, tile_len(tile, kTile, n_cap, d_n),
                                               table, tile, ntiles, tile, orand);
 }
 
@@ -707,7 +733,7 @@ int sort16_with_shape(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t*
   if (passes == 1) return kOk;
   // pass 1: uint16 keys in and out
   env.prof_begin("radix_upsweep");
-  k_radix_count<kTile, 2, uint16_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(kb, table, kRadixBits, nn,
+  k_radix_count<kTile, -1, uint16_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(kb, table, kRadixBits, nn,
                                                                                        ntiles, nullptr, d_n);
   env.prof_end("radix_upsweep");
   if ((rc = check_launch(env, "radix_count launch"))) return rc;
@@ -770,7 +796,7 @@ int seg_sort(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_o
   if (passes == 1) return kOk;
   // pass 1: uint16 keys in, tagged uint32 keys out
   env.prof_begin("radix_upsweep");
-  k_seg_count<kTile, 2, uint16_t><<<dim3(ub), dim3(kUpBlock), 0, env.stream()>>>(kb, table, kRadixBits, req_off,
+  k_seg_count<kTile, -1, uint16_t><<<dim3(ub), dim3(kUpBlock), 0, env.stream()>>>(kb, table, kRadixBits, req_off,
                                                                                   tile_base, nreq, ub);
   env.prof_end("radix_upsweep");
   if ((rc = check_launch(env, "seg_count launch"))) return rc;

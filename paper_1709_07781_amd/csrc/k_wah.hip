@@ -33,12 +33,18 @@
 namespace ka {
 namespace {
 
-constexpr int kEncBlock = 256;
+// 512 work-items x 16 elements: a tile of 8192 pairs.  The look-back's
+// latency (a few device-coherent round trips, about 0.75 us each) is paid
+// once per tile while the whole work-group waits; 8192-element tiles halve
+// how often it is paid for the same occupancy in waves (two work-groups of
+// 8 waves per CU, bound by LDS): measured 244 -> 228 us on 2^26 Zipf pairs;
+// 16384-element tiles (one work-group per CU) took 308 us.
+constexpr int kEncBlock = 512;
 #ifndef KA_ENC_ITEMS
 #define KA_ENC_ITEMS 16
 #endif
 constexpr int kEncItems = KA_ENC_ITEMS;
-constexpr int kEncTile = kEncBlock * kEncItems;  // 4096 pairs
+constexpr int kEncTile = kEncBlock * kEncItems;  // 8192 pairs
 constexpr int kVecs = kEncTile / 4 / kEncBlock;  // 16-byte loads per work-item and array
 constexpr int kLook = 32;                        // >= 30 elements of look-ahead
 constexpr int kStage = kEncTile + kLook;         // staged elements (the look-behind is kept apart)
@@ -159,7 +165,7 @@ struct Reject {
 // status[tile]: the tile's (words, values) look-back word, zeroed before the
 // launch.
 template <bool kVec, class KeyT>
-__global__ __launch_bounds__(kEncBlock, 4) void k_wah_write(const KeyT* __restrict__ skeys,
+__global__ __launch_bounds__(kEncBlock, 2) void k_wah_write(const KeyT* __restrict__ skeys,
                                                          const uint32_t* __restrict__ srows, uint32_t n_cap,
                                                          const uint64_t* __restrict__ d_n,
                                                          uint64_t* __restrict__ status, uint32_t spin_limit,

@@ -5,7 +5,14 @@
 //
 // The plan owns every buffer the pipeline touches -- the input, the request
 // table, the outputs and one scratch arena handed out by a bump allocator --
-// so nothing is allocated while the graph is captured or replayed.  Look-back
+// so nothing is allocated while the graph is captured or replayed.
+//
+// A plan for any batch is recorded for capacities (values, requests) instead
+// of one shape: the request table lives on the device with max_requests + 1
+// entries, a batch of fewer requests is padded with empty ones, and the
+// graph's first kernel reads the value count from the table's last entry, so
+// every kernel sizes its grid by the capacity and works on the count it finds
+// there.  Each run uploads a table and values and replays the same graph.  Look-back
 // kernels get the plan's own status words, which a fill kernel inside the
 // graph clears before each look-back launch: the epoch baked into a replayed
 // launch is always the same, so stale words must not survive from the
@@ -55,6 +62,16 @@ struct Plan {
   System* sys = nullptr;
   uint64_t n = 0;
   uint32_t nreq = 0, value_bits = 0;
+  // any-batch plans: capacities, the largest request allowed, the count slot
+  // the graph fills from the table, and two pinned tables used in turn (each
+  // rewritten once its previous upload has finished)
+  bool any = false;
+  uint64_t n_cap = 0;
+  uint32_t nreq_cap = 0, max_req = kMaxReqUnknown;
+  uint64_t* d_n = nullptr;
+  uint32_t* h_tab[2] = {nullptr, nullptr};
+  hipEvent_t tab_done[2] = {nullptr, nullptr};
+  int tab_next = 0;
   hipStream_t s = nullptr;
   void* mem = nullptr;  // one device allocation for everything
   uint32_t *input = nullptr, *req_off = nullptr, *keys = nullptr, *offsets = nullptr, *words = nullptr;
@@ -95,24 +112,21 @@ static void plan_free(ka_batch_plan* p) {
     (void)hipStreamSynchronize(p->s);
     (void)hipStreamDestroy(p->s);
   }
+  for (int i = 0; i < 2; ++i) {
+    if (p->tab_done[i]) (void)hipEventDestroy(p->tab_done[i]);
+    if (p->h_tab[i]) (void)hipHostFree(p->h_tab[i]);
+  }
   if (p->mem) (void)hipFree(p->mem);
   (void)hipGetLastError();
   if (p->sys) p->sys->release();
   delete p;
 }
 
-KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_t nreq, uint32_t value_bits,
-                                uint32_t flags, ka_batch_plan** out) {
-  KA_GUARD_BEGIN
-  if (!sys || !req_off || !out) return set_error(KA_E_ARG, "null argument");
-  if (nreq == 0) return set_error(KA_E_ARG, "no requests");
-  const uint64_t n = req_off[nreq];
-  if (req_off[0] != 0) return set_error(KA_E_ARG, "req_off must start at 0");
-  uint32_t biggest = 0;  // the largest request (selects the small-request path)
-  for (uint32_t j = 0; j < nreq; ++j) {
-    if (req_off[j + 1] < req_off[j]) return set_error(KA_E_ARG, "req_off must be non-decreasing");
-    biggest = std::max(biggest, req_off[j + 1] - req_off[j]);
-  }
+// Allocates a plan for n values in nreq requests and records its graphs; the
+// request table is uploaded from req_off (nreq + 1 host entries), and with
+// any_batch the graph reads the value count from the table on the device.
+static int plan_build(ka_system* sys, const uint32_t* req_off, uint64_t n, uint32_t nreq, uint32_t value_bits,
+                      uint32_t biggest, bool any_batch, uint32_t flags, ka_batch_plan** out) {
   if (n >= (1ull << 30)) return set_error(KA_E_ARG, "n must be below 2^30");
   if (value_bits == 0 || value_bits > 32) return set_error(KA_E_ARG, "value_bits must be 1..32");
   const uint32_t req_bits = nreq > 1 ? 32u - (uint32_t)__builtin_clz(nreq - 1) : 0u;
@@ -127,6 +141,10 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
   p->n = n;
   p->nreq = nreq;
   p->value_bits = value_bits;
+  p->any = any_batch;
+  p->n_cap = n;
+  p->nreq_cap = nreq;
+  p->max_req = biggest;
   // ---- one allocation: input, table, outputs, look-back state, scratch arena -----------
   const uint64_t n1 = n ? n : 1;
   // the segmented sort cuts tiles at request boundaries: at most one more per request
@@ -141,7 +159,7 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
   };
   const uint64_t o_in = take(4 * n1), o_req = take(4 * (nreq + 1ull)), o_keys = take(4 * n1);
   const uint64_t o_offs = take(4 * (n + nreq)), o_words = take(8 * n1), o_ks = take(4 * (nreq + 1ull));
-  const uint64_t o_ws = take(4 * (nreq + 1ull)), o_lens = take(5 * 8);
+  const uint64_t o_ws = take(4 * (nreq + 1ull)), o_lens = take(6 * 8);
   const uint64_t o_plan = take(kSortPlanBytes), o_status = take(8 * scan_tiles), o_arena = take(arena_bytes);
   if (hipMalloc(&p->mem, off) != hipSuccess) {
     (void)hipGetLastError();
@@ -157,6 +175,7 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
   p->key_start = reinterpret_cast<uint32_t*>(m + o_ks);
   p->word_start = reinterpret_cast<uint32_t*>(m + o_ws);
   p->lens = reinterpret_cast<uint64_t*>(m + o_lens);
+  p->d_n = p->lens + 5;
   PlanEnv& e = p->env;
   e.lb.plan = m + o_plan;
   e.lb.status = reinterpret_cast<uint64_t*>(m + o_status);
@@ -169,7 +188,17 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
     return set_error(KA_E_DEVICE, "plan: stream creation");
   }
   e.s = p->s;
-  // the request table is uploaded once
+  if (any_batch) {
+    for (int i = 0; i < 2; ++i)
+      if (hipHostMalloc(reinterpret_cast<void**>(&p->h_tab[i]), 4 * (nreq + 1ull), hipHostMallocDefault) !=
+              hipSuccess ||
+          hipEventCreateWithFlags(&p->tab_done[i], hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        plan_free(p);
+        return set_error(KA_E_OOM, "plan: pinned request tables");
+      }
+  }
+  // the request table is uploaded (a fixed plan's once and for all)
   if (hipMemcpyAsync(p->req_off, req_off, 4 * (nreq + 1ull), hipMemcpyHostToDevice, p->s) != hipSuccess ||
       hipStreamSynchronize(p->s) != hipSuccess) {
     (void)hipGetLastError();
@@ -193,9 +222,11 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
       plan_free(p);
       return set_error(KA_E_DEVICE, "plan: begin capture");
     }
-    rc = launch_wah_batch(e, p->input, n, p->req_off, nreq, value_bits, p->keys, p->offsets, p->words,
-                          p->key_start, p->word_start, p->lens, p->lens + 1, p->lens + 2, p->lens + 3, p->lens + 4,
-                          shape, biggest);
+    rc = any_batch ? launch_len_from_u32(e, p->d_n, p->req_off + nreq) : kOk;
+    if (!rc)
+      rc = launch_wah_batch(e, p->input, n, p->req_off, nreq, value_bits, p->keys, p->offsets, p->words,
+                            p->key_start, p->word_start, p->lens, p->lens + 1, p->lens + 2, p->lens + 3, p->lens + 4,
+                            shape, biggest, nullptr, any_batch ? p->d_n : nullptr);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(p->s, &g);
     p->graph[v] = g;
@@ -210,8 +241,39 @@ KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_
       return set_error(KA_E_DEVICE, "plan: graph instantiation");
     }
   }
+  if (any_batch) {  // the plan starts out holding an empty batch
+    p->n = 0;
+    p->nreq = 0;
+  }
   *out = p;
   return KA_OK;
+}
+
+KA_API int ka_batch_plan_create(ka_system* sys, const uint32_t* req_off, uint32_t nreq, uint32_t value_bits,
+                                uint32_t flags, ka_batch_plan** out) {
+  KA_GUARD_BEGIN
+  if (!sys || !req_off || !out) return set_error(KA_E_ARG, "null argument");
+  if (nreq == 0) return set_error(KA_E_ARG, "no requests");
+  if (req_off[0] != 0) return set_error(KA_E_ARG, "req_off must start at 0");
+  uint32_t biggest = 0;  // the largest request (selects the small-request path)
+  for (uint32_t j = 0; j < nreq; ++j) {
+    if (req_off[j + 1] < req_off[j]) return set_error(KA_E_ARG, "req_off must be non-decreasing");
+    biggest = std::max(biggest, req_off[j + 1] - req_off[j]);
+  }
+  return plan_build(sys, req_off, req_off[nreq], nreq, value_bits, biggest, false, flags, out);
+  KA_GUARD_END
+}
+
+KA_API int ka_batch_plan_create_any(ka_system* sys, uint64_t max_values, uint32_t max_requests,
+                                    uint32_t max_request_values, uint32_t value_bits, uint32_t flags,
+                                    ka_batch_plan** out) {
+  KA_GUARD_BEGIN
+  if (!sys || !out) return set_error(KA_E_ARG, "null argument");
+  if (max_requests == 0) return set_error(KA_E_ARG, "max_requests must be at least 1");
+  if (max_values >= (1ull << 30)) return set_error(KA_E_ARG, "max_values must be below 2^30");
+  const uint32_t biggest = max_request_values ? max_request_values : kMaxReqUnknown;
+  std::vector<uint32_t> empty(max_requests + 1ull, 0u);  // the empty batch the plan starts with
+  return plan_build(sys, empty.data(), max_values, max_requests, value_bits, biggest, true, flags, out);
   KA_GUARD_END
 }
 
@@ -271,6 +333,44 @@ KA_API int ka_batch_plan_run(ka_batch_plan* plan, const uint32_t* values, uint32
   return KA_OK;
 }
 
+KA_API int ka_batch_plan_run_batch(ka_batch_plan* plan, const uint32_t* values, const uint32_t* req_off,
+                                   uint32_t nreq, uint32_t flags) {
+  KA_GUARD_BEGIN
+  if (!plan || !req_off) return set_error(KA_E_ARG, "null argument");
+  if (!plan->any) return set_error(KA_E_STATE, "the plan was recorded for one batch shape");
+  if (nreq > plan->nreq_cap) return set_error(KA_E_ARG, "more requests than the plan holds");
+  if (req_off[0] != 0) return set_error(KA_E_ARG, "req_off must start at 0");
+  for (uint32_t j = 0; j < nreq; ++j) {
+    if (req_off[j + 1] < req_off[j]) return set_error(KA_E_ARG, "req_off must be non-decreasing");
+    if (plan->max_req != kMaxReqUnknown && req_off[j + 1] - req_off[j] > plan->max_req)
+      return set_error(KA_E_ARG, "a request is larger than the plan's largest request");
+  }
+  const uint64_t n = req_off[nreq];
+  if (n > plan->n_cap) return set_error(KA_E_ARG, "more values than the plan holds");
+  int rc = plan->sys->use_device();
+  if (rc) return rc;
+  // the table, padded with empty requests, through a pinned buffer whose
+  // previous upload has finished
+  const int k = plan->tab_next;
+  if (hipEventSynchronize(plan->tab_done[k]) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(KA_E_DEVICE, "plan: table upload");
+  }
+  uint32_t* t = plan->h_tab[k];
+  std::memcpy(t, req_off, 4 * (nreq + 1ull));
+  for (uint32_t j = nreq + 1; j <= plan->nreq_cap; ++j) t[j] = (uint32_t)n;
+  if (hipMemcpyAsync(plan->req_off, t, 4 * (plan->nreq_cap + 1ull), hipMemcpyHostToDevice, plan->s) != hipSuccess ||
+      hipEventRecord(plan->tab_done[k], plan->s) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(KA_E_DEVICE, "plan: table upload");
+  }
+  plan->tab_next = k ^ 1;
+  plan->n = n;
+  plan->nreq = nreq;
+  return ka_batch_plan_run(plan, values, flags);
+  KA_GUARD_END
+}
+
 KA_API int ka_batch_plan_shape(ka_batch_plan* plan, int* shape, float* ms, uint32_t nms) {
   if (!plan || !shape) return set_error(KA_E_ARG, "null argument");
   *shape = plan->chosen < 0 ? -1 : (plan->forced >= 0 ? plan->forced : plan->chosen);
@@ -290,6 +390,12 @@ KA_API int ka_batch_plan_result(ka_batch_plan* plan, ka_wah_batch_result* out) {
     return set_error(KA_E_DEVICE, "plan: synchronisation");
   }
   if (len[3] == 0) return set_error(KA_E_ARG, "a value is at or above 2^value_bits");
+  // an any-batch plan's padding (empty requests after the real ones) adds one
+  // offsets entry and one table entry each, at the ends
+  const uint64_t pad = plan->nreq_cap - plan->nreq;
+  len[1] -= pad;
+  len[3] -= pad;
+  len[4] -= pad;
   ka_wah_batch_result r{};
   r.nreq = plan->nreq;
   r.n = plan->n;

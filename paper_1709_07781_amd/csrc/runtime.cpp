@@ -116,11 +116,12 @@ int System::ensure_init() {
 }
 
 hipEvent_t System::get_event(bool timing) {
-  if (!timing) {
+  {
     std::lock_guard<std::mutex> g(ev_mu);
-    if (!events.empty()) {
-      hipEvent_t e = events.back();
-      events.pop_back();
+    auto& pool = timing ? timing_events : events;
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
       return e;
     }
   }
@@ -133,6 +134,35 @@ void System::put_event(hipEvent_t e) {
   if (!e) return;
   std::lock_guard<std::mutex> g(ev_mu);
   events.push_back(e);
+}
+
+void System::put_timing_event(hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> g(ev_mu);
+  timing_events.push_back(e);
+}
+
+// Profile records are folded in launch order; the events go back to the
+// timing pool, so a long profiled run holds a bounded number of them.
+void System::prof_fold_locked(bool all) {
+  size_t k = 0;
+  for (; k < prof_pending.size(); ++k) {
+    ProfRec& p = prof_pending[k];
+    if (all) {
+      hipEventSynchronize(p.b);
+    } else if (hipEventQuery(p.b) != hipSuccess) {
+      (void)hipGetLastError();  // "not ready" must not stay pending
+      break;
+    }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, p.a, p.b);
+    auto& acc = prof_acc[p.name];
+    acc.first += 1;
+    acc.second += ms;
+    put_timing_event(p.a);
+    put_timing_event(p.b);
+  }
+  prof_pending.erase(prof_pending.begin(), prof_pending.begin() + k);
 }
 
 void System::release() {
@@ -958,6 +988,8 @@ KA_API int ka_system_destroy(ka_system* sys) {
     {
       std::lock_guard<std::mutex> g(sys->ev_mu);
       for (hipEvent_t e : sys->events) hipEventDestroy(e);
+      for (hipEvent_t e : sys->timing_events) hipEventDestroy(e);
+      sys->timing_events.clear();
       sys->events.clear();
     }
     for (auto& sc : sys->streams)
@@ -1719,17 +1751,7 @@ KA_API int ka_wah_result_free(ka_wah_result* res) {
 // ---- profiling ------------------------------------------------------------------------
 static void prof_drain(ka_system* sys) {
   std::lock_guard<std::mutex> g(sys->prof_mu);
-  for (auto& p : sys->prof_pending) {
-    hipEventSynchronize(p.b);
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, p.a, p.b);
-    auto& acc = sys->prof_acc[p.name];
-    acc.first += 1;
-    acc.second += ms;
-    hipEventDestroy(p.a);
-    hipEventDestroy(p.b);
-  }
-  sys->prof_pending.clear();
+  sys->prof_fold_locked(true);
 }
 
 KA_API int ka_profile_get(ka_system* sys, const char* kernel, uint64_t* launches, double* total_ms) {

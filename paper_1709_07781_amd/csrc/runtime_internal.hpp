@@ -109,7 +109,8 @@ struct System {
   std::atomic<uint64_t> length_reads{0};  // device-resident lengths read back on the host (each waits)
   uint32_t lb_spin = kLbSpinLimit;  // look-back spin limit (KA_LOOKBACK_SPIN)
   std::mutex ev_mu;
-  std::vector<hipEvent_t> events;  // pool of timing-disabled events
+  std::vector<hipEvent_t> events;         // pool of timing-disabled events
+  std::vector<hipEvent_t> timing_events;  // pool of timing events (profiling)
   std::mutex prof_mu;
   std::vector<ProfRec> prof_pending;
   std::map<std::string, std::pair<uint64_t, double>> prof_acc;
@@ -123,6 +124,10 @@ struct System {
   int use_device();    // makes the system's device current for this thread
   hipEvent_t get_event(bool timing = false);
   void put_event(hipEvent_t e);
+  void put_timing_event(hipEvent_t e);
+  // Folds finished profile records into the totals: all of them, waiting for
+  // each (all = true), or the finished ones at the front (caller holds prof_mu).
+  void prof_fold_locked(bool all);
   void retain() { rc.fetch_add(1); }
   void release();
 };
@@ -188,6 +193,8 @@ class CmdEnv final : public Env {
     std::lock_guard<std::mutex> g(sys_->prof_mu);
     sys_->prof_pending.push_back({kernel, ev0_, ev1});
     ev0_ = nullptr;
+    // keep the live timing events bounded: fold the finished front records
+    if (sys_->prof_pending.size() >= 4096) sys_->prof_fold_locked(false);
   }
   int fail(int code, const char* msg) override { return set_error(code, msg); }
   uint32_t si() const { return si_; }

@@ -5,7 +5,9 @@
 //
 //  * ka_server_submit copies the request's data into pinned host memory
 //    (recycled by size class) and appends it to the mailbox with its arrival
-//    time.
+//    time.  A large payload is cut into chunks that the submitting thread and
+//    the server's copy threads copy together; an index payload's values are
+//    checked against 2^value_bits in the same pass.
 //  * The mailbox thread forms a batch from the oldest waiting requests as soon
 //    as a stream slot is free and the HBM budget admits them (at most
 //    max_batch requests and max_batch_bytes of input; a request that arrives
@@ -59,6 +61,110 @@ uint64_t request_bytes(uint32_t kind, uint64_t n) {
       return 4 * n + 64;
   }
 }
+
+// dst[i] = src[i] for i < n; returns the OR of the values shifted right by
+// shift (0 for shift >= 32): nonzero iff some value is at or above 2^shift.
+uint32_t copy_checked(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, uint64_t n, uint32_t shift) {
+  if (shift >= 32) {
+    std::memcpy(dst, src, 4 * n);
+    return 0;
+  }
+  uint32_t o = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint32_t x = src[i];
+    dst[i] = x;
+    o |= x;
+  }
+  return o >> shift;
+}
+
+// Copies host payloads into pinned memory.  A payload of kSplitBytes or more
+// is cut into kChunk-element chunks; the submitting thread and the pool's
+// threads take chunks until none is left.  A job stays reachable only while it
+// is queued; the submitter unqueues it and waits until no thread is inside it.
+class CopyPool {
+ public:
+  static constexpr uint64_t kSplitBytes = 1ull << 20;
+  static constexpr uint64_t kChunk = 1ull << 16;  // elements (256 KiB)
+
+  void start(uint32_t threads) {
+    for (uint32_t i = 0; i < threads; ++i) th_.emplace_back([this] { work(); });
+  }
+  void stop() {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      stopping_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+    th_.clear();
+  }
+  uint32_t copy(uint32_t* dst, const uint32_t* src, uint64_t n, uint32_t shift) {
+    if (th_.empty() || 4 * n < kSplitBytes) return copy_checked(dst, src, n, shift);
+    Job j{dst, src, n, shift, (n + kChunk - 1) / kChunk};
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      jobs_.push_back(&j);
+    }
+    cv_.notify_all();
+    run(j);
+    std::unique_lock<std::mutex> lk(mu_);
+    for (auto it = jobs_.begin(); it != jobs_.end(); ++it)
+      if (*it == &j) {
+        jobs_.erase(it);
+        break;
+      }
+    cv_idle_.wait(lk, [&] { return j.active == 0; });
+    return j.over.load();
+  }
+
+ private:
+  struct Job {
+    uint32_t* dst;
+    const uint32_t* src;
+    uint64_t n;
+    uint32_t shift;
+    uint64_t chunks;
+    std::atomic<uint64_t> next{0};
+    std::atomic<uint32_t> over{0};
+    uint32_t active = 0;  // pool threads inside the job (under mu_)
+  };
+  static void run(Job& j) {
+    uint32_t o = 0;
+    for (uint64_t c; (c = j.next.fetch_add(1)) < j.chunks;) {
+      const uint64_t b = c * kChunk, e = std::min(j.n, b + kChunk);
+      o |= copy_checked(j.dst + b, j.src + b, e - b, j.shift);
+    }
+    if (o) j.over.fetch_or(o);
+  }
+  void work() {
+    for (;;) {
+      Job* j = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stopping_ || !jobs_.empty(); });
+        if (stopping_) return;
+        j = jobs_.front();
+        if (j->next.load() >= j->chunks) {  // every chunk is taken: nothing left here
+          jobs_.pop_front();
+          continue;
+        }
+        ++j->active;
+      }
+      run(*j);
+      {
+        std::lock_guard<std::mutex> g(mu_);
+        --j->active;
+      }
+      cv_idle_.notify_all();
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_, cv_idle_;
+  std::deque<Job*> jobs_;
+  std::vector<std::thread> th_;
+  bool stopping_ = false;
+};
 
 }  // namespace
 
@@ -144,6 +250,8 @@ struct Server {
   bool stop = false;
   bool loop_done = false;  // the mailbox thread has exited: no batch will be added
   std::thread loop, completion;
+
+  CopyPool copier;
 
   std::mutex st_mu;
   std::vector<double> lat_us;
@@ -525,6 +633,7 @@ KA_API int ka_server_create(ka_system* sys, const ka_server_config* cfg, ka_serv
         if (p[k]) sys->stage.give_back(p[k]);
     }
   }
+  s->copier.start(cfg && cfg->copy_threads ? std::min<uint32_t>(cfg->copy_threads - 1, 64) : 3);
   sys->retain();
   s->loop = std::thread([s] { s->run_loop(); });
   s->completion = std::thread([s] { s->run_completion(); });
@@ -542,11 +651,6 @@ int server_enqueue(ka_server* srv, uint32_t kind, const uint32_t* data, Ref* dre
   if (kind > KA_REQ_CHAIN) return set_error(KA_E_ARG, "unknown request kind");
   if (n >= (1ull << 30)) return set_error(KA_E_ARG, "n must be below 2^30");
   if (request_bytes(kind, n) > srv->budget) return set_error(KA_E_BUDGET, "request larger than the server budget");
-  if (data && kind == KA_REQ_WAH && srv->value_bits < 32) {
-    uint32_t over = 0;
-    for (uint64_t i = 0; i < n; ++i) over |= data[i] >> srv->value_bits;
-    if (over) return set_error(KA_E_ARG, "an index value is at or above 2^value_bits");
-  }
   ka_srv_req* r = new ka_srv_req();
   r->sys = srv->sys;
   r->kind = kind;
@@ -558,7 +662,11 @@ int server_enqueue(ka_server* srv, uint32_t kind, const uint32_t* data, Ref* dre
       delete r;
       return set_error(KA_E_OOM, "server: pinned staging");
     }
-    std::memcpy(r->pin, data, 4 * n);
+    const uint32_t shift = kind == KA_REQ_WAH ? srv->value_bits : 32u;
+    if (srv->copier.copy(static_cast<uint32_t*>(r->pin), data, n, shift)) {
+      delete r;
+      return set_error(KA_E_ARG, "an index value is at or above 2^value_bits");
+    }
   }
   if (dref) {
     ref_retain(dref);
@@ -766,6 +874,7 @@ KA_API int ka_server_destroy(ka_server* srv) {
   if (srv->loop.joinable()) srv->loop.join();  // no batch is launched after this
   srv->cv_done.notify_all();
   if (srv->completion.joinable()) srv->completion.join();  // in-flight batches finish first
+  srv->copier.stop();  // no submission may still run (the caller's contract)
   for (auto* r : cancelled) {
     r->finish(KA_E_CANCELLED);
     r->release();

@@ -265,9 +265,11 @@ class Server:
     their outputs and the latency statistics."""
 
     def __init__(self, session: Session, streams: int = 2, max_batch: int = 0, budget_bytes: int = 0,
-                 value_bits: int = 12, chain_a=None, chain_b=None, max_batch_bytes: int = 0):
+                 value_bits: int = 12, chain_a=None, chain_b=None, max_batch_bytes: int = 0,
+                 copy_threads: int = 0):
         from . import ka_server_config
         cfg = ka_server_config()
+        cfg.copy_threads = copy_threads
         cfg.streams = streams
         cfg.max_batch = max_batch
         cfg.max_batch_bytes = max_batch_bytes
@@ -341,12 +343,20 @@ class Server:
 class BatchPlan:
     """A batch shape recorded into a HIP graph (ka_batch_plan_*)."""
 
-    def __init__(self, session: Session, req_off, value_bits: int, autotune: bool = False, shape: int | None = None):
-        self.off = np.ascontiguousarray(req_off, dtype=np.uint32)
-        self.nreq = self.off.size - 1
+    def __init__(self, session: Session, req_off, value_bits: int, autotune: bool = False, shape: int | None = None,
+                 any_batch=None):
+        """req_off: the one batch shape; or any_batch = (max_values,
+        max_requests, max_request_values) for a plan that serves any batch
+        within these capacities (req_off then ignored, may be None)."""
         self.plan = c_void_p()
         flags = (1 if autotune else 0) | (((shape + 1) << 8) if shape is not None else 0)
-        check(lib.ka_batch_plan_create(session.sys, self.off.ctypes.data, self.nreq, value_bits, flags,
+        if any_batch is not None:
+            mv, mr, mq = any_batch
+            check(lib.ka_batch_plan_create_any(session.sys, mv, mr, mq, value_bits, flags, byref(self.plan)),
+                  "ka_batch_plan_create_any")
+            return
+        self.off = np.ascontiguousarray(req_off, dtype=np.uint32)
+        check(lib.ka_batch_plan_create(session.sys, self.off.ctypes.data, self.off.size - 1, value_bits, flags,
                                        byref(self.plan)), "ka_batch_plan_create")
 
     def shape(self):
@@ -377,11 +387,23 @@ class BatchPlan:
             check(lib.ka_batch_plan_run(self.plan, c_void_p(values.data_ptr()), KA_WAH_INPUT_DEVICE),
                   "ka_batch_plan_run")
 
+    def run_batch(self, values, req_off):
+        """Any-batch plans: the next batch (values: numpy uint32 on the host or
+        a device tensor; req_off: nreq + 1 entries)."""
+        off = np.ascontiguousarray(req_off, dtype=np.uint32)
+        if isinstance(values, np.ndarray):
+            v = np.ascontiguousarray(values, dtype=np.uint32)
+            ptr, fl = (v.ctypes.data if v.size else None), 0
+        else:
+            v, ptr, fl = values, c_void_p(values.data_ptr()), KA_WAH_INPUT_DEVICE
+        check(lib.ka_batch_plan_run_batch(self.plan, ptr, off.ctypes.data, off.size - 1, fl),
+              "ka_batch_plan_run_batch")
+
     def result(self):
         """Per-request (keys, offsets, words) of the last run."""
         res = ka_wah_batch_result()
         check(lib.ka_batch_plan_result(self.plan, byref(res)), "ka_batch_plan_result")
-        nreq, D, W = self.nreq, res.D, res.W
+        nreq, D, W = res.nreq, res.D, res.W
         keys = np.ctypeslib.as_array(res.keys, shape=(max(D, 1),))[:D].copy()
         offs = np.ctypeslib.as_array(res.offsets, shape=(D + nreq,)).copy()
         words = np.ctypeslib.as_array(res.words, shape=(max(W, 1),))[:W].copy()

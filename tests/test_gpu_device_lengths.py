@@ -13,7 +13,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-SORT_TILE, ENC_TILE = 8192, 4096
+SORT_TILE, ENC_TILE = 8192, 8192
 
 
 @pytest.fixture(scope="module")
@@ -68,7 +68,7 @@ def _compact_actor(sess):
     return sess.spawn("compact_nonzero_u32", [ka.arg(ka.KA_IN, in_mode=ka.KA_VAL), ka.arg(ka.KA_OUT)])
 
 
-SIZES = [1, 7, ENC_TILE + 1, SORT_TILE + 3, 3 * SORT_TILE + 7, 70_001]
+SIZES = [1, 7, 4097, ENC_TILE + 1, ENC_TILE + 31, 3 * SORT_TILE + 7, 70_001]
 FRACS = [0.0, 0.3, 0.9, 1.0]
 
 

@@ -9,7 +9,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-SCAN_TILE, SORT_TILE, ENC_TILE = 8192, 8192, 4096
+SCAN_TILE, SORT_TILE, ENC_TILE = 8192, 8192, 8192
 LARGE_SCAN, LARGE_SCAN_TILE = 1 << 23, 16384  # scans above LARGE_SCAN elements use the larger tile
 
 
@@ -161,8 +161,8 @@ def test_radix_sort_pairs_explicit_rows(sess, ora, n):
 # ---- WAH encode on sorted pairs ----------------------------------------------------------
 @pytest.mark.parametrize("kind", ["uniform1024", "all_equal", "distinct", "zipf", "alternating_chunks", "sparse_hot",
                                   "all_max"])
-@pytest.mark.parametrize("n", [1, 30, 31, 32, 62, 2047, 2049, ENC_TILE - 1, ENC_TILE, ENC_TILE + 1, ENC_TILE + 31,
-                               5 * ENC_TILE + 17, 65_536])
+@pytest.mark.parametrize("n", [1, 30, 31, 32, 62, 2047, 2049, 4097, ENC_TILE - 1, ENC_TILE, ENC_TILE + 1,
+                               ENC_TILE + 31, 5 * ENC_TILE + 17, 65_536])
 def test_wah_encode_sorted(sess, ora, kind, n):
     ka = _ka()
     v = workloads.structured(kind, n, seed=n + 3)

@@ -137,3 +137,100 @@ def test_autotuned_plan(sess):
     finally:
         plan.close()
 
+
+
+# ---- plans for any batch -----------------------------------------------------------------
+def _batches(seed, cap_values, cap_requests, bits, lo, hi):
+    """A sequence of different batches within the capacities: varied request
+    counts and sizes, an empty batch, a batch of empty requests, and one filling
+    both capacities exactly (last request takes the remaining values)."""
+    out = []
+    for i, count in enumerate([cap_requests // 3, 1, cap_requests, 7, cap_requests // 2]):
+        off, v = workloads.batched_requests(seed=seed + i, count=max(count, 1), lo_log2=lo, hi_log2=hi,
+                                            bound=1 << bits, max_total=cap_values)
+        out.append((off, v))
+    out.append((np.zeros(1, np.int64), np.zeros(0, np.uint32)))               # no requests
+    out.append((np.zeros(4, np.int64), np.zeros(0, np.uint32)))               # three empty requests
+    sizes = np.full(cap_requests, cap_values // cap_requests, np.int64)
+    sizes[-1] += cap_values - sizes.sum()
+    off = np.zeros(cap_requests + 1, np.int64)
+    np.cumsum(sizes, out=off[1:])
+    out.append((off, workloads.uniform_values(seed + 99, cap_values, 1 << bits)))  # both capacities full
+    return out
+
+
+@pytest.mark.parametrize("bits,shape", [(12, 0), (12, 1), (20, 0), (16, 2)])
+def test_any_batch_plan_serves_every_batch(sess, bits, shape):
+    """One recorded graph serves a sequence of different batches (request
+    counts, sizes, empty batches, both capacities full): every result equals
+    the oracle's, with eager work between the runs."""
+    import torch
+    from paper_1709_07781_amd.session import BatchPlan
+    cap_values, cap_requests = 3 * 8192 * 8 + 5, 96
+    plan = BatchPlan(sess, None, bits, shape=shape, any_batch=(cap_values, cap_requests, 0))
+    try:
+        for off, v in _batches(200 + bits, cap_values, cap_requests, bits, 4, 14):
+            plan.run_batch(v, off)
+            got = plan.result()
+            assert torch.arange(100, device="cuda").sum().item() == 4950
+            _same(got, _oracle(off, v))
+            plan.run(v)  # the same batch again through ka_batch_plan_run
+            _same(plan.result(), _oracle(off, v))
+    finally:
+        plan.close()
+
+
+def test_any_batch_plan_small_requests_and_device_input(sess):
+    """Requests bounded by 1024 values take the one-work-group-per-request
+    path; values from a device tensor; autotuning on the first batch."""
+    import torch
+    from paper_1709_07781_amd.session import BatchPlan
+    cap_values, cap_requests = 300_000, 1024
+    plan = BatchPlan(sess, None, 12, autotune=True, any_batch=(cap_values, cap_requests, 1024))
+    try:
+        for i, count in enumerate([1024, 10, 500]):
+            off, v = workloads.batched_requests(seed=300 + i, count=count, lo_log2=0, hi_log2=10)
+            dv = torch.from_numpy(v.view(np.int32)).to("cuda")
+            torch.cuda.synchronize()
+            plan.run_batch(dv, off)
+            _same(plan.result(), _oracle(off, v))  # waits for the plan's stream
+            del dv
+    finally:
+        plan.close()
+
+
+def test_any_batch_plan_rejections_and_errors(sess):
+    import ctypes
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import BatchPlan
+    plan = BatchPlan(sess, None, 8, any_batch=(10_000, 8, 2000))
+    fixed = BatchPlan(sess, np.array([0, 10], np.uint32), 8)
+    try:
+        off = np.array([0, 100, 300], np.uint32)
+        v = workloads.uniform_values(95, 300, 1 << 8)
+        v[150] = 256
+        plan.run_batch(v, off)
+        with pytest.raises(ka.KaError) as e:
+            plan.result()
+        assert e.value.code == ka.KA_E_ARG
+        v[150] = 3
+        plan.run_batch(v, off)
+        _same(plan.result(), _oracle(off, v))
+        bad = [np.arange(10, dtype=np.uint32) * 1000,                # 9 requests > 8
+               np.array([0, 2001], np.uint32),                        # a request above 2000 values
+               np.array([0, 2000, 4000, 6000, 8000, 10000, 10001], np.uint32),  # more than 10000 values
+               np.array([0, 5, 3], np.uint32), np.array([1, 5], np.uint32)]
+        for o in bad:
+            x = np.zeros(int(o.max()), np.uint32)
+            with pytest.raises(ka.KaError) as e:
+                plan.run_batch(x, o)
+            assert e.value.code == ka.KA_E_ARG
+        with pytest.raises(ka.KaError) as e:
+            fixed.run_batch(np.zeros(10, np.uint32), np.array([0, 10], np.uint32))
+        assert e.value.code == ka.KA_E_STATE
+        p = ctypes.c_void_p()
+        assert ka.lib.ka_batch_plan_create_any(sess.sys, 100, 0, 0, 8, 0, ctypes.byref(p)) == ka.KA_E_ARG
+        assert ka.lib.ka_batch_plan_create_any(sess.sys, 100, 1 << 20, 0, 16, 0, ctypes.byref(p)) == ka.KA_E_ARG
+    finally:
+        plan.close()
+        fixed.close()

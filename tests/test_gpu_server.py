@@ -114,6 +114,42 @@ def test_value_bits_checked_at_submit(sess):
         srv.close()
 
 
+@pytest.mark.parametrize("copy_threads", [1, 0, 8])
+def test_large_payload_copied_and_checked_in_chunks(sess, copy_threads):
+    """A payload of 1 MiB or more is copied in 2^16-value chunks by several
+    threads, its values checked in the same pass: a value at or above
+    2^value_bits in the first chunk, at a chunk edge or in the ragged last
+    chunk fails the submission; valid payloads of the same size give the
+    oracle's index (1 copy thread: the submitting thread copies alone)."""
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import Server
+    chunk = 1 << 16
+    n = 3 * chunk + 5
+    ora = oracle.default()
+    srv = Server(sess, copy_threads=copy_threads)
+    try:
+        for pos in (0, chunk - 1, chunk, 2 * chunk + 1, n - 1):
+            x = workloads.uniform_values(70 + pos % 7, n, 4096)
+            x[pos] = 4096 + pos
+            with pytest.raises(ka.KaError) as e:
+                srv.submit(workloads.KIND_WAH, x)
+            assert e.value.code == ka.KA_E_ARG, f"bad value at {pos}"
+        xs = [workloads.uniform_values(80 + i, n + i * 977, 4096) for i in range(3)]
+        hs = [srv.submit(workloads.KIND_WAH, x) for x in xs]
+        for x, h in zip(xs, hs):
+            assert srv.wait(h) == 0
+            for g, e in zip(_results(srv, h, workloads.KIND_WAH), ora.wah_index(x)):
+                np.testing.assert_array_equal(g, e)
+            srv.release(h)
+        y = workloads.u32(90, n)
+        h = srv.submit(workloads.KIND_SCAN, y)
+        assert srv.wait(h) == 0
+        np.testing.assert_array_equal(srv.result(h, 0), ora.exclusive_scan(y))
+        srv.release(h)
+    finally:
+        srv.close()
+
+
 def test_destroy_cancels_or_finishes_everything(sess):
     """Destroying a server with a full mailbox ends every request: finished
     (with the right result) or cancelled."""

@@ -13,8 +13,8 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-SORT_TILE, ENC_TILE = 8192, 4096
-SIZES = [0, 1, 30, 31, 32, ENC_TILE - 1, ENC_TILE, ENC_TILE + 1, SORT_TILE - 1, SORT_TILE, SORT_TILE + 1,
+SORT_TILE, ENC_TILE = 8192, 8192
+SIZES = [0, 1, 30, 31, 32, 4095, 4097, ENC_TILE - 1, ENC_TILE, ENC_TILE + 1, ENC_TILE + 31, 2 * ENC_TILE + 29,
          3 * SORT_TILE + 5, 40_000, (1 << 20) + 17]
 KINDS = ["uniform4096", "u32", "all_equal", "all_max", "distinct", "reverse", "zipf", "alternating_chunks",
          "sparse_hot"]
