@@ -427,7 +427,11 @@ KA_API int ka_wah_batch_result_free(ka_wah_batch_result* res);
  * each request inside its own positions over 16-bit keys when value_bits <=
  * 16 (ceil(value_bits / 8) passes, 1024 x 8 work-items x keys per tile), else
  * the request-tagged keys with that tile; variants 1 and 2 sort the
- * request-tagged 32-bit keys with 512 x 16 and 512 x 8.  The plan owns
+ * request-tagged 32-bit keys with 512 x 16 and 512 x 8.  A batch whose
+ * requests all hold at most 1024 values (and value_bits <= 22) takes the
+ * small-request path instead: variants 0 and 2 are its three-launch form,
+ * variant 1 one persistent fused launch (requests handed out by a ticket
+ * counter, placed by a look-back over requests).  The plan owns
  * its input, outputs and scratch (nothing is allocated per run); outputs are
  * those of ka_wah_batch.  Requirements on req_off and value_bits as there. */
 #define KA_PLAN_AUTOTUNE 1u /* record one graph per sort variant; the first run picks the fastest */

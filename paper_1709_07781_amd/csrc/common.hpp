@@ -381,6 +381,36 @@ __device__ __forceinline__ typename St::sum_t lb_lookback_st(const uint64_t* sta
   return excl;
 }
 
+// Look-back without fallback, for chains whose every tile is being worked on
+// by a running work-group (tiles handed out in order by a ticket counter, so a
+// tile waited for is held by a work-group that waits only for earlier ones):
+// polls the nearest tile not yet accounted for, then sums windows of 64 as
+// lb_lookback_st does.
+template <class St>
+__device__ __forceinline__ typename St::sum_t lb_lookback_ticket(const uint64_t* status, uint32_t tile,
+                                                                 const St& st) {
+  typedef typename St::sum_t S;
+  const uint32_t lane = lane_id();
+  S excl = St::zero();
+  int64_t j = (int64_t)tile - 1;
+  while (j >= 0) {
+    const uint64_t w0 = lb_load(status + j);
+    const uint32_t f0 = st.flag(w0);
+    if (f0 == 0) {
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    if (f0 == kLbInclusive) {
+      excl = St::add(excl, st.payload(w0));
+      break;
+    }
+    const int64_t idx = j - (int64_t)lane;
+    const uint64_t w = (lane && idx >= 0) ? lb_load(status + idx) : w0;
+    if (lb_window_step(w, st, j, excl)) break;
+  }
+  return excl;
+}
+
 template <class Reduce>
 __device__ __forceinline__ uint32_t lb_lookback(const uint64_t* status, uint32_t tile, uint32_t epoch,
                                                 uint32_t spin_limit, Reduce&& reduce) {

@@ -204,29 +204,187 @@ __global__ __launch_bounds__(kSplitBlock) void k_batch_tables(
 }
 
 // ---------------------------------------------------------------------------------
-// Small requests: one work-group builds one request's whole index
+// Small requests: one persistent launch, one request at a time per work-group
 // ---------------------------------------------------------------------------------
 // When every request holds at most kSmallMax values and values fit in
-// 32 - kSmallRowBits bits, each request is sorted and encoded by one
-// work-group in LDS, so the batch takes three launches instead of the tagged
-// sort's and encoder's fifteen or so:
-//   k_small_index  sorts value << kSmallRowBits | row (a bitonic sort; the row
-//                  bits make equal values keep their order), marks value,
-//                  group and fill heads as the encoder does, and writes the
-//                  request's words, keys and offsets into slots bounded by its
-//                  size (words at 2 * req_off[j], keys at req_off[j], offsets
-//                  at req_off[j] + j), with its word and value counts and
-//                  whether a value was out of range;
-//   k_small_starts scans the counts into key_start and word_start and sets the
-//                  output lengths (all 0 if a value was out of range);
-//   k_small_place  copies each request's slots to their places.
+// 32 - kSmallRowBits bits, the whole batch is one persistent launch,
+// k_small_fused: each work-group takes the next request in order from a
+// ticket counter and
+//   * sorts value << kSmallRowBits | row in LDS (a bitonic sort; the row bits
+//     make equal values keep their order) and marks value, group and fill
+//     heads as the encoder does (Sec. 4.1 parts 3-5);
+//   * publishes the request's word and value counts, and finds those of all
+//     earlier requests by decoupled look-back over the requests' status words;
+//   * writes its words, keys and offsets straight to their places and its
+//     key_start / word_start entries.
+// Tickets are taken in order by running work-groups only, so every request a
+// work-group waits for is held by a running work-group that waits only for
+// earlier ones: the look-back needs no fallback.  A request with a value at
+// or above 2^value_bits (or above kSmallMax values) sets the batch's flag;
+// the request that finishes the batch (the last ticket) writes the totals
+// and, after the look-back has seen every earlier request, the lengths (all 0
+// for a rejected batch).
 constexpr int kSmallMax = 1024;
 constexpr uint32_t kSmallRowBits = 10;
 constexpr int kSmallBlock = 256;
 constexpr int kSmallPer = kSmallMax / kSmallBlock;  // consecutive sorted elements per work-item
 constexpr uint32_t kSmallRows = 31, kSmallFill = 0x80000000u;
+constexpr uint32_t kSmallGrid = 2048;               // persistent work-groups (8 per CU)
 static_assert((1 << kSmallRowBits) == kSmallMax, "row bits cover a request");
 
+__global__ __launch_bounds__(kSmallBlock) void k_small_fused(
+    const uint32_t* __restrict__ values, const uint32_t* __restrict__ req_off, uint32_t nreq, uint32_t value_bits,
+    uint32_t* __restrict__ ticket, uint64_t* __restrict__ status, uint32_t* __restrict__ bad_flag,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ offsets,
+    uint32_t* __restrict__ words, uint32_t* __restrict__ key_start, uint32_t* __restrict__ word_start,
+    uint64_t* __restrict__ len_keys, uint64_t* __restrict__ len_offsets, uint64_t* __restrict__ len_words,
+    uint64_t* __restrict__ len_key_start, uint64_t* __restrict__ len_word_start) {
+  __shared__ uint32_t s[kSmallMax];
+  __shared__ uint32_t s_scan[kSmallBlock / 64];
+  __shared__ uint32_t s_j, s_pre[2];
+  const uint32_t tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) s_j = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t j = s_j;
+    if (j >= nreq) break;  // uniform over the work-group
+    const uint32_t b = req_off[j];
+    // A request above kSmallMax (a wrong size hint) is rejected like an
+    // out-of-range value; only its first kSmallMax values are touched.
+    const uint32_t n_req = req_off[j + 1] - b;
+    const uint32_t n = min(n_req, (uint32_t)kSmallMax);
+    uint32_t over = n_req > (uint32_t)kSmallMax ? 1u : 0u;
+#pragma unroll
+    for (int q = 0; q < kSmallPer; ++q) {
+      const uint32_t i = q * kSmallBlock + tid;
+      uint32_t c = 0xFFFFFFFFu;  // padding sorts last
+      if (i < n) {
+        const uint32_t v = values[b + i];
+        over |= v >> value_bits;  // value_bits <= 32 - kSmallRowBits here
+        c = (v << kSmallRowBits) | i;
+      }
+      s[i] = c;
+    }
+    const bool bad = __syncthreads_or(over != 0u);
+    // bitonic sort of the first m = 2^ceil(log2 n) entries, ascending
+    uint32_t m = 1;
+    while (m < n) m <<= 1;
+    for (uint32_t k = 2; k <= m; k <<= 1) {
+      for (uint32_t h = k >> 1; h > 0; h >>= 1) {
+        for (uint32_t i = tid; i < m; i += kSmallBlock) {
+          const uint32_t l = i ^ h;
+          if (l > i) {
+            const uint32_t x = s[i], y = s[l];
+            if ((x > y) == ((i & k) == 0u)) {
+              s[i] = y;
+              s[l] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // heads of values, groups and fills, as in the encoder
+    const uint32_t e0 = tid * kSmallPer;
+    uint32_t heads = 0, segs = 0, gaps = 0;
+#pragma unroll
+    for (int q = 0; q < kSmallPer; ++q) {
+      const uint32_t i = e0 + q;
+      if (i < n) {
+        const uint32_t c = s[i], v = c >> kSmallRowBits, ch = (c & (kSmallMax - 1)) / kSmallRows;
+        bool seg = true, grp = true, gap = ch != 0u;
+        if (i > 0) {
+          const uint32_t p = s[i - 1], pv = p >> kSmallRowBits, pch = (p & (kSmallMax - 1)) / kSmallRows;
+          seg = v != pv;
+          grp = seg || ch != pch;
+          gap = grp && (seg ? ch != 0u : ch != pch + 1u);
+        }
+        heads |= (uint32_t)grp << q;
+        segs |= (uint32_t)seg << q;
+        gaps |= (uint32_t)gap << q;
+      }
+    }
+    const uint32_t nw = (uint32_t)__popc(heads) + (uint32_t)__popc(gaps), ns = (uint32_t)__popc(segs);
+    uint32_t total;
+    const uint32_t pre = block_excl_scan<kSmallBlock>((ns << 16) | nw, s_scan, &total);
+    const uint32_t W = total & 0xFFFFu, D = total >> 16;
+    // publish this request's counts, then the look-back for the earlier ones
+    if (tid == 0) {
+      if (bad) {
+        atomicOr(bad_flag, 1u);
+        __threadfence();  // the flag is visible before the counts that follow it
+      }
+      lb_publish_raw(status + j, lb_pack_pair(W, D, j == 0 ? kLbInclusive : kLbAggregate));
+    }
+    if (tid < 64) {
+      LbPairSum p{0u, 0u};
+      if (j > 0) {
+        p = lb_lookback_ticket(status, j, LbPair{});
+        if (tid == 0) lb_publish_raw(status + j, lb_pack_pair(p.a + W, p.b + D, kLbInclusive));
+      }
+      if (tid == 0) {
+        s_pre[0] = p.a;
+        s_pre[1] = p.b;
+      }
+    }
+    __syncthreads();
+    const uint32_t wpre = s_pre[0], dpre = s_pre[1];
+    uint32_t w = wpre + (pre & 0xFFFFu), d = dpre + (pre >> 16);
+#pragma unroll
+    for (int q = 0; q < kSmallPer; ++q) {
+      if (!((heads >> q) & 1u)) continue;
+      const uint32_t i = e0 + q;
+      const uint32_t c = s[i], v = c >> kSmallRowBits, ch = (c & (kSmallMax - 1)) / kSmallRows;
+      const bool seg = (segs >> q) & 1u;
+      if (seg) {
+        keys[d] = v;
+        offsets[d + j] = w - wpre;  // relative to the request's own words
+        ++d;
+      }
+      if ((gaps >> q) & 1u) {
+        const uint32_t pch = seg ? 0u : (s[i - 1] & (kSmallMax - 1)) / kSmallRows;
+        words[w++] = kSmallFill | (seg ? ch : ch - pch - 1u);
+      }
+      // the literal: the bits of the group's rows (at most 31 elements)
+      uint32_t lit = 0;
+      for (uint32_t t = i; t < n; ++t) {
+        const uint32_t ct = s[t];
+        const uint32_t rt = ct & (kSmallMax - 1);
+        if ((ct >> kSmallRowBits) != v || rt / kSmallRows != ch) break;
+        lit |= 1u << (rt - ch * kSmallRows);
+      }
+      words[w++] = lit;
+    }
+    if (tid == 0) {
+      offsets[dpre + D + j] = W;
+      key_start[j] = dpre;
+      word_start[j] = wpre;
+      if (j == nreq - 1) {  // every earlier request is accounted for
+        key_start[nreq] = dpre + D;
+        word_start[nreq] = wpre + W;
+        __threadfence();
+        const bool rejected = __hip_atomic_load(bad_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        *len_keys = rejected ? 0u : dpre + D;
+        *len_offsets = rejected ? 0u : (uint64_t)dpre + D + nreq;
+        *len_words = rejected ? 0u : wpre + W;
+        *len_key_start = rejected ? 0u : (uint64_t)nreq + 1;
+        *len_word_start = rejected ? 0u : (uint64_t)nreq + 1;
+      }
+    }
+    __syncthreads();  // s, s_j and s_pre are reused by the next request
+  }
+}
+
+// The three-launch form of the small-request path:
+//   k_small_index  the fused kernel's sort and heads for request j =
+//                  blockIdx.x, its words, keys and offsets into slots bounded
+//                  by its size (words at 2 req_off[j], keys at req_off[j],
+//                  offsets at req_off[j] + j), and its counts and flag;
+//   k_small_starts scans the counts into key_start and word_start and sets the
+//                  output lengths (all 0 if a value was out of range);
+//   k_small_place  copies each request's slots to their places.
+// Every work-group is independent and the placement waits for a kernel
+// boundary instead of a look-back, at the price of the slots' extra traffic.
 __global__ __launch_bounds__(kSmallBlock) void k_small_index(const uint32_t* __restrict__ values,
                                                              const uint32_t* __restrict__ req_off,
                                                              uint32_t value_bits, uint32_t* __restrict__ wslot,
@@ -413,8 +571,12 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
   if (n && (!values || !keys || !words)) return env.fail(kErrArg, "wah_index_batch: null buffer");
   const uint32_t nn = (uint32_t)n;
 
-  if (max_req <= (uint32_t)kSmallMax && value_bits <= 32 - kSmallRowBits) {
-    // every request is small: one work-group per request
+  // Every request small: the three-launch form, or (sort variant 1, which the
+  // autotuner times with the others; not with per-request rejection) the
+  // persistent fused launch.
+  const bool small = max_req <= (uint32_t)kSmallMax && value_bits <= 32 - kSmallRowBits;
+  if (small && (sort_shape != 1 || req_bad)) {
+    // every request is small, three launches: one work-group per request, then the placement
     uint32_t* wslot = static_cast<uint32_t*>(env.scratch(8 * (n ? n : 1)));
     uint32_t* kslot = static_cast<uint32_t*>(env.scratch(4 * (n ? n : 1)));
     uint32_t* oslot = static_cast<uint32_t*>(env.scratch(4 * (n + nreq)));
@@ -435,6 +597,23 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
                                                                        key_start, word_start, keys, offsets, words);
     env.prof_end("batch_small_place");
     return check_launch(env, "batch_small_place launch");
+  }
+
+  if (small) {
+    // every request is small, variant 1: one persistent launch (after clearing
+    // its ticket, flag and status words)
+    uint32_t* ticket = static_cast<uint32_t*>(env.scratch(8));
+    uint64_t* status = static_cast<uint64_t*>(env.scratch(8ull * nreq));
+    if (!ticket || !status) return env.fail(kErrOom, "wah_index_batch: scratch");
+    int rc = launch_fill_u32(env, ticket, 2, 0);  // ticket and batch flag
+    if (!rc) rc = launch_fill_u64(env, status, nreq, 0);
+    if (rc) return rc;
+    env.prof_begin("batch_small_fused");
+    k_small_fused<<<dim3(std::min<uint32_t>(nreq, kSmallGrid)), dim3(kSmallBlock), 0, env.stream()>>>(
+        values, req_off, nreq, value_bits, ticket, status, ticket + 1, keys, offsets, words, key_start,
+        word_start, len_keys, len_offsets, len_words, len_key_start, len_word_start);
+    env.prof_end("batch_small_fused");
+    return check_launch(env, "batch_small_fused launch");
   }
 
   const bool segmented = value_bits <= 16 && sort_shape == 0;

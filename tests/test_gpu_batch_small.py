@@ -1,5 +1,6 @@
 """GPU parity of the batched index build on batches whose requests all hold at
-most 1024 values (one work-group per request: sort in LDS, encode, place).
+most 1024 values (one persistent launch: each work-group takes requests in
+turn, sorts one in LDS, encodes it and writes it after the earlier requests).
 Every request must equal the oracle's index of that request alone, and the
 same batch through the tagged-sort path (value_bits above 22, where the
 small-request path does not apply) must give the same bytes."""
@@ -146,3 +147,61 @@ def test_actor_size_hint(sess):
     finally:
         for r in refs:
             sess.release_ref(r)
+
+
+@pytest.mark.parametrize("count", [1, 2047, 2048, 2049, 5000])
+def test_small_requests_many_tickets(sess, count):
+    """Both forms of the small-request path: the three-launch form (ka_wah_batch)
+    and the persistent fused launch (a plan of sort variant 1), which has fewer
+    work-groups than requests, so each takes several in turn from the ticket
+    counter and writes a request's words and keys after all earlier requests'
+    (the look-back over requests).  A value out of range in a late request
+    rejects the batch in both."""
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import BatchPlan
+    off, v = workloads.batched_requests(seed=120 + count % 7, count=count, lo_log2=0, hi_log2=10)
+    _check(sess.wah_batch(v, off, 12), off, v)
+    j = count - 1 - count // 7  # a late request that is not empty
+    while off[j + 1] == off[j]:
+        j -= 1
+    bad = v.copy()
+    bad[off[j]] = 1 << 12
+    offu = off.astype(np.uint32)
+    res = ka.ka_wah_batch_result()
+    rc = ka.lib.ka_wah_batch(sess.sys, bad.ctypes.data, bad.size, offu.ctypes.data, count, 12, 0, ctypes.byref(res))
+    assert rc == ka.KA_E_ARG
+    plan = BatchPlan(sess, off, 12, shape=1)
+    try:
+        for x, ok in ((v, True), (bad, False), (v, True)):
+            plan.run(x)
+            if ok:
+                _check(plan.result(), off, x)
+            else:
+                with pytest.raises(ka.KaError) as e:
+                    plan.result()
+                assert e.value.code == ka.KA_E_ARG
+    finally:
+        plan.close()
+    _check(sess.wah_batch(v, off, 12), off, v)  # and the next batch is exact again
+
+
+@pytest.mark.parametrize("kind", ["uniform", "all_equal", "alternating_chunks", "sparse_hot"])
+def test_fused_launch_structured(sess, kind):
+    """The persistent fused launch on the structured layouts and every size
+    class of SMALL_SIZES, replayed."""
+    from paper_1709_07781_amd.session import BatchPlan
+    off = _offsets(SMALL_SIZES * 3)
+    parts = []
+    for i, n in enumerate(SMALL_SIZES * 3):
+        if kind == "uniform":
+            parts.append(workloads.uniform_values(700 + i, n, 1 << 12))
+        else:
+            parts.append(workloads.structured(kind, n, seed=800 + i) & np.uint32((1 << 12) - 1))
+    v = np.concatenate(parts).astype(np.uint32)
+    plan = BatchPlan(sess, off, 12, shape=1)
+    try:
+        for _ in range(3):
+            plan.run(v)
+            _check(plan.result(), off, v)
+    finally:
+        plan.close()
