@@ -389,14 +389,14 @@ def bench_batched(args) -> int:
         "graph": {"ms_per_step": g_ms, "value": N / (g_ms * 1e-3),
                   "how": "ka_batch_plan, autotuned: the same batch recorded into a HIP graph per sort tile "
                          "shape, the fastest on the first run replayed",
-                  "shape": tuned[0][0], "first_run_ms_per_shape": tuned[0][1][:3]},
+                  "shape": tuned[0][0], "first_run_ms_per_shape": tuned[0][1][:4]},
         "graph_any_batch": {"ms_per_step": ga_ms, "capacity_1p5x_ms_per_step": ga2_ms,
                             "how": "ka_batch_plan_create_any: one graph recorded for capacities (values, requests) "
                                    "that serves any batch within them; capacities equal to this batch, and 1.5 "
                                    "times it (the grids sized by the capacity, the counts read on the device)"},
         "small_batch": {"workload": "4096 requests, sizes log-uniform in [2^4, 2^10], values below 2^12",
                         "n": int(soff[-1]), "actor_ms": s_ms, "graph_ms": sg_ms, "plain_ms": sp_ms,
-                        "shape": tuned[1][0], "first_run_ms_per_shape": tuned[1][1][:3]},
+                        "shape": tuned[1][0], "first_run_ms_per_shape": tuned[1][1][:4]},
         "roofline": {"bound": "hbm", "kernel": "k_radix_scatter", "achieved": sc_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": sc_gbs / HBM_PEAK_GBS, "traffic": None,
                      "launches": sc_launches, "avg_launch_ms": sc_ms / max(sc_launches, 1),

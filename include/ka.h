@@ -425,9 +425,11 @@ KA_API int ka_wah_batch_result_free(ka_wah_batch_result* res);
  * KA_PLAN_AUTOTUNE it records one graph per sort variant and its first run
  * times them all on the real values and keeps the fastest: variant 0 sorts
  * each request inside its own positions over 16-bit keys when value_bits <=
- * 16 (ceil(value_bits / 8) passes, 1024 x 8 work-items x keys per tile), else
- * the request-tagged keys with that tile; variants 1 and 2 sort the
- * request-tagged 32-bit keys with 512 x 16 and 512 x 8.  A batch whose
+ * 16 (ceil(value_bits / 8) passes, the digits splitting value_bits evenly,
+ * 1024 x 8 work-items x keys per tile), else the request-tagged keys with
+ * that tile; variants 1 and 2 sort the request-tagged 32-bit keys with
+ * 512 x 16 and 512 x 8; variant 3 is variant 0 with 8-bit digits first (the
+ * rest in the second pass).  A batch whose
  * requests all hold at most 1024 values (and value_bits <= 22) takes the
  * small-request path instead: variants 0 and 2 are its three-launch form,
  * variant 1 one persistent fused launch (requests handed out by a ticket

@@ -68,6 +68,13 @@ int launch_radix_sort_pairs(Env& env, const uint32_t* keys, const uint32_t* rows
                             uint32_t* srows, uint64_t n, int shape = 0, const uint64_t* d_n = nullptr);
 // Number of tile shapes launch_radix_sort_pairs offers (shape 0 is the default).
 int sort_shape_count();
+// Number of variants of the batched index build (its sort_shape argument):
+// 0 the segmented sort with the even digit split for values of at most 16
+// bits, else the tagged sort with tile shape 0; 1 and 2 the tagged sort with
+// tile shapes 1 and 2; 3 the segmented sort with the byte digit split.  A
+// batch of small requests takes its own path: variant 1 the persistent fused
+// launch, the others the three-launch form.
+int batch_variant_count();
 // Sort of a batch of requests (request j: values[req_off[j] .. req_off[j+1]),
 // all below 2^value_bits, value_bits 1..16) by value inside each request,
 // stable: skeys[i] = j << value_bits | value, srows[i] = the position inside
@@ -76,7 +83,7 @@ int sort_shape_count();
 // clears them.
 int launch_radix_sort_segments(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
                                uint32_t value_bits, uint32_t* skeys, uint32_t* srows, uint32_t* bad,
-                               uint32_t* req_bad);
+                               uint32_t* req_bad, bool even_split = true);
 // Device address of the OR of all keys of the last launch_radix_sort_pairs on
 // this stream (valid once that sort has run, for n > 0).
 const uint32_t* sort_plan_keys_or(Env& env);

@@ -616,7 +616,7 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
     return check_launch(env, "batch_small_fused launch");
   }
 
-  const bool segmented = value_bits <= 16 && sort_shape == 0;
+  const bool segmented = value_bits <= 16 && (sort_shape == 0 || sort_shape == 3);
   uint32_t* bad = static_cast<uint32_t*>(env.scratch(4));
   uint32_t* tkeys = segmented ? bad : static_cast<uint32_t*>(env.scratch(4 * (n ? n : 1)));
   uint32_t* skeys = static_cast<uint32_t*>(env.scratch(4 * (n ? n : 1)));
@@ -634,7 +634,8 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
   // of nreq - 1 passes' worth of digits), rows made relative by the encoder.
   if (n) {
     if (segmented) {
-      if ((rc = launch_radix_sort_segments(env, values, n, req_off, nreq, value_bits, skeys, srows, bad, req_bad)))
+      if ((rc = launch_radix_sort_segments(env, values, n, req_off, nreq, value_bits, skeys, srows, bad, req_bad,
+                                           sort_shape != 3)))
         return rc;
     } else {
       const uint64_t blocks = (n + kKeyTile - 1) / kKeyTile;
@@ -643,7 +644,8 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
           values, tkeys, nn, req_off, nreq, TagOp{value_bits, req_bad}, bad, d_n);
       env.prof_end("batch_keys");
       if ((rc = check_launch(env, "batch_keys launch"))) return rc;
-      if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n, sort_shape, d_n))) return rc;
+      if ((rc = launch_radix_sort_pairs(env, tkeys, nullptr, skeys, srows, n, sort_shape == 3 ? 0 : sort_shape, d_n)))
+        return rc;
     }
   }
   // The tagged keys are the encoder's keys; rows are (or become) request-relative.

@@ -168,7 +168,8 @@ constexpr int kUpWaves = kUpBlock / 64;
 template <int kTile, int kRounds, bool kOrAnd, class SK>
 __device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32_t shift, uint32_t base, uint32_t len,
                                              uint32_t* __restrict__ table, uint64_t col, uint64_t stride,
-                                             uint32_t tile, uint32_t* __restrict__ orand) {
+                                             uint32_t tile, uint32_t* __restrict__ orand,
+                                             uint32_t mask = kRadix - 1) {
   constexpr int kUpVecs = kTile / 4 / kUpBlock;  // 4-key loads per work-item
   constexpr uintptr_t kAlign = 4 * sizeof(SK) - 1;
   __shared__ uint32_t s_hist[kUpWaves][kRadix];
@@ -200,14 +201,14 @@ __device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32
   // more there (measured on 16-bit Zipf keys: 62 -> 42 us; uniform keys 51 ->
   // 44 us).
   uint32_t c0 = 0, ch = 0;
-  const uint32_t hot = (uint32_t)__builtin_amdgcn_readfirstlane((int)((k[0][0] >> shift) & (kRadix - 1)));
+  const uint32_t hot = (uint32_t)__builtin_amdgcn_readfirstlane((int)((k[0][0] >> shift) & mask));
 #pragma unroll
   for (int j = 0; j < kUpVecs; ++j)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const bool valid = 4 * (j * kUpBlock + tid) + c < len;
       if (kRounds < 0) {
-        const uint32_t d = (k[j][c] >> shift) & (kRadix - 1);
+        const uint32_t d = (k[j][c] >> shift) & mask;
         if (valid) {
           if (d == hot)
             ++ch;
@@ -217,7 +218,7 @@ __device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32
             atomicAdd(&s_hist[w][d], 1u);
         }
       } else {
-        lds_add_aggregated<(kRounds < 0 ? 0 : kRounds)>(s_hist[w], (k[j][c] >> shift) & (kRadix - 1), valid);
+        lds_add_aggregated<(kRounds < 0 ? 0 : kRounds)>(s_hist[w], (k[j][c] >> shift) & mask, valid);
       }
       if (kOrAnd && valid) {
         kor |= k[j][c];
@@ -281,13 +282,13 @@ __global__ __launch_bounds__(kUpBlock) void k_radix_upsweep(PassBuffers buf, con
 // of the first pass clears *reject.
 template <int kTile, int kRounds, class SK>
 __global__ __launch_bounds__(kUpBlock) void k_radix_count(const SK* __restrict__ keys, uint32_t* __restrict__ table,
-                                                          uint32_t shift, uint32_t n_cap, uint32_t ntiles,
-                                                          uint32_t* __restrict__ reject,
+                                                          uint32_t shift, uint32_t mask, uint32_t n_cap,
+                                                          uint32_t ntiles, uint32_t* __restrict__ reject,
                                                           const uint64_t* __restrict__ d_n) {
   if (reject && blockIdx.x == 0 && threadIdx.x == 0) *reject = 0u;
   const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
   upsweep_tile<kTile, kRounds, false>(keys, shift, tile * kTile, tile_len(tile, kTile, n_cap, d_n), table, tile,
-                                      ntiles, tile, nullptr);
+                                      ntiles, tile, nullptr, mask);
 }
 
 // The sort plan from the OR and the AND of every tile's keys: a pass moves
@@ -403,12 +404,14 @@ __device__ __forceinline__ void scatter_load(const IO& io, uint32_t base, uint32
 // (their loads may still be in flight); dstart = the table entry of digit
 // threadIdx.x for this tile.  Starts and ends with a barrier.  With kCheck a
 // key at or above 2^check_shift sets *reject to 1.
-template <int kBlock, int kItems, bool kCheck = false, bool kTag = false, class IO>
+template <int kBlock, int kItems, bool kCheck = false, bool kTag = false, int kBits = kRadixBits, class IO>
 __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, const IO& io, uint32_t shift,
                                              uint32_t tile_n, uint32_t dstart, const uint32_t (&key)[kItems],
                                              const uint32_t (&row)[kItems], uint32_t check_shift = 32,
                                              uint32_t* reject = nullptr) {
   constexpr int kWaves = kBlock / 64;
+  static_assert(kBits >= 2 && kBits <= kRadixBits && kBits % 2 == 0, "digit widths 2, 4, 6, 8");
+  constexpr uint32_t kMask = (1u << kBits) - 1u;
   const uint32_t tid = threadIdx.x, w = tid / 64, lane = lane_id();
   const uint32_t wbase = w * 64 * kItems;
   for (int i = tid; i < kWaves * kRadix; i += kBlock) (&L.wcnt[0][0])[i] = 0;
@@ -420,16 +423,15 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     const bool valid = wbase + i * 64 + lane < tile_n;
-    const uint32_t d = (key[i] >> shift) & (kRadix - 1);
+    const uint32_t d = (key[i] >> shift) & kMask;
     uint32_t r = 0;
     // peers: the valid lanes whose digit equals this lane's, i.e. that differ
-    // from it in no digit bit
+    // from it in no digit bit (kBits / 2 bit pairs)
     uint32_t diff_lo = 0, diff_hi = 0;
-    static_assert(kRadixBits == 8, "four bit pairs");
     differing_lanes<0>(d, diff_lo, diff_hi);
-    differing_lanes<2>(d, diff_lo, diff_hi);
-    differing_lanes<4>(d, diff_lo, diff_hi);
-    differing_lanes<6>(d, diff_lo, diff_hi);
+    if (kBits > 2) differing_lanes<2>(d, diff_lo, diff_hi);
+    if (kBits > 4) differing_lanes<4>(d, diff_lo, diff_hi);
+    if (kBits > 6) differing_lanes<6>(d, diff_lo, diff_hi);
     const uint64_t peers = __ballot(valid) & ~(((uint64_t)diff_hi << 32) | diff_lo);
     if (valid) {
       const uint32_t below = (uint32_t)__popcll(peers & lt);
@@ -470,7 +472,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     if (wbase + i * 64 + lane < tile_n) {
-      const uint32_t d = (key[i] >> shift) & (kRadix - 1);
+      const uint32_t d = (key[i] >> shift) & kMask;
       const uint32_t pos = L.loff[d] + L.wcnt[w][d] + rank[i];
       L.kr[pos] = make_uint2(key[i], row[i]);
     }
@@ -484,7 +486,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
     if (p < tile_n) {
       const uint2 v = L.kr[p];
       const uint32_t k = v.x;
-      const uint32_t g = L.dbase[(k >> shift) & (kRadix - 1)] + p;
+      const uint32_t g = L.dbase[(k >> shift) & kMask] + p;
       io.dst_keys[g] = (std::remove_pointer_t<decltype(io.dst_keys)>)(kTag ? (k & io.key_and) | io.key_or : k);
       io.dst_rows[g] = v.y;
     }
@@ -517,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
 // Scatter of a fixed pass (no plan): keys uint32 or uint16 on either side.
 // With kCheck (the first pass of the narrow-key sort) a key at or above
 // 2^check_shift sets *reject.
-template <int kBlock, int kItems, bool kCheck, class SK, class DK>
+template <int kBlock, int kItems, bool kCheck, int kBits, class SK, class DK>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter_fixed(PassIoT<SK, DK> io, const uint32_t* __restrict__ table,
                                                                 uint32_t shift, uint32_t n_cap, uint32_t ntiles,
                                                                 uint32_t check_shift, uint32_t* __restrict__ reject,
@@ -531,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter_fixed(PassIoT<SK, DK> 
   const uint32_t dstart = threadIdx.x < kRadix ? table[(uint64_t)threadIdx.x * ntiles + tile] : 0u;
   uint32_t key[kItems], row[kItems];
   scatter_load<kBlock, kItems>(io, base, tile_n, key, row);
-  scatter_tile<kBlock, kItems, kCheck>(L, io, shift, tile_n, dstart, key, row, check_shift, reject);
+  scatter_tile<kBlock, kItems, kCheck, false, kBits>(L, io, shift, tile_n, dstart, key, row, check_shift, reject);
 }
 
 }  // namespace
@@ -656,20 +658,21 @@ __device__ __forceinline__ SegTile seg_tile(const uint32_t* __restrict__ req_off
 
 template <int kTile, int kRounds, class SK>
 __global__ __launch_bounds__(kUpBlock) void k_seg_count(const SK* __restrict__ keys, uint32_t* __restrict__ table,
-                                                        uint32_t shift, const uint32_t* __restrict__ req_off,
+                                                        uint32_t shift, uint32_t mask,
+                                                        const uint32_t* __restrict__ req_off,
                                                         const uint32_t* __restrict__ tile_base, uint32_t nreq,
                                                         uint32_t ub) {
   const uint32_t t = xcd_tile(blockIdx.x, ub);
   if (t >= tile_base[nreq]) return;  // uniform over the work-group
   const SegTile s = seg_tile<kTile>(req_off, tile_base, nreq, t);
   upsweep_tile<kTile, kRounds, false>(keys, shift, s.base, s.len, table, (uint64_t)kRadix * tile_base[s.j] + s.l, s.nt,
-                                      t, nullptr);
+                                      t, nullptr, mask);
 }
 
 // kCheck (the first pass): a key at or above 2^value_bits flags its request
 // (req_bad[j]) or, without req_bad, the batch (*bad).  kTag (the last pass):
 // keys are written as j << value_bits | key.
-template <int kBlock, int kItems, bool kCheck, bool kTag, class SK, class DK>
+template <int kBlock, int kItems, bool kCheck, bool kTag, int kBits, class SK, class DK>
 __global__ __launch_bounds__(kBlock) void k_seg_scatter(PassIoT<SK, DK> io, const uint32_t* __restrict__ table,
                                                         uint32_t shift, const uint32_t* __restrict__ req_off,
                                                         const uint32_t* __restrict__ tile_base, uint32_t nreq,
@@ -689,22 +692,80 @@ __global__ __launch_bounds__(kBlock) void k_seg_scatter(PassIoT<SK, DK> io, cons
   }
   uint32_t key[kItems], row[kItems];
   scatter_load<kBlock, kItems>(io, s.base, s.len, key, row);
-  scatter_tile<kBlock, kItems, kCheck, kTag>(L, io, shift, s.len, dstart, key, row, value_bits,
-                                             req_bad ? req_bad + s.j : bad);
+  scatter_tile<kBlock, kItems, kCheck, kTag, kBits>(L, io, shift, s.len, dstart, key, row, value_bits,
+                                                    req_bad ? req_bad + s.j : bad);
+}
+
+// Digits of a fixed-pass sort of values below 2^value_bits (value_bits 1..16):
+// pass p ranks `bits` bits from `shift` on.  The byte split takes 8 bits, then
+// the rest; the even split halves value_bits.  Widths are rounded up to even
+// (the ranking takes the bits in pairs): bits above value_bits are 0 in every
+// key that passes the range check, and a key that fails it is flagged and its
+// result discarded, so masking them only keeps its ranks in range.
+struct DigitSplit {
+  uint32_t passes;
+  uint32_t shift[2], bits[2];
+};
+
+DigitSplit digit_split(uint32_t value_bits, bool even) {
+  auto up2 = [](uint32_t b) { return (b + 1u) & ~1u; };
+  DigitSplit d{};
+  d.passes = (value_bits + kRadixBits - 1) / kRadixBits;
+  if (d.passes == 1) {
+    d.shift[0] = 0;
+    d.bits[0] = up2(value_bits);
+    return d;
+  }
+  const uint32_t b0 = even ? up2((value_bits + 1) / 2) : (uint32_t)kRadixBits;
+  d.shift[0] = 0;
+  d.bits[0] = b0;
+  d.shift[1] = b0;
+  d.bits[1] = up2(value_bits - b0);
+  return d;
+}
+
+// Launch of a fixed-pass scatter for a digit width known at run time.
+template <int kBits, int kBlock, int kItems, bool kCheck, class SK, class DK>
+void scatter_fixed_bits(Env& env, uint32_t grid, const PassIoT<SK, DK>& io, const uint32_t* offs, uint32_t shift,
+                        uint32_t nn, uint32_t ntiles, uint32_t check_shift, uint32_t* reject, const uint64_t* d_n) {
+  k_radix_scatter_fixed<kBlock, kItems, kCheck, kBits><<<dim3(grid), dim3(kBlock), 0, env.stream()>>>(
+      io, offs, shift, nn, ntiles, check_shift, reject, d_n);
+}
+
+template <int kBlock, int kItems, bool kCheck, class SK, class DK>
+void scatter_fixed(Env& env, uint32_t bits, uint32_t grid, const PassIoT<SK, DK>& io, const uint32_t* offs,
+                   uint32_t shift, uint32_t nn, uint32_t ntiles, uint32_t check_shift, uint32_t* reject,
+                   const uint64_t* d_n) {
+  switch (bits) {
+    case 2:
+      return scatter_fixed_bits<2, kBlock, kItems, kCheck>(env, grid, io, offs, shift, nn, ntiles, check_shift, reject,
+                                                            d_n);
+    case 4:
+      return scatter_fixed_bits<4, kBlock, kItems, kCheck>(env, grid, io, offs, shift, nn, ntiles, check_shift, reject,
+                                                            d_n);
+    case 6:
+      return scatter_fixed_bits<6, kBlock, kItems, kCheck>(env, grid, io, offs, shift, nn, ntiles, check_shift, reject,
+                                                            d_n);
+    default:
+      return scatter_fixed_bits<8, kBlock, kItems, kCheck>(env, grid, io, offs, shift, nn, ntiles, check_shift, reject,
+                                                            d_n);
+  }
 }
 
 // The narrow-key sort: keys below 2^value_bits, value_bits <= 16, rows
-// 0..n-1.  ceil(value_bits / 8) fixed passes (no plan, no skipped launches);
-// from the first pass on the keys are stored as uint16 (6 bytes per pair
-// instead of 8).  The first pass flags a key at or above 2^value_bits in
-// *reject (cleared by its upsweep); the sort's output is then unspecified.
+// 0..n-1.  ceil(value_bits / 8) fixed passes (no plan, no skipped launches)
+// with the even split of digit_split; from the first pass on the keys are
+// stored as uint16 (6 bytes per pair instead of 8).  The first pass flags a
+// key at or above 2^value_bits in *reject (cleared by its upsweep); the sort's
+// output is then unspecified.
 template <int kBlock, int kItems>
 int sort16_with_shape(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t* srows, uint64_t n,
                       uint32_t value_bits, uint32_t* reject, const uint64_t* d_n) {
   constexpr int kTile = kBlock * kItems;
   const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
   const uint32_t nn = (uint32_t)n;
-  const uint32_t passes = (value_bits + kRadixBits - 1) / kRadixBits;
+  const DigitSplit ds = digit_split(value_bits, true);
+  const uint32_t passes = ds.passes;
   uint16_t* kb = nullptr;
   uint32_t* rb = nullptr;
   if (passes > 1) {
@@ -719,42 +780,69 @@ int sort16_with_shape(Env& env, const uint32_t* keys, uint16_t* skeys, uint32_t*
   int rc;
   // pass 0: uint32 values in, uint16 keys out
   env.prof_begin("radix_upsweep0");
-  k_radix_count<kTile, 1, uint32_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(keys, table, 0, nn, ntiles,
-                                                                                       reject, d_n);
+  k_radix_count<kTile, 1, uint32_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(
+      keys, table, ds.shift[0], (1u << ds.bits[0]) - 1u, nn, ntiles, reject, d_n);
   env.prof_end("radix_upsweep0");
   if ((rc = check_launch(env, "radix_count launch"))) return rc;
   if ((rc = launch_exclusive_scan(env, table, offs, tlen, nullptr))) return rc;
   PassIoT<uint32_t, uint16_t> io0{keys, nullptr, passes > 1 ? kb : skeys, passes > 1 ? rb : srows, true};
   env.prof_begin("radix_scatter");
-  k_radix_scatter_fixed<kBlock, kItems, true><<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(
-      io0, offs, 0u, nn, ntiles, value_bits, reject, d_n);
+  scatter_fixed<kBlock, kItems, true>(env, ds.bits[0], ntiles, io0, offs, ds.shift[0], nn, ntiles, value_bits, reject,
+                                      d_n);
   env.prof_end("radix_scatter");
   if ((rc = check_launch(env, "radix_scatter launch"))) return rc;
   if (passes == 1) return kOk;
   // pass 1: uint16 keys in and out
   env.prof_begin("radix_upsweep");
-  k_radix_count<kTile, -1, uint16_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(kb, table, kRadixBits, nn,
-                                                                                       ntiles, nullptr, d_n);
+  k_radix_count<kTile, -1, uint16_t><<<dim3(ntiles), dim3(kUpBlock), 0, env.stream()>>>(
+      kb, table, ds.shift[1], (1u << ds.bits[1]) - 1u, nn, ntiles, nullptr, d_n);
   env.prof_end("radix_upsweep");
   if ((rc = check_launch(env, "radix_count launch"))) return rc;
   if ((rc = launch_exclusive_scan(env, table, offs, tlen, nullptr))) return rc;
   PassIoT<uint16_t, uint16_t> io1{kb, rb, skeys, srows, false};
   env.prof_begin("radix_scatter");
-  k_radix_scatter_fixed<kBlock, kItems, false><<<dim3(ntiles), dim3(kBlock), 0, env.stream()>>>(
-      io1, offs, kRadixBits, nn, ntiles, 32u, nullptr, d_n);
+  scatter_fixed<kBlock, kItems, false>(env, ds.bits[1], ntiles, io1, offs, ds.shift[1], nn, ntiles, 32u, nullptr,
+                                       d_n);
   env.prof_end("radix_scatter");
   return check_launch(env, "radix_scatter launch");
 }
 
+// Launch of a segmented scatter for a digit width known at run time.
+template <int kBlock, int kItems, bool kCheck, bool kTag, class SK, class DK>
+void seg_scatter(Env& env, uint32_t bits, uint32_t grid, const PassIoT<SK, DK>& io, const uint32_t* offs,
+                 uint32_t shift, const uint32_t* req_off, const uint32_t* tile_base, uint32_t nreq, uint32_t ub,
+                 uint32_t value_bits, uint32_t* bad, uint32_t* req_bad) {
+#define KA_SEG_SCATTER(B)                                                                                   \
+  k_seg_scatter<kBlock, kItems, kCheck, kTag, B><<<dim3(grid), dim3(kBlock), 0, env.stream()>>>(          \
+      io, offs, shift, req_off, tile_base, nreq, ub, value_bits, bad, req_bad)
+  switch (bits) {
+    case 2:
+      KA_SEG_SCATTER(2);
+      break;
+    case 4:
+      KA_SEG_SCATTER(4);
+      break;
+    case 6:
+      KA_SEG_SCATTER(6);
+      break;
+    default:
+      KA_SEG_SCATTER(8);
+      break;
+  }
+#undef KA_SEG_SCATTER
+}
+
 // The segmented sort of a batch (values below 2^value_bits, value_bits <= 16):
-// uint16 keys between passes, request-relative rows, tagged uint32 keys out.
+// uint16 keys between passes, request-relative rows, tagged uint32 keys out;
+// the byte or the even digit split.
 int seg_sort(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
-             uint32_t value_bits, uint32_t* skeys, uint32_t* srows, uint32_t* bad, uint32_t* req_bad) {
+             uint32_t value_bits, uint32_t* skeys, uint32_t* srows, uint32_t* bad, uint32_t* req_bad, bool even) {
   constexpr int kBlock = kShapes[0].block, kItems = kShapes[0].items, kTile = kBlock * kItems;
-  const uint32_t passes = (value_bits + kRadixBits - 1) / kRadixBits;
+  const DigitSplit ds = digit_split(value_bits, even);
+  const uint32_t passes = ds.passes;
   const uint64_t ub64 = (n + kTile - 1) / kTile + nreq;  // tiles: at most one more per request
   if (ub64 >= (1ull << 31)) return env.fail(kErrArg, "segmented sort: too many tiles");
-  const uint32_t ub = (uint32_t)ub64, nn = (uint32_t)n;
+  const uint32_t ub = (uint32_t)ub64;
   uint32_t* ntiles = static_cast<uint32_t*>(env.scratch(4ull * (nreq + 1)));
   uint32_t* tile_base = static_cast<uint32_t*>(env.scratch(4ull * (nreq + 1)));
   uint64_t* tlen = static_cast<uint64_t*>(env.scratch(8));
@@ -776,35 +864,35 @@ int seg_sort(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_o
   const uint64_t tcap = (uint64_t)kRadix * ub;
   // pass 0: uint32 values in (checked), uint16 keys out -- or tagged keys if it is the only pass
   env.prof_begin("radix_upsweep0");
-  k_seg_count<kTile, 1, uint32_t><<<dim3(ub), dim3(kUpBlock), 0, env.stream()>>>(values, table, 0, req_off, tile_base,
-                                                                                  nreq, ub);
+  k_seg_count<kTile, 1, uint32_t><<<dim3(ub), dim3(kUpBlock), 0, env.stream()>>>(
+      values, table, ds.shift[0], (1u << ds.bits[0]) - 1u, req_off, tile_base, nreq, ub);
   env.prof_end("radix_upsweep0");
   if ((rc = check_launch(env, "seg_count launch"))) return rc;
   if ((rc = launch_exclusive_scan(env, table, offs, tcap, tlen))) return rc;
   env.prof_begin("radix_scatter");
   if (passes == 1) {
     PassIoT<uint32_t, uint32_t> io{values, nullptr, skeys, srows, true};
-    k_seg_scatter<kBlock, kItems, true, true><<<dim3(ub), dim3(kBlock), 0, env.stream()>>>(
-        io, offs, 0u, req_off, tile_base, nreq, ub, value_bits, bad, req_bad);
+    seg_scatter<kBlock, kItems, true, true>(env, ds.bits[0], ub, io, offs, ds.shift[0], req_off, tile_base, nreq, ub,
+                                            value_bits, bad, req_bad);
   } else {
     PassIoT<uint32_t, uint16_t> io{values, nullptr, kb, rb, true};
-    k_seg_scatter<kBlock, kItems, true, false><<<dim3(ub), dim3(kBlock), 0, env.stream()>>>(
-        io, offs, 0u, req_off, tile_base, nreq, ub, value_bits, bad, req_bad);
+    seg_scatter<kBlock, kItems, true, false>(env, ds.bits[0], ub, io, offs, ds.shift[0], req_off, tile_base, nreq, ub,
+                                             value_bits, bad, req_bad);
   }
   env.prof_end("radix_scatter");
   if ((rc = check_launch(env, "seg_scatter launch"))) return rc;
   if (passes == 1) return kOk;
   // pass 1: uint16 keys in, tagged uint32 keys out
   env.prof_begin("radix_upsweep");
-  k_seg_count<kTile, -1, uint16_t><<<dim3(ub), dim3(kUpBlock), 0, env.stream()>>>(kb, table, kRadixBits, req_off,
-                                                                                  tile_base, nreq, ub);
+  k_seg_count<kTile, -1, uint16_t><<<dim3(ub), dim3(kUpBlock), 0, env.stream()>>>(
+      kb, table, ds.shift[1], (1u << ds.bits[1]) - 1u, req_off, tile_base, nreq, ub);
   env.prof_end("radix_upsweep");
   if ((rc = check_launch(env, "seg_count launch"))) return rc;
   if ((rc = launch_exclusive_scan(env, table, offs, tcap, tlen))) return rc;
   PassIoT<uint16_t, uint32_t> io1{kb, rb, skeys, srows, false};
   env.prof_begin("radix_scatter");
-  k_seg_scatter<kBlock, kItems, false, true><<<dim3(ub), dim3(kBlock), 0, env.stream()>>>(
-      io1, offs, kRadixBits, req_off, tile_base, nreq, ub, value_bits, bad, req_bad);
+  seg_scatter<kBlock, kItems, false, true>(env, ds.bits[1], ub, io1, offs, ds.shift[1], req_off, tile_base, nreq, ub,
+                                           value_bits, bad, req_bad);
   env.prof_end("radix_scatter");
   return check_launch(env, "seg_scatter launch");
 }
@@ -812,16 +900,17 @@ int seg_sort(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_o
 }  // namespace
 
 int sort_shape_count() { return kNumShapes; }
+int batch_variant_count() { return kNumShapes + 1; }
 
 int launch_radix_sort_segments(Env& env, const uint32_t* values, uint64_t n, const uint32_t* req_off, uint32_t nreq,
                                uint32_t value_bits, uint32_t* skeys, uint32_t* srows, uint32_t* bad,
-                               uint32_t* req_bad) {
+                               uint32_t* req_bad, bool even_split) {
   if (n == 0) return kOk;
   if (!values || !req_off || !skeys || !srows || !bad || nreq == 0)
     return env.fail(kErrArg, "segmented sort: null buffer");
   if (value_bits == 0 || value_bits > 16) return env.fail(kErrArg, "segmented sort: value_bits must be 1..16");
   if (n >= (1ull << 31)) return env.fail(kErrArg, "segmented sort: n must be below 2^31");
-  return seg_sort(env, values, n, req_off, nreq, value_bits, skeys, srows, bad, req_bad);
+  return seg_sort(env, values, n, req_off, nreq, value_bits, skeys, srows, bad, req_bad, even_split);
 }
 
 const uint32_t* sort_plan_keys_or(Env& env) {

@@ -207,12 +207,12 @@ static int plan_build(ka_system* sys, const uint32_t* req_off, uint64_t n, uint3
   }
   // ---- record the pipeline, once per tile shape tried ---------------------------------
   const int forced = (int)((flags >> 8) & 0xFFu) - 1;  // KA_PLAN_SHAPE(s): record shape s only
-  if (forced >= sort_shape_count()) {
+  if (forced >= batch_variant_count()) {
     plan_free(p);
     return set_error(KA_E_ARG, "unknown tile shape");
   }
   p->forced = forced;
-  p->shapes = (flags & KA_PLAN_AUTOTUNE) && forced < 0 ? std::min(sort_shape_count(), 4) : 1;
+  p->shapes = (flags & KA_PLAN_AUTOTUNE) && forced < 0 ? std::min(batch_variant_count(), 4) : 1;
   p->chosen = p->shapes > 1 ? -1 : 0;
   for (int v = 0; v < p->shapes; ++v) {
     const int shape = forced >= 0 ? forced : v;
@@ -303,6 +303,9 @@ KA_API int ka_batch_plan_run(ka_batch_plan* plan, const uint32_t* values, uint32
   if (plan->chosen < 0) {
     // Autotuning: the first run times every recorded shape on these values
     // (each leaves the same outputs) and keeps the fastest for later runs.
+    // Each graph is launched once untimed first: a graph's first launch pays
+    // one-time costs that would count against whichever variant is timed
+    // first.
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
       (void)hipGetLastError();
@@ -310,6 +313,13 @@ KA_API int ka_batch_plan_run(ka_batch_plan* plan, const uint32_t* values, uint32
       return set_error(KA_E_DEVICE, "plan: events");
     }
     int best = 0;
+    for (int v = 0; v < plan->shapes; ++v)
+      if (hipGraphLaunch(plan->exec[v], plan->s) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return set_error(KA_E_LAUNCH, "plan: autotuning warm-up");
+      }
     for (int v = 0; v < plan->shapes; ++v) {
       if (hipEventRecord(a, plan->s) != hipSuccess || hipGraphLaunch(plan->exec[v], plan->s) != hipSuccess ||
           hipEventRecord(b, plan->s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||

@@ -156,7 +156,7 @@ def test_batch_tagged_path_rejects_wide_values(sess):
     _check(got, off, good, oracle.default())
 
 
-@pytest.mark.parametrize("bits", [4, 8, 9, 12, 16, 17, 20])
+@pytest.mark.parametrize("bits", [1, 2, 3, 4, 7, 8, 9, 10, 12, 13, 15, 16, 17, 20])
 def test_batch_value_widths_and_tile_edges(sess, bits):
     """Values of 1..16 bits take the segmented sort (tiles cut at request
     boundaries and at the multiples of 8192, one or two passes over 16-bit
@@ -169,3 +169,32 @@ def test_batch_value_widths_and_tile_edges(sess, bits):
     v[:: 97] = (1 << bits) - 1  # the largest value appears in most requests
     res = sess.wah_batch(v, off, bits)
     _check(res, off, v, oracle.default())
+
+
+@pytest.mark.parametrize("bits", [1, 3, 5, 9, 12, 13, 16])
+def test_byte_digit_split(sess, bits):
+    """The segmented sort with the byte digit split (batch variant 3: 8 bits,
+    then the rest rounded up to even; variant 0, which ka_wah_batch takes,
+    splits value_bits evenly) against the oracle, on the same request layout;
+    and a value out of range rejects the batch."""
+    import paper_1709_07781_amd as ka
+    from paper_1709_07781_amd.session import BatchPlan
+    sizes = [0, 1, 8191, 8192, 8193, 3, 0, 20000, 16384 + 5, 7, 0, 40000, 1, 8192 * 3 - 2]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    v = workloads.uniform_values(50 + bits, int(off[-1]), 1 << bits)
+    v[:: 89] = (1 << bits) - 1
+    plan = BatchPlan(sess, off, bits, shape=3)
+    try:
+        plan.run(v)
+        _check(plan.result(), off, v, oracle.default())
+        bad = v.copy()
+        bad[int(off[8]) + 11] = 1 << bits
+        plan.run(bad)
+        with pytest.raises(ka.KaError) as e:
+            plan.result()
+        assert e.value.code == ka.KA_E_ARG
+        plan.run(v)
+        _check(plan.result(), off, v, oracle.default())
+    finally:
+        plan.close()

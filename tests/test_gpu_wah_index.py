@@ -53,7 +53,7 @@ def test_narrow_keys(sess, ora, bits, kind, n):
     _check(sess.wah_index(v, value_bits=bits), ora.wah_index(v), f"bits={bits} {kind} n={n}")
 
 
-@pytest.mark.parametrize("bits", [1, 2, 9, 15])
+@pytest.mark.parametrize("bits", [1, 2, 3, 5, 7, 9, 10, 11, 13, 14, 15])
 @pytest.mark.parametrize("n", [ENC_TILE + 31, 5 * SORT_TILE + 3, 70_001])
 def test_narrow_keys_other_widths(sess, ora, bits, n):
     v = _values("u32", n, bits, seed=n + bits)
