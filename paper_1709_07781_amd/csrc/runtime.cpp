@@ -1532,6 +1532,85 @@ static int wah_actor(ka_system* sys, uint32_t value_bits, uint32_t format, ka_ac
   return KA_OK;
 }
 
+// The lengths of an index's three outputs (written on the device by one launch,
+// so on one stream) in one round trip: three 8-byte copies into pinned memory,
+// one synchronisation.  Each becomes the ref's host-known length.
+static int read_lengths3(System* sys, Ref* const r[3], uint64_t len[3]) {
+  const uint32_t home = r[0]->home;
+  if (r[1]->home != home || r[2]->home != home) {
+    for (int i = 0; i < 3; ++i) {
+      int rc = ref_length(r[i], &len[i]);
+      if (rc) return rc;
+    }
+    return KA_OK;
+  }
+  uint64_t* hl = static_cast<uint64_t*>(sys->stage.get(sys, 3 * sizeof(uint64_t)));
+  if (!hl) return set_error(KA_E_OOM, "pinned staging");
+  hipStream_t s = sys->streams[home]->s;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+    if (r[i]->len_known.load())
+      hl[i] = r[i]->len;
+    else
+      e = hipMemcpyAsync(&hl[i], r[i]->d_len, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    sys->stage.give_back(hl);
+    return set_error(KA_E_DEVICE, "length read-back");
+  }
+  for (int i = 0; i < 3; ++i) {
+    if (!r[i]->len_known.load()) {
+      sys->length_reads.fetch_add(1);
+      r[i]->len = std::min<uint64_t>(hl[i], r[i]->cap);
+      r[i]->len_known.store(true);
+    }
+    len[i] = r[i]->len;
+  }
+  sys->stage.give_back(hl);
+  return KA_OK;
+}
+
+// Host copies of three outputs of one stream after their lengths are known:
+// through one pinned staging buffer and one synchronisation when they are
+// small, else one blocking copy each.
+static int read_outputs3(System* sys, Ref* const r[3], void* const dst[3], const uint64_t bytes[3]) {
+  constexpr uint64_t kStagedMax = 8ull << 20;
+  const uint64_t total = bytes[0] + bytes[1] + bytes[2];
+  const uint32_t home = r[0]->home;
+  if (total == 0) return KA_OK;
+  if (total > kStagedMax || r[1]->home != home || r[2]->home != home) {
+    for (int i = 0; i < 3; ++i) {
+      int rc = bytes[i] ? ka_ref_read(static_cast<ka_ref*>(r[i]), dst[i], bytes[i]) : KA_OK;
+      if (rc) return rc;
+    }
+    return KA_OK;
+  }
+  char* st = static_cast<char*>(sys->stage.get(sys, total));
+  if (!st) return set_error(KA_E_OOM, "pinned staging");
+  hipStream_t s = sys->streams[home]->s;
+  hipError_t e = hipSuccess;
+  uint64_t off = 0;
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+    if (bytes[i]) e = hipMemcpyAsync(st + off, r[i]->ptr, bytes[i], hipMemcpyDeviceToHost, s);
+    off += bytes[i];
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    sys->stage.give_back(st);
+    return set_error(KA_E_DEVICE, "result read-back");
+  }
+  off = 0;
+  for (int i = 0; i < 3; ++i) {
+    if (bytes[i]) std::memcpy(dst[i], st + off, bytes[i]);
+    off += bytes[i];
+  }
+  sys->stage.give_back(st);
+  return KA_OK;
+}
+
 KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint32_t flags, ka_wah_result* out) {
   KA_GUARD_BEGIN
   if (!sys || !out || (n && !values)) return set_error(KA_E_ARG, "null argument");
@@ -1571,10 +1650,10 @@ KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint
   if (rc) return rc;
   ka_wah_result r{};
   r.n = n;
-  uint64_t D = 0, W = 0, O = 0;
-  rc = ref_length(res[0].ref, &D);
-  if (!rc) rc = ref_length(res[1].ref, &O);
-  if (!rc) rc = ref_length(res[2].ref, &W);
+  Ref* const outs[3] = {static_cast<Ref*>(res[0].ref), static_cast<Ref*>(res[1].ref), static_cast<Ref*>(res[2].ref)};
+  uint64_t lens[3] = {0, 0, 0};
+  rc = read_lengths3(sys, outs, lens);
+  const uint64_t D = lens[0], O = lens[1], W = lens[2];
   if (!rc && O == 0 && n > 0) rc = set_error(KA_E_ARG, "a value is at or above 2^value_bits");
   if (!rc && O != D + 1) rc = set_error(KA_E_DEVICE, "inconsistent index lengths");
   if (!rc) {
@@ -1591,9 +1670,11 @@ KA_API int ka_wah_index(ka_system* sys, const uint32_t* values, uint64_t n, uint
     r.offsets = static_cast<uint32_t*>(std::malloc((D + 1) * 4));
     r.words = static_cast<uint32_t*>(std::malloc(std::max<uint64_t>(W, 1) * 4));
     if (!r.keys || !r.offsets || !r.words) rc = set_error(KA_E_OOM, "host allocation failed");
-    if (!rc) rc = ka_ref_read(res[0].ref, r.keys, D * 4);
-    if (!rc) rc = ka_ref_read(res[1].ref, r.offsets, (D + 1) * 4);
-    if (!rc) rc = ka_ref_read(res[2].ref, r.words, W * 4);
+    if (!rc) {
+      void* const dst[3] = {r.keys, r.offsets, r.words};
+      const uint64_t bytes[3] = {D * 4, (D + 1) * 4, W * 4};
+      rc = read_outputs3(sys, outs, dst, bytes);
+    }
   }
   for (auto& v : res)
     if (v.ref) ka_ref_release(v.ref);
