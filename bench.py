@@ -121,6 +121,40 @@ def timed_oracle(o, v, runs: int):
     return times, res
 
 
+def batched_oracle_leg(off, v, budget_s: float = 20.0) -> dict:
+    """The oracle on the batch's requests, one request per host thread at a
+    time (the oracle is a C library called through ctypes, which releases the
+    GIL, so a thread pool runs requests in parallel), over the first requests
+    of the batch up to about budget_s of work: elements/s and the threads used."""
+    import concurrent.futures as cf
+
+    import oracle
+
+    o = oracle.default()
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    threads = max(1, min(threads, 64))
+    nreq = len(off) - 1
+    # size the sample from one request's rate (about 1.1e7 elements/s per core)
+    per_core = 1.1e7
+    cap = budget_s * per_core * threads
+    k = 0
+    while k < nreq and off[k + 1] <= cap:
+        k += 1
+    k = max(k, 1)
+    parts = [v[off[j]:off[j + 1]] for j in range(k)]
+    c0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(o.wah_index, parts))
+    t = time.perf_counter() - c0
+    elems = int(off[k])
+    return {"value": elems / t, "unit": "elements/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {k} of {nreq} requests ({elems} elements), one request per thread at a time",
+            "seconds": t, "host": host_info()}
+
+
 def plain_request_leg(sess, args) -> dict:
     """The plain configuration: one request of 2^16 values uniform below 1024
     through ka_wah_index, host values in and host arrays out (the paper's
@@ -409,6 +443,10 @@ def bench_batched(args) -> int:
         "kernel_ms_per_step": {k: prof[k][1] / args.steps for k in prof if prof[k][0]},
         "parity": parity,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batched_oracle_leg(off, v)
+        log(f"[bench] batched oracle: {out['cpu_baseline']['value']:.3g} elements/s on "
+            f"{out['cpu_baseline']['cores']} threads ({out['cpu_baseline']['sample']})")
     print(json.dumps(out), flush=True)
     return 0 if parity in (None, "bit-exact (requests sampled)") else 1
 
