@@ -59,6 +59,9 @@ class Env {
 // Launchers (one file each).  They queue work on env.stream() and return a
 // KA_* code.  `d_n`, when not null, points to the true element count on the
 // device (at most n_cap), written by an earlier stage.
+// The stages x <- a[i] x + b[i], i = 0 .. len-1, applied in one pass over x
+// (one launch per 16 stages): the served form's chain requests.
+int launch_affine_chain(Env& env, uint32_t* x, uint64_t n, const uint32_t* a, const uint32_t* b, uint32_t len);
 int launch_affine(Env& env, uint32_t* x, uint64_t n_cap, const uint64_t* d_n, uint64_t offset, uint32_t a,
                   uint32_t b);
 int launch_exclusive_scan(Env& env, const uint32_t* in, uint32_t* out, uint64_t n_cap, const uint64_t* d_n);

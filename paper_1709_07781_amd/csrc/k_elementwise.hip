@@ -3,6 +3,8 @@
 // stage probe, Sec. 5.2-5.3), and small fill kernels used instead of
 // hipMemsetAsync so that the queued work stays capturable in a hipGraph.
 
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace ka {
@@ -11,13 +13,28 @@ namespace {
 constexpr int kAffBlock = 256;
 constexpr int kAffVecPerThread = 4;                                  // uint4 per thread
 constexpr int kAffTile = kAffBlock * kAffVecPerThread * 4;           // elements per work-group
+constexpr uint32_t kChainMax = 16;                                   // stages per fused pass
+
+// One affine stage, or up to kChainMax stages applied in turn in one pass
+// (x <- a_i x + b_i for i = 0 .. len-1, all mod 2^32).
+struct Affine1 {
+  uint32_t a, b;
+  __device__ __forceinline__ uint32_t operator()(uint32_t x) const { return a * x + b; }
+};
+struct AffineChain {
+  uint32_t a[kChainMax], b[kChainMax];
+  uint32_t len;
+  __device__ __forceinline__ uint32_t operator()(uint32_t x) const {
+    for (uint32_t i = 0; i < len; ++i) x = a[i] * x + b[i];
+    return x;
+  }
+};
 
 // One work-group handles kAffTile consecutive elements; every load and store
 // is a coalesced 16-byte access when the buffer is 16-byte aligned.
-template <bool kVec>
+template <bool kVec, class Op>
 __global__ __launch_bounds__(kAffBlock) void k_affine_u32(uint32_t* __restrict__ x, uint64_t n_cap,
-                                                          const uint64_t* __restrict__ d_n, uint32_t a,
-                                                          uint32_t b) {
+                                                          const uint64_t* __restrict__ d_n, Op op) {
   const uint64_t n = device_count(n_cap, d_n);
   const uint64_t base = (uint64_t)blockIdx.x * kAffTile;
   if (base >= n) return;
@@ -36,20 +53,20 @@ __global__ __launch_bounds__(kAffBlock) void k_affine_u32(uint32_t* __restrict__
       const uint64_t e = base + ((uint64_t)k * kAffBlock + threadIdx.x) * 4;
       if (full[k]) {
         u32x4 r;
-        r.x = a * v[k].x + b;
-        r.y = a * v[k].y + b;
-        r.z = a * v[k].z + b;
-        r.w = a * v[k].w + b;
+        r.x = op(v[k].x);
+        r.y = op(v[k].y);
+        r.z = op(v[k].z);
+        r.w = op(v[k].w);
         __builtin_nontemporal_store(r, x4 + e / 4);
       } else {
-        for (uint64_t j = e; j < n && j < e + 4; ++j) x[j] = a * x[j] + b;
+        for (uint64_t j = e; j < n && j < e + 4; ++j) x[j] = op(x[j]);
       }
     }
   } else {
 #pragma unroll 4
     for (int k = 0; k < kAffTile / kAffBlock; ++k) {
       const uint64_t e = base + (uint64_t)k * kAffBlock + threadIdx.x;
-      if (e < n) x[e] = a * x[e] + b;
+      if (e < n) x[e] = op(x[e]);
     }
   }
 }
@@ -92,12 +109,38 @@ int launch_affine(Env& env, uint32_t* x, uint64_t n_cap, const uint64_t* d_n, ui
   const uint64_t grid = (n_cap + kAffTile - 1) / kAffTile;
   if (grid > 0x7FFFFFFFull) return env.fail(kErrArg, "affine_u32: too many elements");
   env.prof_begin("affine_u32");
+  const Affine1 op{a, b};
   if ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)
-    k_affine_u32<true><<<dim3((uint32_t)grid), dim3(kAffBlock), 0, env.stream()>>>(p, n_cap, d_n, a, b);
+    k_affine_u32<true><<<dim3((uint32_t)grid), dim3(kAffBlock), 0, env.stream()>>>(p, n_cap, d_n, op);
   else
-    k_affine_u32<false><<<dim3((uint32_t)grid), dim3(kAffBlock), 0, env.stream()>>>(p, n_cap, d_n, a, b);
+    k_affine_u32<false><<<dim3((uint32_t)grid), dim3(kAffBlock), 0, env.stream()>>>(p, n_cap, d_n, op);
   env.prof_end("affine_u32");
   return check_launch(env, "affine_u32 launch");
+}
+
+int launch_affine_chain(Env& env, uint32_t* x, uint64_t n, const uint32_t* a, const uint32_t* b, uint32_t len) {
+  if (n == 0 || len == 0) return kOk;
+  if (!x || !a || !b) return env.fail(kErrArg, "affine chain: null buffer");
+  const uint64_t grid = (n + kAffTile - 1) / kAffTile;
+  if (grid > 0x7FFFFFFFull) return env.fail(kErrArg, "affine chain: too many elements");
+  const bool vec = (reinterpret_cast<uintptr_t>(x) & 15u) == 0;
+  for (uint32_t s0 = 0; s0 < len; s0 += kChainMax) {  // kChainMax stages per pass over x
+    AffineChain op{};
+    op.len = std::min<uint32_t>(kChainMax, len - s0);
+    for (uint32_t i = 0; i < op.len; ++i) {
+      op.a[i] = a[s0 + i];
+      op.b[i] = b[s0 + i];
+    }
+    env.prof_begin("affine_chain_u32");
+    if (vec)
+      k_affine_u32<true><<<dim3((uint32_t)grid), dim3(kAffBlock), 0, env.stream()>>>(x, n, nullptr, op);
+    else
+      k_affine_u32<false><<<dim3((uint32_t)grid), dim3(kAffBlock), 0, env.stream()>>>(x, n, nullptr, op);
+    env.prof_end("affine_chain_u32");
+    const int rc = check_launch(env, "affine chain launch");
+    if (rc) return rc;
+  }
+  return kOk;
 }
 
 int launch_fill_u64(Env& env, uint64_t* p, uint64_t count, uint64_t value) {

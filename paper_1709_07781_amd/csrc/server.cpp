@@ -16,7 +16,8 @@
 //    device layout, then the kernels run per kind, all on the batch's stream:
 //    the index requests as one batched index build, the scans as one scan of
 //    their concatenation rebased per request, the affine chains as the chain
-//    over their concatenation (an elementwise map needs no per-request work);
+//    over their concatenation in one pass (an elementwise map needs no
+//    per-request work, and one kernel applies every stage);
 //    the outputs go back to one pinned buffer, then an event.
 //  * The completion thread waits for batches in launch order, points each
 //    request at its slices of the batch's pinned outputs (no copy; the buffer
@@ -374,8 +375,8 @@ Batch* Server::launch(std::vector<SrvReq*>& take, uint64_t bytes) {
                             u32(d_ks), u32(d_ws), lens, lens + 1, lens + 2, lens + 3, lens + 4, 0, biggest,
                             u32(d_bad));
     if (!rc && rs) rc = launch_segmented_scan(env, u32(d_vs), u32(d_scan), ns, u32(d_rs), rs);
-    for (size_t i = 0; !rc && nc && i < chain_a.size(); ++i)
-      rc = launch_affine(env, u32(d_vc), nc, nullptr, 0, chain_a[i], chain_b[i]);
+    if (!rc && nc)
+      rc = launch_affine_chain(env, u32(d_vc), nc, chain_a.data(), chain_b.data(), (uint32_t)chain_a.size());
     if (rc) {
       b->rc = rc;
       return b;
