@@ -285,3 +285,22 @@ def test_send_device_value_beyond_bits_fails_alone(sess, base):
     finally:
         srv.close()
         sess.release_ref(rbad)
+
+
+@pytest.mark.parametrize("stages", [1, 16, 17, 40])
+def test_long_chains_in_one_pass(sess, stages):
+    """Chain requests run as one fused pass per 16 stages: chains of 1, 16, 17
+    and 40 stages over a batch of uneven requests equal the oracle's chain."""
+    from paper_1709_07781_amd.session import Server
+    a, b = workloads.chain_params(seed=9, stages=stages)
+    ora = oracle.default()
+    xs = [workloads.u32(900 + i, n) for i, n in enumerate([0, 1, 5, 4096, 4099, 100_003])]
+    srv = Server(sess, streams=2, max_batch=64, chain_a=a, chain_b=b)
+    try:
+        hs = [srv.submit(workloads.KIND_CHAIN, x) for x in xs]
+        for x, h in zip(xs, hs):
+            assert srv.wait(h) == 0
+            np.testing.assert_array_equal(srv.result(h, 0), ora.affine_chain(x, a, b), err_msg=f"n={x.size}")
+            srv.release(h)
+    finally:
+        srv.close()
