@@ -178,6 +178,13 @@ inline int check_launch(Env& env, const char* what) {
 
 constexpr uint32_t kLbAggregate = 1u;  // status flag: tile total only
 constexpr uint32_t kLbInclusive = 2u;  // status flag: prefix including the tile
+// Status slots of the LbPair chains (the WAH encoder's tiles, the fused
+// small-request batch's requests): one status word per 64-byte line, at
+// status[kLbSpread * tile].  Each slot is stored twice (aggregate, then
+// inclusive) while later tiles poll it, and with eight words to a line those
+// stores and polls queue on the same lines: the encoder over 2^26 Zipf pairs
+// took 228 us packed and 215 us spread (4 to 32 words apart: 214-216 us).
+constexpr uint32_t kLbSpread = 8;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -294,21 +301,6 @@ struct LbPair {
   __device__ __forceinline__ static sum_t wave_total(sum_t x) { return {wave_sum(x.a), wave_sum(x.b)}; }
 };
 
-// Decoupled look-back with fallback by one whole wave; status[t] is tile t's
-// status word, read through the policy St (LbEpoch or LbPair).  The wave waits
-// on the nearest tile it has not yet accounted for, j, with one status read per
-// poll (every lane reads the same word, one request): polling a wide window
-// instead makes every waiting wave re-read kilobytes per poll, which competes
-// with the streaming traffic of the whole chip.  Once tile j has published, a
-// window of the 64 tiles j, j-1, ..., j-63 (lane l reads tile j - l) is summed
-// up to the nearest inclusive prefix; an unpublished tile inside the window
-// becomes the next tile waited on.  A tile that has published nothing after
-// spin_limit polls is no longer waited for: the wave computes its total itself
-// with reduce(t) -- every lane calls it, and it returns the tile's total in
-// every lane -- and goes on from the tile before it.  Every wait is therefore
-// bounded whatever order the work-groups run in, so tiles can be numbered by
-// work-group id.  reduce(t) may only read data that no work-group of the
-// launch writes.  Returns the exclusive prefix of `tile` in every lane.
 // One step over a window of status words: lane l holds w, the word of tile
 // j - l.  Adds the aggregates up to the nearest inclusive prefix (returns true,
 // done) or up to the nearest unpublished tile, which becomes the new j; with
@@ -338,8 +330,8 @@ __device__ __forceinline__ bool lb_window_step(uint64_t w, const St& st, int64_t
   return false;
 }
 
-// Decoupled look-back with fallback by one whole wave; status[t] is tile t's
-// status word, read through the policy St (LbEpoch or LbPair).  The wave waits
+// Decoupled look-back with fallback by one whole wave; status[kStride * t] is
+// tile t's status word, read through the policy St (LbEpoch or LbPair).  The wave waits
 // on the nearest tile it has not yet accounted for, j, with one status read per
 // poll (every lane reads the same word, one request): polling a wide window
 // instead makes every waiting wave re-read kilobytes per poll, which competes
@@ -352,21 +344,17 @@ __device__ __forceinline__ bool lb_window_step(uint64_t w, const St& st, int64_t
 // every lane -- and goes on from the tile before it.  Every wait is therefore
 // bounded whatever order the work-groups run in, so tiles can be numbered by
 // work-group id.  reduce(t) may only read data that no work-group of the
-// launch writes.  With `window` the first window (tiles tile-1-lane) was read
-// earlier by the caller, so its latency overlapped other work.  Returns the
-// exclusive prefix of `tile` in every lane.
-template <class St, class Reduce>
+// launch writes.  Returns the exclusive prefix of `tile` in every lane.
+template <uint32_t kStride = 1, class St, class Reduce>
 __device__ __forceinline__ typename St::sum_t lb_lookback_st(const uint64_t* status, uint32_t tile, const St& st,
-                                                             uint32_t spin_limit, Reduce&& reduce,
-                                                             const uint64_t* window = nullptr) {
+                                                             uint32_t spin_limit, Reduce&& reduce) {
   typedef typename St::sum_t S;
   const uint32_t lane = lane_id();
   S excl = St::zero();
   int64_t j = (int64_t)tile - 1;
-  if (window && j >= 0 && lb_window_step(*window, st, j, excl)) return excl;
   uint32_t spins = 0;
   while (j >= 0) {
-    const uint64_t w0 = lb_load(status + j);
+    const uint64_t w0 = lb_load(status + kStride * j);
     const uint32_t f0 = st.flag(w0);
     if (f0 == 0) {
       if (++spins < spin_limit) {
@@ -385,7 +373,7 @@ __device__ __forceinline__ typename St::sum_t lb_lookback_st(const uint64_t* sta
     }
     // Tile j holds an aggregate: sum the window below it.
     const int64_t idx = j - (int64_t)lane;
-    const uint64_t w = (lane && idx >= 0) ? lb_load(status + idx) : w0;
+    const uint64_t w = (lane && idx >= 0) ? lb_load(status + kStride * idx) : w0;
     if (lb_window_step(w, st, j, excl)) break;
   }
   return excl;
@@ -395,8 +383,8 @@ __device__ __forceinline__ typename St::sum_t lb_lookback_st(const uint64_t* sta
 // by a running work-group (tiles handed out in order by a ticket counter, so a
 // tile waited for is held by a work-group that waits only for earlier ones):
 // polls the nearest tile not yet accounted for, then sums windows of 64 as
-// lb_lookback_st does.
-template <class St>
+// lb_lookback_st does (tile t's word at status[kStride * t]).
+template <uint32_t kStride = 1, class St>
 __device__ __forceinline__ typename St::sum_t lb_lookback_ticket(const uint64_t* status, uint32_t tile,
                                                                  const St& st) {
   typedef typename St::sum_t S;
@@ -404,7 +392,7 @@ __device__ __forceinline__ typename St::sum_t lb_lookback_ticket(const uint64_t*
   S excl = St::zero();
   int64_t j = (int64_t)tile - 1;
   while (j >= 0) {
-    const uint64_t w0 = lb_load(status + j);
+    const uint64_t w0 = lb_load(status + kStride * j);
     const uint32_t f0 = st.flag(w0);
     if (f0 == 0) {
       __builtin_amdgcn_s_sleep(2);
@@ -415,7 +403,7 @@ __device__ __forceinline__ typename St::sum_t lb_lookback_ticket(const uint64_t*
       break;
     }
     const int64_t idx = j - (int64_t)lane;
-    const uint64_t w = (lane && idx >= 0) ? lb_load(status + idx) : w0;
+    const uint64_t w = (lane && idx >= 0) ? lb_load(status + kStride * idx) : w0;
     if (lb_window_step(w, st, j, excl)) break;
   }
   return excl;

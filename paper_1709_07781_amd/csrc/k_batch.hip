@@ -314,13 +314,13 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_fused(
         atomicOr(bad_flag, 1u);
         __threadfence();  // the flag is visible before the counts that follow it
       }
-      lb_publish_raw(status + j, lb_pack_pair(W, D, j == 0 ? kLbInclusive : kLbAggregate));
+      lb_publish_raw(status + kLbSpread * j, lb_pack_pair(W, D, j == 0 ? kLbInclusive : kLbAggregate));
     }
     if (tid < 64) {
       LbPairSum p{0u, 0u};
       if (j > 0) {
-        p = lb_lookback_ticket(status, j, LbPair{});
-        if (tid == 0) lb_publish_raw(status + j, lb_pack_pair(p.a + W, p.b + D, kLbInclusive));
+        p = lb_lookback_ticket<kLbSpread>(status, j, LbPair{});
+        if (tid == 0) lb_publish_raw(status + kLbSpread * j, lb_pack_pair(p.a + W, p.b + D, kLbInclusive));
       }
       if (tid == 0) {
         s_pre[0] = p.a;
@@ -603,10 +603,10 @@ int launch_wah_batch(Env& env, const uint32_t* values, uint64_t n, const uint32_
     // every request is small, variant 1: one persistent launch (after clearing
     // its ticket, flag and status words)
     uint32_t* ticket = static_cast<uint32_t*>(env.scratch(8));
-    uint64_t* status = static_cast<uint64_t*>(env.scratch(8ull * nreq));
+    uint64_t* status = static_cast<uint64_t*>(env.scratch(8ull * kLbSpread * nreq));
     if (!ticket || !status) return env.fail(kErrOom, "wah_index_batch: scratch");
     int rc = launch_fill_u32(env, ticket, 2, 0);  // ticket and batch flag
-    if (!rc) rc = launch_fill_u64(env, status, nreq, 0);
+    if (!rc) rc = launch_fill_u64(env, status, (uint64_t)kLbSpread * nreq, 0);
     if (rc) return rc;
     env.prof_begin("batch_small_fused");
     k_small_fused<<<dim3(std::min<uint32_t>(nreq, kSmallGrid)), dim3(kSmallBlock), 0, env.stream()>>>(

@@ -162,8 +162,8 @@ struct Reject {
 // ---------------------------------------------------------------------------------
 // write: literals, fills and lookup-table entries of one tile
 // ---------------------------------------------------------------------------------
-// status[tile]: the tile's (words, values) look-back word, zeroed before the
-// launch.
+// status[kLbSpread * tile]: the tile's (words, values) look-back word, zeroed
+// before the launch.
 template <bool kVec, class KeyT>
 __global__ __launch_bounds__(kEncBlock, 2) void k_wah_write(const KeyT* __restrict__ skeys,
                                                          const uint32_t* __restrict__ srows, uint32_t n_cap,
@@ -296,7 +296,8 @@ __global__ __launch_bounds__(kEncBlock, 2) void k_wah_write(const KeyT* __restri
   // ---- publish the tile's counts at once: successors find them while this
   // tile builds its words --------------------------------------------------------------
   if (tid == 0)
-    lb_publish_raw(status + tile, lb_pack_pair(tile_nw, tile_ns, tile == 0 ? kLbInclusive : kLbAggregate));
+    lb_publish_raw(status + kLbSpread * tile,
+                   lb_pack_pair(tile_nw, tile_ns, tile == 0 ? kLbInclusive : kLbAggregate));
 
   // ---- the last group may run past this work-item's elements (at most 30
   // further elements): collect its bits now.  They are the elements of the next
@@ -354,9 +355,10 @@ __global__ __launch_bounds__(kEncBlock, 2) void k_wah_write(const KeyT* __restri
   if (tid < 64) {
     LbPairSum pre{0u, 0u};
     if (tile > 0) {
-      pre = lb_lookback_st(status, tile, LbPair{}, spin_limit,
-                           [&](uint32_t u) { return wave_tile_count(skeys, srows, n, u, br); });
-      if (tid == 0) lb_publish_raw(status + tile, lb_pack_pair(pre.a + tile_nw, pre.b + tile_ns, kLbInclusive));
+      pre = lb_lookback_st<kLbSpread>(status, tile, LbPair{}, spin_limit,
+                                      [&](uint32_t u) { return wave_tile_count(skeys, srows, n, u, br); });
+      if (tid == 0)
+        lb_publish_raw(status + kLbSpread * tile, lb_pack_pair(pre.a + tile_nw, pre.b + tile_ns, kLbInclusive));
     }
     if (tid == 0) {
       s_pre[0] = pre.a;
@@ -390,10 +392,11 @@ __global__ __launch_bounds__(kEncBlock, 2) void k_wah_write(const KeyT* __restri
   }
 }
 
-// Zeroes the encoder's status words (ntiles of them) before the write kernel.
+// Zeroes the encoder's status words (ntiles of them, kLbSpread apart) before
+// the write kernel.
 __global__ void k_wah_clear(uint64_t* __restrict__ status, uint32_t ntiles) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ntiles) status[i] = 0ull;
+  if (i < ntiles) status[kLbSpread * i] = 0ull;
 }
 
 template <class KeyT>
@@ -411,7 +414,7 @@ int encode_impl(Env& env, const KeyT* skeys, const uint32_t* srows, uint64_t n, 
     return check_launch(env, "wah_empty launch");
   }
   // The (words, values) chain has no epoch: its own status words, zeroed here.
-  uint64_t* status = static_cast<uint64_t*>(env.scratch(8ull * ntiles));
+  uint64_t* status = static_cast<uint64_t*>(env.scratch(8ull * kLbSpread * ntiles));
   if (!status) return env.fail(kErrOom, "wah_encode_sorted: look-back status words");
   int rc;
   k_wah_clear<<<dim3((ntiles + 255) / 256), dim3(256), 0, env.stream()>>>(status, ntiles);

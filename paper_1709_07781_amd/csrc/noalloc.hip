@@ -25,8 +25,9 @@ constexpr uint64_t kStatusBytes = kStatusWords * 8;
 constexpr uint64_t kPairBytes = kMaxN * 4;               // one uint32 array of kMaxN elements
 constexpr uint64_t kTableBytes = (kMaxN / 4096 + 1) * 256 * 4;  // digit table at the smallest sort tile
 constexpr uint64_t kTileBytes = (kMaxN / 4096 + 1) * 8 + 4096;  // orand, encoder tile counts, group totals
+constexpr uint64_t kEncStatusBytes = (kMaxN / 4096 + 1) * 8 * kLbSpread;  // encoder status slots
 constexpr uint64_t kScratchBytes =
-    kStatusBytes + kSortPlanBytes + 4 * kPairBytes + 2 * kTableBytes + 6 * kTileBytes + 16 * kAlign;
+    kStatusBytes + kSortPlanBytes + 4 * kPairBytes + 2 * kTableBytes + 6 * kTileBytes + kEncStatusBytes + 16 * kAlign;
 
 __device__ __align__(256) unsigned char scratch[kScratchBytes];
 

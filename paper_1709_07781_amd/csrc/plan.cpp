@@ -150,7 +150,10 @@ static int plan_build(ka_system* sys, const uint32_t* req_off, uint64_t n, uint3
   // the segmented sort cuts tiles at request boundaries: at most one more per request
   const uint64_t sort_tiles = (n + 8191) / 8192 + nreq, enc_tiles = (n + 4095) / 4096;
   const uint64_t scan_tiles = 2 * ((256 * sort_tiles + 4095) / 4096) + 2;  // scan tiles hold >= 4096 entries
-  const uint64_t arena_bytes = 24 * n1 + 16ull * nreq + 2 * sort_tiles * 2064 + 8 * enc_tiles + (64ull << 10);
+  // look-back status slots (kLbSpread words each): the encoder's tiles, or the
+  // requests of the fused small-request launch
+  const uint64_t arena_bytes = 24 * n1 + (16ull + 8 * kLbSpread) * nreq + 2 * sort_tiles * 2064 +
+                               8ull * kLbSpread * enc_tiles + (64ull << 10);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     const uint64_t o = off;
