@@ -15,7 +15,7 @@ namespace ka {
 
 // Look-back state of one stream.  A look-back kernel numbers its tiles by
 // work-group id, and every wait in its look-back is bounded (see
-// lb_lookback), so it needs no co-residency guarantee, no cooperative launch
+// lb_lookback_st), so it needs no co-residency guarantee, no cooperative launch
 // and no ticket counter.  Status words are tagged with a per-launch epoch, so
 // stale words from earlier launches read as "not yet published" and nothing
 // has to be cleared between launches.
@@ -178,12 +178,11 @@ inline int check_launch(Env& env, const char* what) {
 
 constexpr uint32_t kLbAggregate = 1u;  // status flag: tile total only
 constexpr uint32_t kLbInclusive = 2u;  // status flag: prefix including the tile
-// Status slots of the LbPair chains (the WAH encoder's tiles, the fused
-// small-request batch's requests): one status word per 64-byte line, at
-// status[kLbSpread * tile].  Each slot is stored twice (aggregate, then
+// Status slots of every look-back chain: one status word per 64-byte line,
+// at status[kLbSpread * tile].  Each slot is stored twice (aggregate, then
 // inclusive) while later tiles poll it, and with eight words to a line those
-// stores and polls queue on the same lines: the encoder over 2^26 Zipf pairs
-// took 228 us packed and 215 us spread (4 to 32 words apart: 214-216 us).
+// stores and polls queue on the same lines: the WAH encoder over 2^26 Zipf
+// pairs took 228 us packed and 215 us spread (4 to 32 words apart: 214-216 us).
 constexpr uint32_t kLbSpread = 8;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -409,11 +408,6 @@ __device__ __forceinline__ typename St::sum_t lb_lookback_ticket(const uint64_t*
   return excl;
 }
 
-template <class Reduce>
-__device__ __forceinline__ uint32_t lb_lookback(const uint64_t* status, uint32_t tile, uint32_t epoch,
-                                                uint32_t spin_limit, Reduce&& reduce) {
-  return lb_lookback_st(status, tile, LbEpoch{epoch}, spin_limit, reduce);
-}
 
 // Reads the element count: the device-resident one when given.
 __device__ __forceinline__ uint64_t device_count(uint64_t n_cap, const uint64_t* d_n) {

@@ -96,18 +96,20 @@ __device__ __forceinline__ void tile_scan(const uint32_t (&s)[R], uint32_t (&pre
 
 // Wave 0 publishes the tile total, looks back, publishes the inclusive prefix
 // and leaves the tile's exclusive prefix in *s_prefix; reduce(t) gives a
-// silent predecessor's total (see lb_lookback).
+// silent predecessor's total (see lb_lookback_st).  Tile t's status word is
+// lb.status[kLbSpread * t].
 template <class Reduce>
 __device__ __forceinline__ void tile_lookback(const LbArgs& lb, uint32_t tile, uint32_t tile_total,
                                               uint32_t* s_prefix, Reduce&& reduce) {
   if (threadIdx.x < 64) {
     uint32_t prefix = 0;
+    uint64_t* slot = lb.status + (uint64_t)kLbSpread * tile;
     if (tile == 0) {
-      if (threadIdx.x == 0) lb_publish(lb.status, tile_total, lb.epoch, kLbInclusive);
+      if (threadIdx.x == 0) lb_publish(slot, tile_total, lb.epoch, kLbInclusive);
     } else {
-      if (threadIdx.x == 0) lb_publish(lb.status + tile, tile_total, lb.epoch, kLbAggregate);
-      prefix = lb_lookback(lb.status, tile, lb.epoch, lb.spin_limit, reduce);
-      if (threadIdx.x == 0) lb_publish(lb.status + tile, prefix + tile_total, lb.epoch, kLbInclusive);
+      if (threadIdx.x == 0) lb_publish(slot, tile_total, lb.epoch, kLbAggregate);
+      prefix = lb_lookback_st<kLbSpread>(lb.status, tile, LbEpoch{lb.epoch}, lb.spin_limit, reduce);
+      if (threadIdx.x == 0) lb_publish(slot, prefix + tile_total, lb.epoch, kLbInclusive);
     }
     if (threadIdx.x == 0) *s_prefix = prefix;
   }
@@ -221,7 +223,8 @@ template <int R>
 int scan_launch(Env& env, const uint32_t* in, uint32_t* out, uint64_t n_cap, const uint64_t* d_n) {
   const uint32_t grid = (uint32_t)((n_cap + kTileElems<R> - 1) / kTileElems<R>);
   LbArgs lb;
-  if (!env.lookback(grid, &lb)) return env.fail(kErrOom, "exclusive_scan_u32: look-back state");
+  if (!env.lookback((uint64_t)kLbSpread * grid, &lb))
+    return env.fail(kErrOom, "exclusive_scan_u32: look-back state");
   const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
   const dim3 g(grid), b(kScanBlock);
   env.prof_begin("exclusive_scan_u32");
@@ -254,7 +257,8 @@ int launch_compact_nonzero(Env& env, const uint32_t* in, uint32_t* out, uint64_t
   if (ranges_overlap(in, out, n_cap)) return env.fail(kErrArg, "compact_nonzero_u32: in and out overlap");
   const uint32_t grid = (uint32_t)((n_cap + kTileElems<kCompactRounds> - 1) / kTileElems<kCompactRounds>);
   LbArgs lb;
-  if (!env.lookback(grid, &lb)) return env.fail(kErrOom, "compact_nonzero_u32: look-back state");
+  if (!env.lookback((uint64_t)kLbSpread * grid, &lb))
+    return env.fail(kErrOom, "compact_nonzero_u32: look-back state");
   const bool vec = (reinterpret_cast<uintptr_t>(in) & 15u) == 0;
   env.prof_begin("compact_nonzero_u32");
   if (vec)

@@ -20,7 +20,7 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr uint64_t kMaxN = KA_NOALLOC_MAX_N;
-constexpr uint64_t kStatusWords = 8192;                  // look-back status words (all table scans of a call)
+constexpr uint64_t kStatusWords = 8192;  // look-back status words of the table scans (kLbSpread per tile)
 constexpr uint64_t kStatusBytes = kStatusWords * 8;
 constexpr uint64_t kPairBytes = kMaxN * 4;               // one uint32 array of kMaxN elements
 constexpr uint64_t kTableBytes = (kMaxN / 4096 + 1) * 256 * 4;  // digit table at the smallest sort tile

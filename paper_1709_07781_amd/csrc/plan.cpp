@@ -163,7 +163,8 @@ static int plan_build(ka_system* sys, const uint32_t* req_off, uint64_t n, uint3
   const uint64_t o_in = take(4 * n1), o_req = take(4 * (nreq + 1ull)), o_keys = take(4 * n1);
   const uint64_t o_offs = take(4 * (n + nreq)), o_words = take(8 * n1), o_ks = take(4 * (nreq + 1ull));
   const uint64_t o_ws = take(4 * (nreq + 1ull)), o_lens = take(6 * 8);
-  const uint64_t o_plan = take(kSortPlanBytes), o_status = take(8 * scan_tiles), o_arena = take(arena_bytes);
+  const uint64_t o_plan = take(kSortPlanBytes), o_status = take(8ull * kLbSpread * scan_tiles);
+  const uint64_t o_arena = take(arena_bytes);
   if (hipMalloc(&p->mem, off) != hipSuccess) {
     (void)hipGetLastError();
     plan_free(p);
@@ -182,7 +183,7 @@ static int plan_build(ka_system* sys, const uint32_t* req_off, uint64_t n, uint3
   PlanEnv& e = p->env;
   e.lb.plan = m + o_plan;
   e.lb.status = reinterpret_cast<uint64_t*>(m + o_status);
-  e.lb.status_words = scan_tiles;
+  e.lb.status_words = (uint64_t)kLbSpread * scan_tiles;
   e.mem = m + o_arena;
   e.cap = arena_bytes;
   if (hipStreamCreateWithFlags(&p->s, hipStreamNonBlocking) != hipSuccess) {
