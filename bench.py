@@ -763,6 +763,10 @@ def bench_chain(args) -> int:
                "host_round_trip_latency_us": lat_us(host_chain, sync=False),
                "roofline_GBs_refs": 64.0 * m / 1e9 / 1e-3}
         row["roofline_GBs_refs"] = 64.0 * m / (row["refs_device_ms"] * 1e-3) / 1e9
+        # The chain works in place on 4m bytes: at every size here that fits the
+        # 256 MB Infinity Cache, so the rate above is not an HBM fraction.
+        row["working_set_bytes"] = 4 * m
+        row["cache_resident"] = 4 * m <= (256 << 20)
         row["refs_overhead_us"] = row["refs_latency_us"] - row["raw_latency_us"]
         row["refs_overhead_pct"] = 100.0 * row["refs_overhead_us"] / row["raw_latency_us"]
         log(f"[bench] chain m=2^{lg}: refs {row['refs_latency_us']:.1f} us, raw {row['raw_latency_us']:.1f} us, "
@@ -876,25 +880,30 @@ def main() -> int:
     stream = torch.cuda.current_stream()
 
     def timed_region(profiled: bool):
-        """K steps between two events on the library's stream; with profiled,
-        every launch is also bracketed by the library's own events."""
+        """K steps between two events on the library's stream, and an event
+        after every step (the per-step times, for their median); with
+        profiled, every launch is also bracketed by the library's own
+        events."""
         ka.check(ka.lib.ka_profile_enable(sess.sys, 1 if profiled else 0))
         sess.profile_reset()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         ev0.record(stream)
         last_ = None
         for k in range(args.steps):
             last_ = step(keep=(k == args.steps - 1))
+            evs[k].record(stream)
             if k == args.steps - 1 or (k + 1) % 10 == 0:
                 log(f"[bench] {'profiled ' if profiled else ''}step {k + 1}/{args.steps}")
         ev1.record(stream)
         torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1), time.perf_counter() - w0, last_
+        per_step = [a.elapsed_time(b) for a, b in zip([ev0] + evs[:-1], evs)]
+        return ev0.elapsed_time(ev1), time.perf_counter() - w0, last_, per_step
 
     # the reported value: no per-launch events in the timed region
-    dev_ms, wall, last = timed_region(False)
+    dev_ms, wall, last, per_step_ms = timed_region(False)
     ms_per_step = dev_ms / args.steps
     for r in last:
         sess.release_ref(r)
@@ -911,7 +920,7 @@ def main() -> int:
     composed_ms = ev0.elapsed_time(ev1) / args.steps
     log(f"[bench] composed stage actors: {composed_ms:.4f} ms per request")
     # per-kernel device times for the roofline: a second region with the library's events
-    prof_ms, _, last = timed_region(True)
+    prof_ms, _, last, _ = timed_region(True)
     prof = {k: sess.profile(k) for k in KERNELS}
     D = sess.length(last[0])
     W = sess.length(last[2])
@@ -1002,7 +1011,9 @@ def main() -> int:
         "pipeline": {"algorithmic_bytes": pipe_bytes, "moved_bytes": moved_bytes,
                      "bytes_formula": "16*P*n + 8*n + 4*W + 8*D + 4", "ms": ms_per_step, "achieved_GBs": pipe_gbs,
                      "moved_GBs": moved_bytes / (ms_per_step * 1e-3) / 1e9,
-                     "frac": pipe_gbs / HBM_PEAK_GBS, "profiled_ms_per_step": prof_ms / args.steps,
+                     "frac": pipe_gbs / HBM_PEAK_GBS, "step_ms_median": float(np.median(per_step_ms)),
+                     "step_ms_min": min(per_step_ms), "step_ms_max": max(per_step_ms),
+                     "profiled_ms_per_step": prof_ms / args.steps,
                      "kernel_ms_per_step": {k: prof[k][1] / args.steps for k in prof},
                      "launches_per_step": {k: prof[k][0] / args.steps for k in prof},
                      "wall_s": wall},
