@@ -169,12 +169,17 @@ def plain_request_leg(sess, args) -> dict:
     hint = ka.KA_WAH_VALUE_BITS(10)  # values below 1024
     reps = 50
     e2e = []
+    first = None
     for k in range(reps + 3):
         t0 = time.perf_counter()
         res = ka.ka_wah_result()
         ka.check(ka.lib.ka_wah_index(sess.sys, v.ctypes.data, v.size, hint, ctypes.byref(res)))
         dt = time.perf_counter() - t0
         D, W = res.D, res.W
+        if first is None:
+            first = (np.ctypeslib.as_array(res.keys, shape=(max(D, 1),))[:D].copy(),
+                     np.ctypeslib.as_array(res.offsets, shape=(D + 1,)).copy(),
+                     np.ctypeslib.as_array(res.words, shape=(max(W, 1),))[:W].copy())
         ka.check(ka.lib.ka_wah_result_free(ctypes.byref(res)))
         if k >= 3:
             e2e.append(dt)
@@ -191,14 +196,36 @@ def plain_request_leg(sess, args) -> dict:
         ka.check(ka.lib.ka_wah_result_free(ctypes.byref(res)))
         if k >= 3:
             dev.append(dt)
+    # The same request through a batch plan of one request: its launches
+    # recorded once into a HIP graph, then per request one upload, one replay
+    # and one copy of the results back (host in, host out).
+    from paper_1709_07781_amd.session import BatchPlan
+    plan = BatchPlan(sess, [0, v.size], 10)
+    graph = []
+    try:
+        for k in range(reps + 3):
+            t0 = time.perf_counter()
+            plan.run(v)
+            (got,) = plan.result()
+            dt = time.perf_counter() - t0
+            if k == 0 and not all(np.array_equal(g, e) for g, e in zip(got, first)):
+                raise RuntimeError("plain request: the batch plan's index differs from ka_wah_index's")
+            if k >= 3:
+                graph.append(dt)
+    finally:
+        plan.close()
     e2e_ms = float(np.median(e2e)) * 1e3
     dev_ms = float(np.median(dev)) * 1e3
-    log(f"[bench] plain 2^16 request: {e2e_ms:.3f} ms end to end (host in/out), {dev_ms:.3f} ms from HBM")
+    graph_ms = float(np.median(graph)) * 1e3
+    log(f"[bench] plain 2^16 request: {e2e_ms:.3f} ms end to end (host in/out), {dev_ms:.3f} ms from HBM, "
+        f"{graph_ms:.3f} ms end to end through a graph-replayed plan")
     return {"workload": "2^16 values uniform below 1024, one ka_wah_index call (10-bit value hint)", "n": int(v.size),
             "D": int(D),
             "W": int(W), "e2e_ms_median": e2e_ms, "e2e_elements_per_s": v.size / (e2e_ms * 1e-3),
             "device_resident_ms_median": dev_ms, "device_resident_elements_per_s": v.size / (dev_ms * 1e-3),
-            "requests": reps, "how": "wall time per call on the host (waits for the result), median"}
+            "plan_graph_e2e_ms_median": graph_ms, "plan_graph_e2e_elements_per_s": v.size / (graph_ms * 1e-3),
+            "requests": reps, "how": "wall time per call on the host (waits for the result), median; the plan "
+                                     "form: a ka_batch_plan of this one request (host in, host out)"}
 
 
 def pcie_inclusive_leg(sess, v, args) -> dict:
