@@ -220,11 +220,6 @@ __device__ __forceinline__ uint32_t wave_read_last(uint32_t x) {
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t x) { return wave_read_last(wave_incl_scan(x)); }
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  const uint32_t l = lane_id();
-  return l ? (~0ull >> (64 - l)) : 0ull;
-}
-
 // Exclusive block-wide prefix sum of one value per thread.  s_wave needs
 // BLOCK/64 words; the caller separates reuses of s_wave with a barrier.
 template <int BLOCK>
