@@ -14,10 +14,10 @@
 //    first key with that digit.
 //  * k_radix_scatter (one work-group per tile) ranks its keys by digit inside
 //    each wave -- the lanes holding the same digit are found by OR-ing each
-//    lane's bit into a per-digit mask in LDS (8-bit digits; digit 0 by one
-//    ballot) or with one ballot per digit bit (narrower digits), and a key's
-//    rank is the number of such lanes below it plus the wave's earlier count
-//    of that digit, so equal keys keep their order -- reorders the tile by
+//    lane's bit into a per-digit mask in LDS (8-bit digits; digits 0 and 1 by a
+//    ballot each) or with one ballot per digit bit (narrower digits), and a
+//    key's rank is the number of such lanes below it plus the wave's earlier
+//    count of that digit, so equal keys keep their order -- reorders the tile by
 //    digit in LDS and writes each digit's run to its offset from the table,
 //    consecutive work-items writing consecutive addresses.
 // Tiles are taken in an XCD-aware order (see xcd_tile).
@@ -426,16 +426,17 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
   __syncthreads();
 
   // ---- rank inside the wave: peers = lanes with the same digit ----------------
-  // 8-bit digits: digit 0, the most frequent one on small values, by one
-  // ballot; every other digit by its mask: the lanes holding it OR their bits
-  // into it, read it back and clear it (three LDS operations of the one wave,
-  // executed in order; OR commutes, so the mask is exact whatever order the
-  // lanes are served in).  That costs fewer instructions than a ballot per
-  // digit bit (≈30 per key), and the scatter is bound by instruction issue:
-  // 347 -> 334 us per 2^26 pair sort over 16-bit Zipf keys, the same on
-  // uniform ones.  Narrower digits take the ballots (3 rounds for 6 bits),
-  // which are cheaper there: the batched build's 6-bit passes ran 1.3% slower
-  // with the masks.
+  // 8-bit digits: digits 0 and 1, the most frequent ones on small values, by
+  // one ballot each; every other digit by its mask: the lanes holding it OR
+  // their bits into it, read it back and clear it (three LDS operations of the
+  // one wave, executed in order; OR commutes, so the mask is exact whatever
+  // order the lanes are served in).  That costs fewer instructions than a
+  // ballot per digit bit (≈30 per key), and the scatter is bound by
+  // instruction issue: 347 -> 330 us per 2^26 pair sort over 16-bit Zipf keys,
+  // the same on uniform ones (ballots for digit 0 alone: 334 us; for 0..3:
+  // 340 us).  Narrower digits take the ballots (3 rounds for 6 bits), which are
+  // cheaper there: the batched build's 6-bit passes ran 1.3% slower with the
+  // masks.
   const uint64_t mybit = 1ull << lane;
   uint32_t rank[kItems];
 #pragma unroll
@@ -445,8 +446,10 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
     uint32_t r = 0;
     uint64_t peers;
     if (kMaskRank) {
-      peers = __builtin_amdgcn_ballot_w64(valid && d == 0u);
-      if (valid && d != 0u) {
+      const uint64_t b0 = __builtin_amdgcn_ballot_w64(valid && d == 0u);
+      const uint64_t b1 = __builtin_amdgcn_ballot_w64(valid && d == 1u);
+      peers = d == 0u ? b0 : b1;
+      if (valid && d > 1u) {
         __hip_atomic_fetch_or(&dmask[d], mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         peers = __hip_atomic_load(&dmask[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         __hip_atomic_store(&dmask[d], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
