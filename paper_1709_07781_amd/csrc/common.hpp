@@ -189,6 +189,9 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // Native 4 x uint32 vector: one 16-byte global access.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// Four words at word alignment: global loads and stores of 16 bytes need only
+// 4-byte alignment on this target.
+typedef uint32_t u32x4w __attribute__((ext_vector_type(4), aligned(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // Four consecutive keys p[4q .. 4q+3] from one 16-byte (uint32 keys) or 8-byte

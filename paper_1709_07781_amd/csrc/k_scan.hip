@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kScanBlock) void k_compact_nonzero_u32(const uint32
   constexpr int R = kCompactRounds, kTile = kTileElems<R>;
   __shared__ uint32_t s_prefix;
   __shared__ uint32_t s_wave[R][kWaves];
-  __shared__ uint32_t s_out[kTile];
+  __shared__ __align__(16) uint32_t s_out[kTile];
   const uint64_t n = device_count(n_cap, d_n);
   const uint64_t ntiles = (n + kTile - 1) / kTile;
   if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) *d_out_len = 0;  // empty input
@@ -210,7 +210,11 @@ __global__ __launch_bounds__(kScanBlock) void k_compact_nonzero_u32(const uint32
     return wave_tile_total<R, kVec>(in, u, n, [](uint32_t x) { return x != 0 ? 1u : 0u; });
   });
   const uint64_t dst = s_prefix;
-  for (uint32_t i = threadIdx.x; i < total; i += kScanBlock) out[dst + i] = s_out[i];
+  // four kept words per work-item and step (16-byte stores at word alignment)
+  const uint32_t nv = total / 4;
+  for (uint32_t v = threadIdx.x; v < nv; v += kScanBlock)
+    *reinterpret_cast<u32x4w*>(out + dst + 4 * v) = *reinterpret_cast<const u32x4*>(s_out + 4 * v);
+  if (threadIdx.x < total - 4 * nv) out[dst + 4 * nv + threadIdx.x] = s_out[4 * nv + threadIdx.x];
   if (tile == ntiles - 1 && threadIdx.x == 0) *d_out_len = dst + total;
 }
 
