@@ -172,16 +172,31 @@ __device__ __forceinline__ void upsweep_tile(const SK* __restrict__ keys, uint32
                                              uint32_t tile, uint32_t* __restrict__ orand,
                                              uint32_t mask = kRadix - 1) {
   constexpr int kUpVecs = kTile / 4 / kUpBlock;  // 4-key loads per work-item
-  constexpr uintptr_t kAlign = 4 * sizeof(SK) - 1;
+  constexpr uintptr_t kAlign = 15;  // 16-byte loads
   __shared__ uint32_t s_hist[kUpWaves][kRadix];
   __shared__ uint32_t s_or[kUpWaves], s_and[kUpWaves];
   const uint32_t tid = threadIdx.x, w = tid / 64;
 
-  // Key 4 (j * kUpBlock + tid) + c of the tile in k[j][c].
+  // Key 4 (j * kUpBlock + tid) + c of the tile in k[j][c] (uint16 keys of a full
+  // tile: key 8 (j/2 * kUpBlock + tid) + 4 (j mod 2) + c).
   uint32_t k[kUpVecs][4];
   if (len == (uint32_t)kTile && (reinterpret_cast<uintptr_t>(keys + base) & kAlign) == 0) {
+    if (sizeof(SK) == 2) {
+      // uint16 keys: 8 per 16-byte load (which keys a work-item holds does not
+      // change the counts); half the loads of 8-byte ones: 40.5 -> 35.9 us for
+      // the second pass over 2^26 keys
+      static_assert(kUpVecs % 2 == 0, "pairs of 4-key groups");
 #pragma unroll
-    for (int j = 0; j < kUpVecs; ++j) load_key4(keys + base, (uint64_t)j * kUpBlock + tid, k[j]);
+      for (int j = 0; j < kUpVecs / 2; ++j) {
+        const u32x4 a = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + base) + j * kUpBlock + tid);
+        k[2 * j][0] = a.x & 0xFFFFu, k[2 * j][1] = a.x >> 16, k[2 * j][2] = a.y & 0xFFFFu, k[2 * j][3] = a.y >> 16;
+        k[2 * j + 1][0] = a.z & 0xFFFFu, k[2 * j + 1][1] = a.z >> 16;
+        k[2 * j + 1][2] = a.w & 0xFFFFu, k[2 * j + 1][3] = a.w >> 16;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kUpVecs; ++j) load_key4(keys + base, (uint64_t)j * kUpBlock + tid, k[j]);
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < kUpVecs; ++j)
