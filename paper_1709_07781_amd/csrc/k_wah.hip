@@ -33,15 +33,18 @@
 namespace ka {
 namespace {
 
-// 512 work-items x 16 elements: a tile of 8192 pairs.  The look-back's
-// latency (a few device-coherent round trips, about 0.75 us each) is paid
-// once per tile while the whole work-group waits; 8192-element tiles halve
-// how often it is paid for the same occupancy in waves (two work-groups of
-// 8 waves per CU, bound by LDS): measured 244 -> 228 us on 2^26 Zipf pairs;
-// 16384-element tiles (one work-group per CU) took 308 us.
-constexpr int kEncBlock = 512;
+// 1024 work-items x 8 elements: a tile of 8192 pairs, two work-groups of 16
+// waves per CU (bound by LDS; 63 VGPRs).  The look-back's latency (a few
+// device-coherent round trips, about 0.75 us each) is paid once per tile while
+// the tile's work-group waits, and the LDS sweeps stall on bank conflicts:
+// twice the waves of 512 x 16 hide both better, 206 -> 181 us on 2^26 Zipf
+// pairs and 324 -> 225 us on uniform 16-bit ones (the batched build of 4096
+// requests: +0.8%).  Tiles of 4096 pairs paid the look-back twice as often
+// (244 against 228 us at 512 x 16); 16384-pair tiles (one work-group per CU)
+// took 308 us.
+constexpr int kEncBlock = 1024;
 #ifndef KA_ENC_ITEMS
-#define KA_ENC_ITEMS 16
+#define KA_ENC_ITEMS 8
 #endif
 constexpr int kEncItems = KA_ENC_ITEMS;
 constexpr int kEncTile = kEncBlock * kEncItems;  // 8192 pairs
@@ -54,12 +57,12 @@ constexpr uint32_t kFill = 0x80000000u;
 // Padded LDS index: four spare words after every 64 elements.  Groups of 4
 // elements stay 16-byte aligned, so the tile is staged with conflict-free
 // 16-byte writes (work-item t writes elements 4t..4t+3); a work-item reads its
-// 16 consecutive elements with 16-byte reads, and the 16 work-items served
-// together (starting 64 bytes apart, plus 16 after every fourth) cover all 64
+// 8 consecutive elements with two 16-byte reads, and the 16 work-items served
+// together (starting 32 bytes apart, plus 16 after every eighth) cover all 64
 // banks once.
 __device__ __forceinline__ uint32_t pidx(uint32_t i) { return i + 4 * (i >> 6); }
 constexpr int kStagePadded = kStage + 4 * (kStage / 64) + 4;
-static_assert(kEncItems == 16, "one padded run of 16 elements per work-item");
+static_assert(kEncItems == 8, "one padded run of 8 elements per work-item");
 static_assert(2 * kEncTile <= 2 * kStagePadded, "word staging fits over the input staging");
 
 // Words and values emitted by an element with key k and row r whose
@@ -165,7 +168,7 @@ struct Reject {
 // status[kLbSpread * tile]: the tile's (words, values) look-back word, zeroed
 // before the launch.
 template <bool kVec, class KeyT>
-__global__ __launch_bounds__(kEncBlock, 2) void k_wah_write(const KeyT* __restrict__ skeys,
+__global__ __launch_bounds__(kEncBlock, 8) void k_wah_write(const KeyT* __restrict__ skeys,
                                                          const uint32_t* __restrict__ srows, uint32_t n_cap,
                                                          const uint64_t* __restrict__ d_n,
                                                          uint64_t* __restrict__ status, uint32_t spin_limit,
@@ -302,8 +305,8 @@ __global__ __launch_bounds__(kEncBlock, 2) void k_wah_write(const KeyT* __restri
   // ---- the last group may run past this work-item's elements (at most 30
   // further elements): collect its bits now.  They are the elements of the next
   // work-items before their first group head ("lead"): a group holds at most 31
-  // elements, so it reaches at most two work-items further, and the second
-  // one has a head.  Shuffles within the wave; the wave's last two lanes read
+  // elements, so it reaches at most four work-items further, and the fourth
+  // one has a head.  Shuffles within the wave; the wave's last four lanes read
   // ahead in LDS (the next wave's elements, or the look-ahead).  Lanes with
   // invalid elements have no head and no lead bits, which ends a group at the
   // tile's (and the input's) end.
@@ -313,11 +316,14 @@ __global__ __launch_bounds__(kEncBlock, 2) void k_wah_write(const KeyT* __restri
   for (int i = 0; i < kEncItems; ++i)
     if ((uint32_t)i < lead_n) lead |= (1u << bit_of[i]) & ~kFill;  // bit 31 marks invalid elements
   const uint32_t lead1 = (uint32_t)__shfl_down((int)lead, 1), lead2 = (uint32_t)__shfl_down((int)lead, 2);
-  const uint32_t nohead1 = (uint32_t)__shfl_down((int)(heads == 0u), 1);
+  const uint32_t lead3 = (uint32_t)__shfl_down((int)lead, 3), lead4 = (uint32_t)__shfl_down((int)lead, 4);
+  const uint32_t nh = heads == 0u ? 1u : 0u;
+  const uint32_t nohead1 = (uint32_t)__shfl_down((int)nh, 1), nohead2 = (uint32_t)__shfl_down((int)nh, 2);
+  const uint32_t nohead3 = (uint32_t)__shfl_down((int)nh, 3);
   uint32_t tail = 0;
   if (e0 + kEncItems <= tile_n) {
-    if (lane < 62) {
-      tail = lead1 | (nohead1 ? lead2 : 0u);
+    if (lane < 60) {
+      tail = lead1 | (nohead1 ? (lead2 | (nohead2 ? (lead3 | (nohead3 ? lead4 : 0u)) : 0u)) : 0u);
     } else {
       const uint32_t kl = key[kEncItems - 1], cl = grp_of[kEncItems - 1];
       for (uint32_t j = e0 + kEncItems; j < avail; ++j) {
