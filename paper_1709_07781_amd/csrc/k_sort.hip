@@ -418,8 +418,10 @@ __device__ __forceinline__ void scatter_load(const IO& io, uint32_t base, uint32
 // Ranks, reorders and writes one tile whose keys and rows are in registers
 // (their loads may still be in flight); dstart = the table entry of digit
 // threadIdx.x for this tile.  Starts and ends with a barrier.  With kCheck a
-// key at or above 2^check_shift sets *reject to 1.
-template <int kBlock, int kItems, bool kCheck = false, bool kTag = false, int kBits = kRadixBits, class IO>
+// key at or above 2^check_shift sets *reject to 1.  With kFull the tile is
+// full (tile_n = kBlock * kItems) and no element is checked against tile_n.
+template <int kBlock, int kItems, bool kCheck = false, bool kTag = false, int kBits = kRadixBits, bool kFull = false,
+          class IO>
 __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, const IO& io, uint32_t shift,
                                              uint32_t tile_n, uint32_t dstart, const uint32_t (&key)[kItems],
                                              const uint32_t (&row)[kItems], uint32_t check_shift = 32,
@@ -455,7 +457,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
   uint32_t rank[kItems];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
-    const bool valid = wbase + i * 64 + lane < tile_n;
+    const bool valid = (kFull || wbase + i * 64 + lane < tile_n);
     const uint32_t d = (key[i] >> shift) & kMask;
     uint32_t r = 0;
     uint64_t peers;
@@ -490,7 +492,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
     uint32_t over = 0;
 #pragma unroll
     for (int i = 0; i < kItems; ++i)
-      over |= (wbase + i * 64 + lane < tile_n) ? key[i] >> check_shift : 0u;
+      over |= ((kFull || wbase + i * 64 + lane < tile_n)) ? key[i] >> check_shift : 0u;
     if (__ballot(over != 0u) && lane == 0) *reject = 1u;
   }
   __syncthreads();
@@ -520,7 +522,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
   // ---- reorder the tile by digit in LDS ---------------------------------------
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
-    if (wbase + i * 64 + lane < tile_n) {
+    if ((kFull || wbase + i * 64 + lane < tile_n)) {
       const uint32_t d = (key[i] >> shift) & kMask;
       const uint32_t pos = L.wcnt[w][d] + rank[i];
       L.kr[pos] = make_uint2(key[i], row[i]);
@@ -532,7 +534,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<kBlock, kItems>& L, cons
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     const uint32_t p = i * kBlock + tid;
-    if (p < tile_n) {
+    if (kFull || p < tile_n) {
       const uint2 v = L.kr[p];
       const uint32_t k = v.x;
       const uint32_t g = L.dbase[(k >> shift) & kMask] + p;
@@ -562,7 +564,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(PassBuffers buf, const
   const uint32_t dstart = threadIdx.x < kRadix ? table[(uint64_t)threadIdx.x * ntiles + tile] : 0u;
   uint32_t key[kItems], row[kItems];
   scatter_load<kBlock, kItems>(io, base, tile_n, key, row);
-  scatter_tile<kBlock, kItems>(L, io, pass * kRadixBits, tile_n, dstart, key, row);
+  if (tile_n == (uint32_t)kTile)  // uniform: a full tile checks no element against its length
+    scatter_tile<kBlock, kItems, false, false, kRadixBits, true>(L, io, pass * kRadixBits, tile_n, dstart, key, row);
+  else
+    scatter_tile<kBlock, kItems>(L, io, pass * kRadixBits, tile_n, dstart, key, row);
 }
 
 // Scatter of a fixed pass (no plan): keys uint32 or uint16 on either side.
@@ -582,7 +587,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter_fixed(PassIoT<SK, DK> 
   const uint32_t dstart = threadIdx.x < kRadix ? table[(uint64_t)threadIdx.x * ntiles + tile] : 0u;
   uint32_t key[kItems], row[kItems];
   scatter_load<kBlock, kItems>(io, base, tile_n, key, row);
-  scatter_tile<kBlock, kItems, kCheck, false, kBits>(L, io, shift, tile_n, dstart, key, row, check_shift, reject);
+  if (tile_n == (uint32_t)kTile)  // uniform: a full tile checks no element against its length
+    scatter_tile<kBlock, kItems, kCheck, false, kBits, true>(L, io, shift, tile_n, dstart, key, row, check_shift,
+                                                             reject);
+  else
+    scatter_tile<kBlock, kItems, kCheck, false, kBits, false>(L, io, shift, tile_n, dstart, key, row, check_shift,
+                                                              reject);
 }
 
 }  // namespace
@@ -741,8 +751,11 @@ __global__ __launch_bounds__(kBlock) void k_seg_scatter(PassIoT<SK, DK> io, cons
   }
   uint32_t key[kItems], row[kItems];
   scatter_load<kBlock, kItems>(io, s.base, s.len, key, row);
-  scatter_tile<kBlock, kItems, kCheck, kTag, kBits>(L, io, shift, s.len, dstart, key, row, value_bits,
-                                                    req_bad ? req_bad + s.j : bad);
+  uint32_t* const flag = req_bad ? req_bad + s.j : bad;
+  if (s.len == (uint32_t)kTile)  // uniform: a full tile checks no element against its length
+    scatter_tile<kBlock, kItems, kCheck, kTag, kBits, true>(L, io, shift, s.len, dstart, key, row, value_bits, flag);
+  else
+    scatter_tile<kBlock, kItems, kCheck, kTag, kBits, false>(L, io, shift, s.len, dstart, key, row, value_bits, flag);
 }
 
 // Digits of a fixed-pass sort of values below 2^value_bits (value_bits 1..16):

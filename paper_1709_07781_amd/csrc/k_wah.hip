@@ -273,12 +273,13 @@ __global__ __launch_bounds__(kEncBlock, 8) void k_wah_write(const KeyT* __restri
 
   // ---- group and value heads, words and values emitted ------------------------------
   uint32_t heads = 0, segs = 0, gaps = 0;  // bit i: element i starts a group / a value / has a fill
+  const bool first_of_input = base + e0 == 0u;  // this work-item's element 0 is the input's first
 #pragma unroll
   for (int i = 0; i < kEncItems; ++i) {
     const uint32_t c = grp_of[i];
     const uint32_t kp = i ? key[i - 1] : kprev;
     const uint32_t cp = i ? grp_of[i - 1] : cprev;
-    const bool seg = key[i] != kp || (base + e0 + i) == 0;
+    const bool seg = key[i] != kp || (i == 0 && first_of_input);
     const bool grp = seg || c != cp;
     const bool gap = grp && (seg ? c != 0u : c != cp + 1u);
     heads |= (uint32_t)grp << i;
