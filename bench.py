@@ -906,11 +906,22 @@ def main() -> int:
 
     stream = torch.cuda.current_stream()
 
-    def timed_region(profiled: bool):
-        """K steps between two events on the library's stream, and an event
-        after every step (the per-step times, for their median); with
-        profiled, every launch is also bracketed by the library's own
-        events."""
+    def finish(t, keep=False):
+        outs = sess.receive(t, 3)
+        sess.release_ticket(t)
+        if keep:
+            return outs
+        for r in outs:
+            sess.release_ref(r)
+        return None
+
+    def timed_region(profiled: bool, actor=index_actor):
+        """K requests between two events on the library's stream, and an
+        event after every request (the per-step times, for their median);
+        with profiled, every launch is also bracketed by the library's own
+        events.  Requests are pipelined: request k+1 is sent before request
+        k is received (every request runs in full and is received), so the
+        device never waits for the host's turnaround between requests."""
         ka.check(ka.lib.ka_profile_enable(sess.sys, 1 if profiled else 0))
         sess.profile_reset()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -918,12 +929,16 @@ def main() -> int:
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         ev0.record(stream)
-        last_ = None
+        prev = None
         for k in range(args.steps):
-            last_ = step(keep=(k == args.steps - 1))
+            t = sess.send(actor, ka.ref(vin))
             evs[k].record(stream)
+            if prev is not None:
+                finish(prev)
+            prev = t
             if k == args.steps - 1 or (k + 1) % 10 == 0:
                 log(f"[bench] {'profiled ' if profiled else ''}step {k + 1}/{args.steps}")
+        last_ = finish(prev, keep=True)
         ev1.record(stream)
         torch.cuda.synchronize()
         per_step = [a.elapsed_time(b) for a, b in zip([ev0] + evs[:-1], evs)]
@@ -937,14 +952,10 @@ def main() -> int:
     # the composed two-actor pipeline, same input and timing
     for _ in range(args.warmup):
         step(actor=pipe)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step(actor=pipe)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    composed_ms = ev0.elapsed_time(ev1) / args.steps
+    composed_dev_ms, _, last_c, _ = timed_region(False, actor=pipe)
+    for r in last_c:
+        sess.release_ref(r)
+    composed_ms = composed_dev_ms / args.steps
     log(f"[bench] composed stage actors: {composed_ms:.4f} ms per request")
     # per-kernel device times for the roofline: a second region with the library's events
     prof_ms, _, last, _ = timed_region(True)
